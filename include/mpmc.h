@@ -1,0 +1,231 @@
+/*
+ * mpmc.h -- C ABI of libmpmc.so: the GPU hot path of Multipolynomial Monte
+ * Carlo trace estimation (Lashomb, Morgan, Whyte, Wilcox, arXiv:2306.09559)
+ * for gfx950 (AMD Instinct MI355X).
+ *
+ * The library estimates pieces of Tr(A^{-1}) for the Wilson-Dirac matrix A
+ * with Hutchinson samples b^H M b over Z4 noise b (Sec. 1), where M is a
+ * difference of GMRES polynomials in A (eq. multpolytr, Sec. 3.1), possibly
+ * a composite polynomial (Sec. 2.4, Sec. 3.2), possibly deflated with right
+ * and left eigenvectors (Sec. 4.1, Sec. 4.3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Lattice    dims = {Lx, Ly, Lz, Lt}; site s = x + Lx*(y + Ly*(z + Lz*t));
+ *            V = Lx*Ly*Lz*Lt sites, n = 12*V unknowns per vector, unknown
+ *            i = 12*s + 3*spin + colour.  x, y, z are periodic; t is
+ *            periodic or antiperiodic (a hop across the t boundary carries -1).
+ * Operator   (A psi)(x) = psi(x) - kappa sum_mu [ (1 - g_mu) U_mu(x) psi(x+mu)
+ *                                  + (1 + g_mu) U_mu(x-mu)^H psi(x-mu) ]
+ *            with DeGrand-Rossi (chiral) gamma matrices, g5 = diag(1,1,-1,-1).
+ *            The paper names the quenched Wilson-Dirac matrix (Sec. 5,
+ *            Example 2); this hopping-parameter form is the reading used.
+ * Precision  MPMC_F64: fields, links and eigenvectors are complex128.
+ *            MPMC_F32: they are complex64; inverse roots are rounded to FP32
+ *            for vector updates, while every dot product, sample value,
+ *            deflation coefficient and accumulator stays FP64.
+ * Field      a batch of N vectors in "field layout" with RHS block width rb
+ *            (a power of two, 1..256, dividing N): unknown (spin,colour) =
+ *            c in 0..11 of site s of vector r = nb*rb + j is the complex
+ *            number at index ((nb*12 + c)*V + s)*rb + j.  Complex numbers
+ *            are (re, im) pairs of the field precision.
+ * Gauge      library gauge layout (written by mpmc_pack_gauge): link
+ *            element (row a, col b) of U_mu(s) at index (mu*9 + 3a + b)*V + s.
+ * Noise      Z4 entries {1, i, -1, -i} (Sec. 1) from SplitMix64 (Steele,
+ *            Lea & Flood 2014), out(x, k) = mix(x + k*0x9E3779B97F4A7C15):
+ *              key  = out(out(out(seed,1) ^ lattice,1) ^ level,1)
+ *              S_r  = out(key ^ r, 1)          r = global sample index
+ *              q    = (out(S_r, i/32 + 1) >> 2*(i%32)) & 3,  b_r[i] = i^q.
+ *            Noise is regenerated in registers wherever it is consumed.
+ * Roots      a GMRES polynomial of degree d is given by the d+1 inverse
+ *            roots t_j = 1/theta_j of its residual polynomial
+ *            pi(a) = prod_j (1 - a/theta_j) = 1 - a p(a) (Sec. 3.1), as
+ *            complex FP64 (re, im) pairs in device memory, in the order they
+ *            are applied (Leja order).  p is applied in Newton form:
+ *            w_0 = x, w_{j+1} = w_j - t_j A w_j, p(A) x = sum_j t_j w_j.
+ *
+ * Memory and streams
+ * ------------------
+ * Every pointer marked "device" is caller-owned device memory of the current
+ * HIP device; the library only borrows it for the work it enqueues.  Calls
+ * enqueue on `stream` (a hipStream_t, NULL = default stream), return without
+ * synchronising, never allocate device memory, and never read device memory
+ * on the host.  Scratch memory is the caller's `ws` of at least the size
+ * the matching *_workspace_size function returns (256-byte aligned).
+ *
+ * Errors
+ * ------
+ * Every entry point returns MPMC_OK (0) or a negative status; arguments are
+ * validated on the host before anything is enqueued, so an error leaves the
+ * outputs untouched.  MPMC_EHIP reports a launch failure (hipGetLastError).
+ * Non-finite sample values are counted in the level accumulator.  No C++
+ * exception crosses this interface.  Calls are thread-compatible.
+ */
+#ifndef MPMC_H
+#define MPMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MPMC_OK = 0,
+    MPMC_EINVAL = -1,       /* null pointer, size or layout out of range */
+    MPMC_EUNSUPPORTED = -2, /* unknown precision, mode or operator kind */
+    MPMC_EWORKSPACE = -3,   /* ws smaller than the *_workspace_size result */
+    MPMC_EHIP = -4          /* HIP runtime or launch failure */
+};
+
+enum { MPMC_F64 = 0, MPMC_F32 = 1 };
+
+typedef struct {
+    int32_t dims[4];        /* Lx, Ly, Lz, Lt, each >= 1, V*12 < 2^31 */
+    int32_t antiperiodic_t; /* 0 or 1 */
+    int32_t prec;           /* MPMC_F64 or MPMC_F32: precision of gauge and fields */
+    double kappa;           /* hopping parameter */
+    const void *gauge;      /* device, library gauge layout, 36*V complex */
+} mpmc_lattice;
+
+typedef struct {
+    int32_t nrhs;           /* N >= 1 */
+    int32_t rb;             /* RHS block width: power of two in [1, 256], divides N */
+} mpmc_shape;
+
+typedef struct {
+    uint64_t seed;
+    uint64_t lattice;       /* lattice id */
+    uint64_t level;         /* level id */
+    uint64_t first_sample;  /* vector r of a batch is global sample first_sample + r */
+} mpmc_noise;
+
+typedef struct {
+    int32_t n_in;                /* roots of p (single) or of p_in (composite), >= 1 */
+    int32_t n_out;               /* 0: single polynomial; >= 1: roots of p_out */
+    const double *inv_roots_in;  /* device, n_in complex FP64 */
+    const double *inv_roots_out; /* device, n_out complex FP64, or NULL when n_out = 0 */
+} mpmc_poly;
+
+/* Deflation data (Sec. 4): right eigenvectors z_i and left eigenvectors
+ * u_i = scale_i * g5 z_{pair_i} (the g5 rule of Sec. 4 with the biorthonormal
+ * scaling u_i^H z_i = 1), so U is never stored. */
+typedef struct {
+    int32_t k;                   /* triplets, 1 <= k <= kpad */
+    int32_t kpad;                /* multiple of 16, <= 256 */
+    const void *V;               /* device, z_1..z_kpad in field layout with nrhs = rb = kpad
+                                    (entries i >= k must be zero), lattice precision */
+    const int32_t *pair;         /* device, k indices in [0, k) */
+    const double *scale;         /* device, k complex FP64 */
+    const double *hinv;          /* device, k*k complex FP64 row-major H^{-1}, H = U^H A V
+                                    (Sec. 2.1 step 2); needed by MPMC_DEFL_PROJECT only */
+} mpmc_defl;
+
+/* Status code as text (static storage). */
+const char *mpmc_status_string(int status);
+
+/* Library version and the gfx target it was built for. */
+const char *mpmc_build_info(void);
+
+/* ---- layout conversion and noise ------------------------------------- */
+
+/* canon: device complex128 (4, V, 3, 3) = U[mu][s][a][b] -> gauge (lattice
+ * precision, library gauge layout).  Both device, caller-owned. */
+int mpmc_pack_gauge(const int32_t dims[4], int32_t prec, const double *canon, void *gauge,
+                    void *stream);
+
+/* canon: device complex128 (N, V, 4, 3) <-> field (prec, field layout). */
+int mpmc_pack_fields(const int32_t dims[4], int32_t prec, mpmc_shape shape, const double *canon,
+                     void *field, void *stream);
+int mpmc_unpack_fields(const int32_t dims[4], int32_t prec, mpmc_shape shape, const void *field,
+                       double *canon, void *stream);
+
+/* Write the Z4 vectors of `noise` (samples first_sample .. +N-1) into a field
+ * (Sec. 1).  Bit-identical to the noise every other entry point regenerates. */
+int mpmc_z4_fill(const int32_t dims[4], int32_t prec, mpmc_shape shape, const mpmc_noise *noise,
+                 void *field, void *stream);
+
+/* ---- the operator ------------------------------------------------------ */
+
+/* y = A x for N vectors (the matrix-vector product every cost in the paper
+ * is counted in, Sec. 5).  x, y: device fields, distinct. */
+int mpmc_wilson_apply(const mpmc_lattice *lat, mpmc_shape shape, const void *x, void *y,
+                      void *stream);
+
+/* ---- polynomials (Sec. 2.3, 2.4, 3.1, 3.2) ----------------------------- */
+
+size_t mpmc_poly_workspace_size(const mpmc_lattice *lat, const mpmc_poly *poly, mpmc_shape shape);
+
+/* Apply a GMRES polynomial p(A) (n_out = 0) or the composite polynomial
+ * p_1(A) = p_in(A) p_out(A p_in(A)) (n_out >= 1, Sec. 3.2; cost
+ * n_in*n_out - 1 operator applications) to N vectors.
+ *   x      device field, or NULL: x = Z4 noise of `noise`
+ *   noise  the Z4 batch b; when NULL, b = x
+ *   y      device field receiving p(A) x, or NULL (scalar mode)
+ *   bhy    device, 2*N FP64 receiving b_r^H (p(A) x)_r, or NULL
+ * At least one of y, bhy must be non-NULL; x == NULL needs noise. */
+int mpmc_poly_apply(const mpmc_lattice *lat, const mpmc_poly *poly, mpmc_shape shape,
+                    const void *x, const mpmc_noise *noise, void *y, double *bhy, void *ws,
+                    size_t ws_bytes, void *stream);
+
+/* ---- deflation (Sec. 2.1, Sec. 4) -------------------------------------- */
+
+enum {
+    MPMC_DEFL_COEFF = 0,    /* zeta = V^H b, omega = U^H b                               */
+    MPMC_DEFL_RECON = 1,    /* X = V d                                                   */
+    MPMC_DEFL_PROJECT = 2   /* Left-right Projection of b with x0 = 0 (Sec. 2.1):        */
+                            /* zeta, omega as COEFF, d = H^{-1} omega, X = b - A V d     */
+};
+
+size_t mpmc_deflate_workspace_size(const mpmc_lattice *lat, const mpmc_defl *defl, mpmc_shape shape);
+
+/*   b      device field, or NULL: b = Z4 noise of `noise` (COEFF, PROJECT)
+ *   zeta   device k x N complex FP64 (row i = eigenvector), or NULL (COEFF)
+ *   omega  device k x N complex FP64, or NULL (COEFF); both written by PROJECT
+ *   d      device k x N complex FP64: read by RECON, written by PROJECT
+ *   X      device field: written by RECON and PROJECT
+ * The V^H products run on FP64 (MPMC_F64) or FP32 (MPMC_F32) matrix cores
+ * and are accumulated in FP64 across the lattice. */
+int mpmc_deflate_project(const mpmc_lattice *lat, const mpmc_defl *defl, int32_t mode,
+                         mpmc_shape shape, const void *b, const mpmc_noise *noise, double *zeta,
+                         double *omega, double *d, void *X, void *ws, size_t ws_bytes,
+                         void *stream);
+
+/* ---- one Monte Carlo level (eq. multpolytr; Sec. 4.1; Sec. 5 step 3) --- */
+
+enum {
+    MPMC_OP_NONE = 0,            /* operator 0                                          */
+    MPMC_OP_POLY = 1,            /* p(A): single or composite polynomial               */
+    MPMC_OP_DEFLATED_POLY = 2    /* Q = V H^{-1} U^H + p(A)(I - A V H^{-1} U^H) (Sec. 4.3) */
+};
+
+typedef struct {
+    int32_t kind_hi, kind_lo;    /* MPMC_OP_* ; kind_hi must not be NONE */
+    mpmc_poly poly_hi, poly_lo;
+    const mpmc_defl *defl;       /* eigen-triplets, or NULL; required by DEFLATED_POLY */
+    int32_t deflate_samples;     /* 1: subtract sum_i c_i conj(zeta_i) omega_i from each sample */
+    const double *c;             /* device, k complex FP64 c_i = f_hi(l_i) - f_lo(l_i) (Sec. 4.1) */
+} mpmc_level;
+
+size_t mpmc_level_workspace_size(const mpmc_lattice *lat, const mpmc_level *level, mpmc_shape shape);
+
+/* Draw N Z4 samples b_r of `noise` and compute, in FP64,
+ *   hi_r = b_r^H P_hi b_r,  lo_r = b_r^H P_lo b_r,
+ *   s_r  = hi_r - lo_r - sum_i c_i conj(zeta_ir) omega_ir   (deflated levels)
+ * with zeta = V^H b, omega = U^H b.
+ *   samples  device, N x 6 FP64: (s, hi, lo) as complex pairs per sample
+ *   acc      device, 8 FP64, updated in place (zero it before the first batch):
+ *            [0] count, [1] mean re, [2] mean im, [3] sum |s - mean|^2,
+ *            [4] non-finite samples seen, [5..7] reserved (0).
+ * Batches merge into acc with the pairwise update of Chan, Golub & LeVeque,
+ * in submission order, so results are reproducible bit for bit.  The level
+ * estimate is acc mean + sum_i c_i (u_i^H z_i = 1 by the scaling). */
+int mpmc_mlmc_level_estimate(const mpmc_lattice *lat, const mpmc_level *level, mpmc_shape shape,
+                             const mpmc_noise *noise, double *samples, double *acc, void *ws,
+                             size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPMC_H */

@@ -115,3 +115,10 @@ def dense_triplets(Adense: np.ndarray, k: int, gamma5: Callable, imaglim: float 
                 raise ValueError("unpaired complex eigenvalue in the gamma_5-hermitian spectrum")
     kk = len(pair)
     return lam[:kk], Z[:kk], np.array(pair, dtype=np.int64)
+
+
+def projection_coefficients(Z: np.ndarray, U: np.ndarray, B: np.ndarray):
+    """zeta = V^* b and omega = U^* b for a batch B of shape (N, n);
+    returns two (k, N) arrays (Sec. 2.1 step 2, Sec. 4.1)."""
+    B = np.atleast_2d(B)
+    return Z.conj() @ B.T, U.conj() @ B.T

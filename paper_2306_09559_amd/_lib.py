@@ -1,0 +1,297 @@
+"""ctypes binding of libmpmc.so (the C ABI declared in include/mpmc.h).
+
+Argument marshalling only: torch tensors are passed as device pointers,
+torch's current HIP stream as the stream; every operation runs in the
+library's HIP kernels.  Importing this module raises if libmpmc.so has not
+been built (there is no fallback path).
+
+Field tensors use the library's field layout as a complex tensor of shape
+(nrhs/rb, 12, V, rb): complex128 for MPMC_F64, complex64 for MPMC_F32.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpmc.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2306_09559_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, EINVAL, EUNSUPPORTED, EWORKSPACE, EHIP = 0, -1, -2, -3, -4
+F64, F32 = 0, 1
+DEFL_COEFF, DEFL_RECON, DEFL_PROJECT = 0, 1, 2
+OP_NONE, OP_POLY, OP_DEFLATED_POLY = 0, 1, 2
+
+c_i32, c_u64, c_f64, c_vp, c_size = ctypes.c_int32, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
+
+
+class mpmc_lattice(ctypes.Structure):
+    _fields_ = [("dims", c_i32 * 4), ("antiperiodic_t", c_i32), ("prec", c_i32), ("kappa", c_f64),
+                ("gauge", c_vp)]
+
+
+class mpmc_shape(ctypes.Structure):
+    _fields_ = [("nrhs", c_i32), ("rb", c_i32)]
+
+
+class mpmc_noise(ctypes.Structure):
+    _fields_ = [("seed", c_u64), ("lattice", c_u64), ("level", c_u64), ("first_sample", c_u64)]
+
+
+class mpmc_poly(ctypes.Structure):
+    _fields_ = [("n_in", c_i32), ("n_out", c_i32), ("inv_roots_in", c_vp), ("inv_roots_out", c_vp)]
+
+
+class mpmc_defl(ctypes.Structure):
+    _fields_ = [("k", c_i32), ("kpad", c_i32), ("V", c_vp), ("pair", c_vp), ("scale", c_vp), ("hinv", c_vp)]
+
+
+class mpmc_level(ctypes.Structure):
+    _fields_ = [("kind_hi", c_i32), ("kind_lo", c_i32), ("poly_hi", mpmc_poly), ("poly_lo", mpmc_poly),
+                ("defl", ctypes.POINTER(mpmc_defl)), ("deflate_samples", c_i32), ("c", c_vp)]
+
+
+P = ctypes.POINTER
+_sig = {
+    "mpmc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "mpmc_build_info": (ctypes.c_char_p, []),
+    "mpmc_pack_gauge": (ctypes.c_int, [P(c_i32), c_i32, c_vp, c_vp, c_vp]),
+    "mpmc_pack_fields": (ctypes.c_int, [P(c_i32), c_i32, mpmc_shape, c_vp, c_vp, c_vp]),
+    "mpmc_unpack_fields": (ctypes.c_int, [P(c_i32), c_i32, mpmc_shape, c_vp, c_vp, c_vp]),
+    "mpmc_z4_fill": (ctypes.c_int, [P(c_i32), c_i32, mpmc_shape, P(mpmc_noise), c_vp, c_vp]),
+    "mpmc_wilson_apply": (ctypes.c_int, [P(mpmc_lattice), mpmc_shape, c_vp, c_vp, c_vp]),
+    "mpmc_poly_workspace_size": (c_size, [P(mpmc_lattice), P(mpmc_poly), mpmc_shape]),
+    "mpmc_poly_apply": (ctypes.c_int, [P(mpmc_lattice), P(mpmc_poly), mpmc_shape, c_vp, P(mpmc_noise), c_vp,
+                                       c_vp, c_vp, c_size, c_vp]),
+    "mpmc_deflate_workspace_size": (c_size, [P(mpmc_lattice), P(mpmc_defl), mpmc_shape]),
+    "mpmc_deflate_project": (ctypes.c_int, [P(mpmc_lattice), P(mpmc_defl), c_i32, mpmc_shape, c_vp,
+                                            P(mpmc_noise), c_vp, c_vp, c_vp, c_vp, c_vp, c_size, c_vp]),
+    "mpmc_level_workspace_size": (c_size, [P(mpmc_lattice), P(mpmc_level), mpmc_shape]),
+    "mpmc_mlmc_level_estimate": (ctypes.c_int, [P(mpmc_lattice), P(mpmc_level), mpmc_shape, P(mpmc_noise), c_vp,
+                                                c_vp, c_vp, c_size, c_vp]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+class MpmcError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        super().__init__(f"{fn} failed: status {status} ({status_string(status)})")
+        self.status = status
+
+
+def status_string(status: int) -> str:
+    return _lib.mpmc_status_string(int(status)).decode()
+
+
+def build_info() -> str:
+    return _lib.mpmc_build_info().decode()
+
+
+def _check(fn: str, st: int):
+    if st != OK:
+        raise MpmcError(fn, st)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dims(d: Sequence[int]):
+    return (c_i32 * 4)(*[int(x) for x in d])
+
+
+# ------------------------------------------------------------------ descriptors
+def complex_dtype(prec: int):
+    return torch.complex128 if prec == F64 else torch.complex64
+
+
+@dataclass
+class Noise:
+    seed: int
+    lattice: int
+    level: int
+    first_sample: int = 0
+
+    def c(self) -> mpmc_noise:
+        return mpmc_noise(self.seed, self.lattice, self.level, self.first_sample)
+
+
+@dataclass
+class DeviceLattice:
+    """Geometry, hopping parameter and the packed gauge field on the device."""
+    dims: tuple
+    kappa: float
+    antiperiodic_t: bool
+    prec: int
+    gauge: torch.Tensor
+
+    @property
+    def V(self) -> int:
+        lx, ly, lz, lt = self.dims
+        return lx * ly * lz * lt
+
+    def c(self) -> mpmc_lattice:
+        return mpmc_lattice(_dims(self.dims), int(self.antiperiodic_t), int(self.prec), float(self.kappa),
+                            self.gauge.data_ptr())
+
+
+@dataclass
+class DevicePoly:
+    """Inverse roots (complex128 device tensors) of p, or of p_in and p_out."""
+    inv_in: torch.Tensor
+    inv_out: Optional[torch.Tensor] = None
+
+    def c(self) -> mpmc_poly:
+        n_out = 0 if self.inv_out is None else int(self.inv_out.numel())
+        return mpmc_poly(int(self.inv_in.numel()), n_out, self.inv_in.data_ptr(),
+                         None if self.inv_out is None else self.inv_out.data_ptr())
+
+
+@dataclass
+class DeviceDefl:
+    """Right eigenvectors V (field layout, nrhs = rb = kpad), pair, scale, H^{-1}."""
+    k: int
+    V: torch.Tensor
+    pair: torch.Tensor            # int32 (k,)
+    scale: torch.Tensor           # complex128 (k,)
+    hinv: Optional[torch.Tensor]  # complex128 (k, k)
+
+    @property
+    def kpad(self) -> int:
+        return int(self.V.shape[-1])
+
+    def c(self) -> mpmc_defl:
+        return mpmc_defl(int(self.k), self.kpad, self.V.data_ptr(), self.pair.data_ptr(), self.scale.data_ptr(),
+                         None if self.hinv is None else self.hinv.data_ptr())
+
+
+@dataclass
+class DeviceLevel:
+    kind_hi: int
+    poly_hi: DevicePoly
+    kind_lo: int = OP_NONE
+    poly_lo: Optional[DevicePoly] = None
+    defl: Optional[DeviceDefl] = None
+    deflate_samples: bool = False
+    c: Optional[torch.Tensor] = None   # complex128 (k,)
+
+    def cstruct(self):
+        dref = self.defl.c() if self.defl is not None else None
+        lo = self.poly_lo.c() if self.poly_lo is not None else mpmc_poly(0, 0, None, None)
+        lv = mpmc_level(int(self.kind_hi), int(self.kind_lo), self.poly_hi.c(), lo,
+                        ctypes.pointer(dref) if dref is not None else None, int(self.deflate_samples),
+                        None if self.c is None else self.c.data_ptr())
+        return lv, dref
+
+
+def field_shape(t: torch.Tensor) -> mpmc_shape:
+    nb, twelve, _V, rb = t.shape
+    assert twelve == 12
+    return mpmc_shape(int(nb * rb), int(rb))
+
+
+def empty_field(V: int, nrhs: int, rb: int, prec: int, device="cuda") -> torch.Tensor:
+    assert nrhs % rb == 0
+    return torch.empty((nrhs // rb, 12, V, rb), dtype=complex_dtype(prec), device=device)
+
+
+def workspace(nbytes: int, device="cuda") -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+# ------------------------------------------------------------------ entry points
+def pack_gauge(dims, prec: int, canon: torch.Tensor, gauge: torch.Tensor):
+    assert canon.dtype == torch.complex128 and canon.is_contiguous()
+    _check("mpmc_pack_gauge", _lib.mpmc_pack_gauge(_dims(dims), prec, _ptr(canon), _ptr(gauge), _stream()))
+
+
+def pack_fields(dims, prec: int, canon: torch.Tensor, field: torch.Tensor):
+    assert canon.dtype == torch.complex128 and canon.is_contiguous()
+    _check("mpmc_pack_fields", _lib.mpmc_pack_fields(_dims(dims), prec, field_shape(field), _ptr(canon),
+                                                     _ptr(field), _stream()))
+
+
+def unpack_fields(dims, prec: int, field: torch.Tensor, canon: torch.Tensor):
+    _check("mpmc_unpack_fields", _lib.mpmc_unpack_fields(_dims(dims), prec, field_shape(field), _ptr(field),
+                                                         _ptr(canon), _stream()))
+
+
+def z4_fill(dims, prec: int, noise: Noise, field: torch.Tensor):
+    nz = noise.c()
+    _check("mpmc_z4_fill", _lib.mpmc_z4_fill(_dims(dims), prec, field_shape(field), ctypes.byref(nz), _ptr(field),
+                                             _stream()))
+
+
+def wilson_apply(lat: DeviceLattice, x: torch.Tensor, y: torch.Tensor):
+    L = lat.c()
+    _check("mpmc_wilson_apply", _lib.mpmc_wilson_apply(ctypes.byref(L), field_shape(x), _ptr(x), _ptr(y),
+                                                       _stream()))
+
+
+def poly_workspace_size(lat: DeviceLattice, poly: DevicePoly, nrhs: int, rb: int) -> int:
+    L, Pl = lat.c(), poly.c()
+    return int(_lib.mpmc_poly_workspace_size(ctypes.byref(L), ctypes.byref(Pl), mpmc_shape(nrhs, rb)))
+
+
+def poly_apply(lat: DeviceLattice, poly: DevicePoly, nrhs: int, rb: int, x: Optional[torch.Tensor],
+               noise: Optional[Noise], y: Optional[torch.Tensor], bhy: Optional[torch.Tensor],
+               ws: torch.Tensor):
+    L, Pl = lat.c(), poly.c()
+    nz = noise.c() if noise is not None else None
+    _check("mpmc_poly_apply", _lib.mpmc_poly_apply(
+        ctypes.byref(L), ctypes.byref(Pl), mpmc_shape(nrhs, rb), _ptr(x), ctypes.byref(nz) if nz else None,
+        _ptr(y), _ptr(bhy), _ptr(ws), ws.numel(), _stream()))
+
+
+def deflate_workspace_size(lat: DeviceLattice, defl: DeviceDefl, nrhs: int, rb: int) -> int:
+    L, D = lat.c(), defl.c()
+    return int(_lib.mpmc_deflate_workspace_size(ctypes.byref(L), ctypes.byref(D), mpmc_shape(nrhs, rb)))
+
+
+def deflate_project(lat: DeviceLattice, defl: DeviceDefl, mode: int, nrhs: int, rb: int,
+                    b: Optional[torch.Tensor], noise: Optional[Noise], zeta: Optional[torch.Tensor],
+                    omega: Optional[torch.Tensor], d: Optional[torch.Tensor], X: Optional[torch.Tensor],
+                    ws: torch.Tensor):
+    L, D = lat.c(), defl.c()
+    nz = noise.c() if noise is not None else None
+    _check("mpmc_deflate_project", _lib.mpmc_deflate_project(
+        ctypes.byref(L), ctypes.byref(D), int(mode), mpmc_shape(nrhs, rb), _ptr(b),
+        ctypes.byref(nz) if nz else None, _ptr(zeta), _ptr(omega), _ptr(d), _ptr(X), _ptr(ws), ws.numel(),
+        _stream()))
+
+
+def level_workspace_size(lat: DeviceLattice, level: DeviceLevel, nrhs: int, rb: int) -> int:
+    L = lat.c()
+    lv, _keep = level.cstruct()
+    return int(_lib.mpmc_level_workspace_size(ctypes.byref(L), ctypes.byref(lv), mpmc_shape(nrhs, rb)))
+
+
+def mlmc_level_estimate(lat: DeviceLattice, level: DeviceLevel, nrhs: int, rb: int, noise: Noise,
+                        samples: torch.Tensor, acc: torch.Tensor, ws: torch.Tensor):
+    L = lat.c()
+    lv, _keep = level.cstruct()
+    nz = noise.c()
+    _check("mpmc_mlmc_level_estimate", _lib.mpmc_mlmc_level_estimate(
+        ctypes.byref(L), ctypes.byref(lv), mpmc_shape(nrhs, rb), ctypes.byref(nz), _ptr(samples), _ptr(acc),
+        _ptr(ws), ws.numel(), _stream()))

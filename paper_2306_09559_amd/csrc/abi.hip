@@ -1,0 +1,208 @@
+// The extern "C" boundary of libmpmc: argument validation on the host,
+// workspace sizing and dispatch to the precision-specific launchers.
+#include <stdio.h>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace mpmc {
+
+size_t poly_ws_bytes(const int32_t dims[4], int32_t prec, const mpmc_poly &poly, mpmc_shape sh) {
+    const size_t fb = align256(field_bytes(dims, prec, sh.nrhs));
+    const int V = dims[0] * dims[1] * dims[2] * dims[3];
+    const FieldTiling t = make_tiling(V, sh.nrhs, sh.rb);
+    const size_t part = align256((size_t)t.groups() * (size_t)sh.rb * sizeof(double2));
+    const int nf = poly.n_out > 0 ? 5 : (poly.n_in > 1 ? 2 : 0);
+    return (size_t)nf * fb + part;
+}
+
+PolyWs carve_poly_ws(const int32_t dims[4], int32_t prec, const mpmc_poly &poly, mpmc_shape sh, void *ws) {
+    PolyWs p{};
+    const size_t fb = align256(field_bytes(dims, prec, sh.nrhs));
+    const int nf = poly.n_out > 0 ? 5 : (poly.n_in > 1 ? 2 : 0);
+    char *w = (char *)ws;
+    for (int i = 0; i < nf; ++i) p.f[i] = w + (size_t)i * fb;
+    p.part = w + (size_t)nf * fb;
+    return p;
+}
+
+}  // namespace mpmc
+
+using namespace mpmc;
+
+namespace {
+
+bool valid_dims(const int32_t *dims) {
+    if (!dims) return false;
+    long long V = 1;
+    for (int d = 0; d < 4; ++d) {
+        if (dims[d] < 1) return false;
+        V *= dims[d];
+    }
+    return V * 12 < (1LL << 31);
+}
+
+bool valid_prec(int32_t p) { return p == MPMC_F64 || p == MPMC_F32; }
+
+bool valid_shape(mpmc_shape s) {
+    if (s.nrhs < 1 || s.rb < 1 || s.rb > 256) return false;
+    if ((s.rb & (s.rb - 1)) != 0) return false;
+    return s.nrhs % s.rb == 0;
+}
+
+// the field kernels address one component plane of an RHS block with 32-bit
+// byte offsets: V * rb * sizeof(complex) must stay below 4 GiB
+bool plane_fits(const int32_t *dims, int32_t prec, mpmc_shape s) {
+    const unsigned long long V = (unsigned long long)dims[0] * dims[1] * dims[2] * dims[3];
+    return V * (unsigned long long)s.rb * (prec == MPMC_F64 ? 16ull : 8ull) < (1ull << 32);
+}
+
+int check_lattice(const mpmc_lattice *lat) {
+    if (!lat || !valid_dims(lat->dims) || !lat->gauge) return MPMC_EINVAL;
+    if (!valid_prec(lat->prec)) return MPMC_EUNSUPPORTED;
+    if (lat->antiperiodic_t != 0 && lat->antiperiodic_t != 1) return MPMC_EINVAL;
+    return MPMC_OK;
+}
+
+int check_poly(const mpmc_poly *p) {
+    if (!p || p->n_in < 1 || !p->inv_roots_in || p->n_out < 0) return MPMC_EINVAL;
+    if (p->n_out > 0 && !p->inv_roots_out) return MPMC_EINVAL;
+    return MPMC_OK;
+}
+
+int check_defl(const mpmc_defl *d, bool need_hinv) {
+    if (!d || d->k < 1 || d->kpad < d->k || d->kpad % 16 != 0 || d->kpad > 256) return MPMC_EINVAL;
+    if (!d->V || !d->pair || !d->scale) return MPMC_EINVAL;
+    if (need_hinv && !d->hinv) return MPMC_EINVAL;
+    return MPMC_OK;
+}
+
+int check_ws(void *ws, size_t have, size_t need) {
+    if (have < need) return MPMC_EWORKSPACE;
+    if (need > 0 && !ws) return MPMC_EINVAL;
+    return MPMC_OK;
+}
+
+#define MPMC_TRY(x)                       \
+    do {                                  \
+        const int _s = (x);               \
+        if (_s != MPMC_OK) return _s;     \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char *mpmc_status_string(int status) {
+    switch (status) {
+    case MPMC_OK: return "ok";
+    case MPMC_EINVAL: return "invalid argument (null pointer, size or layout out of range)";
+    case MPMC_EUNSUPPORTED: return "unsupported precision, mode or operator kind";
+    case MPMC_EWORKSPACE: return "workspace smaller than the required size";
+    case MPMC_EHIP: return "HIP runtime or kernel launch failure";
+    default: return "unknown status";
+    }
+}
+
+const char *mpmc_build_info(void) { return "libmpmc 0.1 gfx950"; }
+
+int mpmc_pack_gauge(const int32_t dims[4], int32_t prec, const double *canon, void *gauge, void *stream) {
+    if (!valid_dims(dims) || !canon || !gauge) return MPMC_EINVAL;
+    if (!valid_prec(prec)) return MPMC_EUNSUPPORTED;
+    return pack_gauge_impl(dims, prec, canon, gauge, stream);
+}
+
+int mpmc_pack_fields(const int32_t dims[4], int32_t prec, mpmc_shape shape, const double *canon, void *field,
+                     void *stream) {
+    if (!valid_dims(dims) || !valid_shape(shape) || !canon || !field) return MPMC_EINVAL;
+    if (!valid_prec(prec)) return MPMC_EUNSUPPORTED;
+    return pack_fields_impl(dims, prec, shape, canon, field, stream);
+}
+
+int mpmc_unpack_fields(const int32_t dims[4], int32_t prec, mpmc_shape shape, const void *field, double *canon,
+                       void *stream) {
+    if (!valid_dims(dims) || !valid_shape(shape) || !canon || !field) return MPMC_EINVAL;
+    if (!valid_prec(prec)) return MPMC_EUNSUPPORTED;
+    return unpack_fields_impl(dims, prec, shape, field, canon, stream);
+}
+
+int mpmc_z4_fill(const int32_t dims[4], int32_t prec, mpmc_shape shape, const mpmc_noise *noise, void *field,
+                 void *stream) {
+    if (!valid_dims(dims) || !valid_shape(shape) || !noise || !field) return MPMC_EINVAL;
+    if (!valid_prec(prec)) return MPMC_EUNSUPPORTED;
+    return z4_fill_impl(dims, prec, shape, *noise, field, stream);
+}
+
+int mpmc_wilson_apply(const mpmc_lattice *lat, mpmc_shape shape, const void *x, void *y, void *stream) {
+    MPMC_TRY(check_lattice(lat));
+    if (!valid_shape(shape) || !plane_fits(lat->dims, lat->prec, shape) || !x || !y || x == y) return MPMC_EINVAL;
+    return lat->prec == MPMC_F64 ? wilson_apply_t<double>(*lat, shape, x, y, stream)
+                                 : wilson_apply_t<float>(*lat, shape, x, y, stream);
+}
+
+size_t mpmc_poly_workspace_size(const mpmc_lattice *lat, const mpmc_poly *poly, mpmc_shape shape) {
+    if (check_lattice(lat) != MPMC_OK || check_poly(poly) != MPMC_OK || !valid_shape(shape)) return 0;
+    return poly_ws_bytes(lat->dims, lat->prec, *poly, shape);
+}
+
+int mpmc_poly_apply(const mpmc_lattice *lat, const mpmc_poly *poly, mpmc_shape shape, const void *x,
+                    const mpmc_noise *noise, void *y, double *bhy, void *ws, size_t ws_bytes, void *stream) {
+    MPMC_TRY(check_lattice(lat));
+    MPMC_TRY(check_poly(poly));
+    if (!valid_shape(shape) || !plane_fits(lat->dims, lat->prec, shape)) return MPMC_EINVAL;
+    if (!y && !bhy) return MPMC_EINVAL;
+    if (!x && !noise) return MPMC_EINVAL;
+    if (x && x == y) return MPMC_EINVAL;
+    MPMC_TRY(check_ws(ws, ws_bytes, poly_ws_bytes(lat->dims, lat->prec, *poly, shape)));
+    const PolyWs p = carve_poly_ws(lat->dims, lat->prec, *poly, shape, ws);
+    return lat->prec == MPMC_F64 ? poly_apply_t<double>(*lat, *poly, shape, x, noise, y, bhy, p, stream)
+                                 : poly_apply_t<float>(*lat, *poly, shape, x, noise, y, bhy, p, stream);
+}
+
+size_t mpmc_deflate_workspace_size(const mpmc_lattice *lat, const mpmc_defl *defl, mpmc_shape shape) {
+    if (check_lattice(lat) != MPMC_OK || check_defl(defl, false) != MPMC_OK || !valid_shape(shape)) return 0;
+    return defl_ws_bytes(*lat, *defl, shape);
+}
+
+int mpmc_deflate_project(const mpmc_lattice *lat, const mpmc_defl *defl, int32_t mode, mpmc_shape shape,
+                         const void *b, const mpmc_noise *noise, double *zeta, double *omega, double *d, void *X,
+                         void *ws, size_t ws_bytes, void *stream) {
+    MPMC_TRY(check_lattice(lat));
+    if (mode != MPMC_DEFL_COEFF && mode != MPMC_DEFL_RECON && mode != MPMC_DEFL_PROJECT) return MPMC_EUNSUPPORTED;
+    MPMC_TRY(check_defl(defl, mode == MPMC_DEFL_PROJECT));
+    if (!valid_shape(shape) || !plane_fits(lat->dims, lat->prec, shape)) return MPMC_EINVAL;
+    if (mode != MPMC_DEFL_RECON && !b && !noise) return MPMC_EINVAL;
+    if (mode == MPMC_DEFL_COEFF && !zeta && !omega) return MPMC_EINVAL;
+    if (mode == MPMC_DEFL_RECON && (!d || !X)) return MPMC_EINVAL;
+    if (mode == MPMC_DEFL_PROJECT && (!d || !X || (b && b == X))) return MPMC_EINVAL;
+    MPMC_TRY(check_ws(ws, ws_bytes, defl_ws_bytes(*lat, *defl, shape)));
+    return deflate_impl(*lat, *defl, mode, shape, b, noise, zeta, omega, d, X, ws, stream);
+}
+
+size_t mpmc_level_workspace_size(const mpmc_lattice *lat, const mpmc_level *level, mpmc_shape shape) {
+    if (check_lattice(lat) != MPMC_OK || !level || !valid_shape(shape)) return 0;
+    if (check_poly(&level->poly_hi) != MPMC_OK) return 0;
+    if (level->kind_lo != MPMC_OP_NONE && check_poly(&level->poly_lo) != MPMC_OK) return 0;
+    return level_ws_bytes(*lat, *level, shape);
+}
+
+int mpmc_mlmc_level_estimate(const mpmc_lattice *lat, const mpmc_level *level, mpmc_shape shape,
+                             const mpmc_noise *noise, double *samples, double *acc, void *ws, size_t ws_bytes,
+                             void *stream) {
+    MPMC_TRY(check_lattice(lat));
+    if (!level || !noise || !samples || !acc || !valid_shape(shape)) return MPMC_EINVAL;
+    if (!plane_fits(lat->dims, lat->prec, shape)) return MPMC_EINVAL;
+    const int kh = level->kind_hi, kl = level->kind_lo;
+    if (kh != MPMC_OP_POLY && kh != MPMC_OP_DEFLATED_POLY) return MPMC_EUNSUPPORTED;
+    if (kl != MPMC_OP_NONE && kl != MPMC_OP_POLY && kl != MPMC_OP_DEFLATED_POLY) return MPMC_EUNSUPPORTED;
+    MPMC_TRY(check_poly(&level->poly_hi));
+    if (kl != MPMC_OP_NONE) MPMC_TRY(check_poly(&level->poly_lo));
+    const bool proj = kh == MPMC_OP_DEFLATED_POLY || kl == MPMC_OP_DEFLATED_POLY;
+    if (proj || level->deflate_samples) MPMC_TRY(check_defl(level->defl, proj));
+    if (level->deflate_samples && !level->c) return MPMC_EINVAL;
+    if (level->deflate_samples != 0 && level->deflate_samples != 1) return MPMC_EINVAL;
+    MPMC_TRY(check_ws(ws, ws_bytes, level_ws_bytes(*lat, *level, shape)));
+    return level_impl(*lat, *level, shape, *noise, samples, acc, ws, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,136 @@
+// Device-side building blocks shared by the libmpmc kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mpmc.h"
+
+namespace mpmc {
+
+// ---------------------------------------------------------------- complex
+template <typename T> struct c2;
+template <> struct c2<double> { using type = double2; };
+template <> struct c2<float> { using type = float2; };
+template <typename T> using cplx_t = typename c2<T>::type;
+
+template <typename T> __device__ __forceinline__ cplx_t<T> mk(T re, T im) {
+    cplx_t<T> z;
+    z.x = re;
+    z.y = im;
+    return z;
+}
+template <typename T> __device__ __forceinline__ cplx_t<T> cadd(cplx_t<T> a, cplx_t<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+template <typename T> __device__ __forceinline__ cplx_t<T> csub(cplx_t<T> a, cplx_t<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+// a * b
+template <typename T> __device__ __forceinline__ cplx_t<T> cmul(cplx_t<T> a, cplx_t<T> b) {
+    return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// acc + a * b
+template <typename T> __device__ __forceinline__ cplx_t<T> cfma(cplx_t<T> a, cplx_t<T> b, cplx_t<T> acc) {
+    return mk<T>(acc.x + a.x * b.x - a.y * b.y, acc.y + a.x * b.y + a.y * b.x);
+}
+// acc + conj(a) * b
+template <typename T> __device__ __forceinline__ cplx_t<T> cfmaconj(cplx_t<T> a, cplx_t<T> b, cplx_t<T> acc) {
+    return mk<T>(acc.x + a.x * b.x + a.y * b.y, acc.y + a.x * b.y - a.y * b.x);
+}
+// i * a and -i * a
+template <typename T> __device__ __forceinline__ cplx_t<T> mul_i(cplx_t<T> a) { return mk<T>(-a.y, a.x); }
+template <typename T> __device__ __forceinline__ cplx_t<T> mul_mi(cplx_t<T> a) { return mk<T>(a.y, -a.x); }
+
+// ---------------------------------------------------------------- geometry
+struct Geo {
+    int L[4];      // Lx, Ly, Lz, Lt
+    int st[4];     // site strides 1, Lx, Lx*Ly, Lx*Ly*Lz
+    int V;
+    int apbc;      // antiperiodic time
+};
+
+inline Geo make_geo(const int32_t dims[4], int apbc) {
+    Geo g;
+    for (int d = 0; d < 4; ++d) g.L[d] = dims[d];
+    g.st[0] = 1;
+    g.st[1] = dims[0];
+    g.st[2] = dims[0] * dims[1];
+    g.st[3] = dims[0] * dims[1] * dims[2];
+    g.V = g.st[3] * dims[3];
+    g.apbc = apbc;
+    return g;
+}
+
+// ---------------------------------------------------------------- Z4 noise
+// SplitMix64 (Steele, Lea & Flood 2014): output k of state x = mix(x + k*gamma).
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ULL;
+
+__host__ __device__ __forceinline__ uint64_t sm_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+__host__ __device__ __forceinline__ uint64_t sm_out(uint64_t x, uint64_t k) { return sm_mix(x + k * kGolden); }
+
+inline uint64_t noise_key(const mpmc_noise &nz) {
+    uint64_t k = sm_out(nz.seed, 1);
+    k = sm_out(k ^ nz.lattice, 1);
+    return sm_out(k ^ nz.level, 1);
+}
+
+// per-sample generator state
+__device__ __forceinline__ uint64_t sample_state(uint64_t key, uint64_t sample) { return sm_out(key ^ sample, 1); }
+
+// 2-bit code q of unknown i of the sample with state S
+__device__ __forceinline__ unsigned z4_code(uint64_t S, unsigned i) {
+    const uint64_t w = sm_out(S, (uint64_t)(i >> 5) + 1);
+    return (unsigned)(w >> (2 * (i & 31))) & 3u;
+}
+
+// the 12 codes of site s (unknowns 12s .. 12s+11) packed 2 bits each
+__device__ __forceinline__ uint32_t z4_site_codes(uint64_t S, unsigned s) {
+    const unsigned i0 = 12u * s;
+    const unsigned w0 = i0 >> 5, sh = 2u * (i0 & 31u);
+    const uint64_t a = sm_out(S, (uint64_t)w0 + 1);
+    uint64_t bits = a >> sh;
+    if (sh > 40u) {  // the 24 bits straddle two 64-bit words
+        const uint64_t b = sm_out(S, (uint64_t)w0 + 2);
+        bits |= b << (64u - sh);
+    }
+    return (uint32_t)(bits & 0xFFFFFFu);
+}
+
+template <typename T> __device__ __forceinline__ cplx_t<T> z4_value(unsigned q) {
+    // q = 0, 1, 2, 3 -> 1, i, -1, -i
+    const T re = (q == 0u) ? T(1) : ((q == 2u) ? T(-1) : T(0));
+    const T im = (q == 1u) ? T(1) : ((q == 3u) ? T(-1) : T(0));
+    return mk<T>(re, im);
+}
+
+// ---------------------------------------------------------------- launch shape
+constexpr int kBlock = 256;   // threads per workgroup of the field kernels
+constexpr int kXcds = 8;      // MI355X: 8 XCDs, workgroups dispatched round-robin
+
+// Map the hardware workgroup index to a logical index so that each XCD
+// (hardware index mod 8) receives one contiguous range of logical work:
+// neighbouring tiles then share that XCD's L2.  A bijection on [0, G).
+__device__ __forceinline__ unsigned xcd_remap(unsigned bid, unsigned G) {
+    const unsigned x = bid % kXcds, slot = bid / kXcds;
+    const unsigned q = G / kXcds, rem = G % kXcds;
+    return x * q + (x < rem ? x : rem) + slot;
+}
+
+// Field-kernel work decomposition: a workgroup covers spw = 256/rb sites of
+// one RHS block, all rb vectors of that block.
+struct FieldTiling {
+    int rb, spw, nblk, nb;   // nblk site blocks per RHS block, nb RHS blocks
+    unsigned groups() const { return (unsigned)(nblk * nb); }
+};
+
+inline FieldTiling make_tiling(int V, int nrhs, int rb) {
+    FieldTiling t;
+    t.rb = rb;
+    t.spw = kBlock / rb;
+    t.nblk = (V + t.spw - 1) / t.spw;
+    t.nb = nrhs / rb;
+    return t;
+}
+
+}  // namespace mpmc

@@ -1,0 +1,657 @@
+// Multi-RHS Wilson-Dirac hopping kernel and the polynomial drivers built on it.
+//
+// One thread owns one (site, vector) pair and produces all 12 unknowns of
+// that site.  Each of the 8 neighbours is spin-projected to a half spinor
+// (2 spins x 3 colours) before the SU(3) product, then reconstructed; the
+// projector algebra below is that of the DeGrand-Rossi gamma matrices.
+// A workgroup covers 256/rb consecutive sites of one RHS block, lanes
+// walking the rb vectors of a site fastest, so every field access of a
+// wavefront is one contiguous run and the links of a site are shared by its
+// rb lanes.  Workgroups are remapped so each XCD sweeps a contiguous range
+// of tiles (its L2 then holds the neighbours).
+//
+// The same kernel body serves every operator application of the hot path:
+//   out = alpha * in + beta * D in  (+ b)            D = hopping term
+// with (alpha, beta) = (1, -kappa) for A itself, (1 - t, kappa t) for a
+// Newton / product-chain step w -> w - t A w (Sec. 3.1), (-1, kappa) plus b
+// for the projected residual b - A x (Sec. 2.1 step 4), and optional fused
+// epilogues: the Newton accumulator y += t w, the FP64 partial of b^H w,
+// and the outer Newton update of the composite polynomial (Sec. 3.2).
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace mpmc {
+
+template <typename T> struct HopArgs {
+    Geo g;
+    int rb, spw, nblk;
+    unsigned G;                 // logical workgroups
+    const cplx_t<T> *in;        // input field; unused when the input is noise
+    cplx_t<T> *out;
+    const cplx_t<T> *gauge;     // [mu][9][V]
+    // step coefficients: t = troots[j] if troots, else (alpha, beta) given
+    const double2 *troots;
+    int j;
+    double kappa;
+    double2 alpha, beta;
+    // noise (input when IN_Z4, dot/add vector when bvec == nullptr)
+    uint64_t key, first;
+    const cplx_t<T> *bvec;
+    // Newton accumulator y (YACC)
+    cplx_t<T> *y;
+    int y_first, y_last;
+    // dot partials (DOT): part[L*rb + lane] accumulates sum_j t_j b^H w_j
+    double2 *part;
+    int dot_first;
+    // composite outer step (OUTER): u_next = (1-phi) u + phi * out
+    const cplx_t<T> *u;
+    cplx_t<T> *u_next;
+    const double2 *phi;
+    int jo, jo_last;
+};
+
+namespace {
+
+template <typename T> struct Half { cplx_t<T> h[2][3]; };
+
+// A field restricted to one RHS block: component c of the thread's vector at
+// site s lives at base + c*cstride + (s*rb + j)*sizeof(C).  base and cstride
+// are wavefront-uniform (scalar registers); the per-site byte offset fits in
+// 32 bits because V*rb*sizeof(C) < 4 GiB is checked on the host.
+template <typename T> struct Blk {
+    const char *base;
+    size_t cstride;
+    __device__ __forceinline__ cplx_t<T> ld(int c, uint32_t off) const {
+        return *(const cplx_t<T> *)(base + (size_t)c * cstride + off);
+    }
+    __device__ __forceinline__ void st(int c, uint32_t off, cplx_t<T> v) const {
+        *(cplx_t<T> *)(const_cast<char *>(base) + (size_t)c * cstride + off) = v;
+    }
+};
+
+template <typename T> __device__ __forceinline__ Blk<T> blk(const void *f, int nbk, int V, int rb) {
+    Blk<T> b;
+    b.cstride = (size_t)V * (size_t)rb * sizeof(cplx_t<T>);
+    b.base = (const char *)f + (size_t)nbk * 12 * b.cstride;
+    return b;
+}
+
+// byte offset of (site s, lane j) inside a component plane
+template <typename T> __device__ __forceinline__ uint32_t site_off(int s, int rb, int j) {
+    return (uint32_t)(s * rb + j) * (uint32_t)sizeof(cplx_t<T>);
+}
+
+template <typename T>
+__device__ __forceinline__ void load_site(const Blk<T> &in, int rb, int jr, bool z4, uint64_t S, int s, T sign,
+                                          cplx_t<T> (&p)[12]) {
+    if (z4) {
+        const uint32_t codes = z4_site_codes(S, (unsigned)s);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            cplx_t<T> v = z4_value<T>((codes >> (2 * c)) & 3u);
+            p[c] = mk<T>(sign * v.x, sign * v.y);
+        }
+    } else {
+        const uint32_t off = site_off<T>(s, rb, jr);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            cplx_t<T> v = in.ld(c, off);
+            p[c] = mk<T>(sign * v.x, sign * v.y);
+        }
+    }
+}
+
+// (1 - g_mu) psi  (FWD) or (1 + g_mu) psi (!FWD) as a half spinor (spins 0, 1)
+template <typename T, int MU, bool FWD>
+__device__ __forceinline__ void project(const cplx_t<T> (&p)[12], cplx_t<T> (&h)[2][3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const cplx_t<T> p0 = p[a], p1 = p[3 + a], p2 = p[6 + a], p3 = p[9 + a];
+        if (MU == 0) {        // g1: h0 = p0 -+ i p3, h1 = p1 -+ i p2
+            h[0][a] = FWD ? cadd<T>(p0, mul_mi<T>(p3)) : cadd<T>(p0, mul_i<T>(p3));
+            h[1][a] = FWD ? cadd<T>(p1, mul_mi<T>(p2)) : cadd<T>(p1, mul_i<T>(p2));
+        } else if (MU == 1) { // g2: h0 = p0 +- p3, h1 = p1 -+ p2
+            h[0][a] = FWD ? cadd<T>(p0, p3) : csub<T>(p0, p3);
+            h[1][a] = FWD ? csub<T>(p1, p2) : cadd<T>(p1, p2);
+        } else if (MU == 2) { // g3: h0 = p0 -+ i p2, h1 = p1 +- i p3
+            h[0][a] = FWD ? cadd<T>(p0, mul_mi<T>(p2)) : cadd<T>(p0, mul_i<T>(p2));
+            h[1][a] = FWD ? cadd<T>(p1, mul_i<T>(p3)) : cadd<T>(p1, mul_mi<T>(p3));
+        } else {              // g4: h0 = p0 -+ p2, h1 = p1 -+ p3
+            h[0][a] = FWD ? csub<T>(p0, p2) : cadd<T>(p0, p2);
+            h[1][a] = FWD ? csub<T>(p1, p3) : cadd<T>(p1, p3);
+        }
+    }
+}
+
+// accumulate the reconstructed 4-spinor of the (colour-rotated) half spinor
+template <typename T, int MU, bool FWD>
+__device__ __forceinline__ void reconstruct(const cplx_t<T> (&h)[2][3], cplx_t<T> (&acc)[12]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const cplx_t<T> h0 = h[0][a], h1 = h[1][a];
+        acc[a] = cadd<T>(acc[a], h0);
+        acc[3 + a] = cadd<T>(acc[3 + a], h1);
+        cplx_t<T> r2, r3;
+        if (MU == 0) {        // (1-g1): r2 = i h1, r3 = i h0 ; (1+g1): -i h1, -i h0
+            r2 = FWD ? mul_i<T>(h1) : mul_mi<T>(h1);
+            r3 = FWD ? mul_i<T>(h0) : mul_mi<T>(h0);
+        } else if (MU == 1) { // (1-g2): r2 = -h1, r3 = h0 ; (1+g2): h1, -h0
+            r2 = FWD ? mk<T>(-h1.x, -h1.y) : h1;
+            r3 = FWD ? h0 : mk<T>(-h0.x, -h0.y);
+        } else if (MU == 2) { // (1-g3): r2 = i h0, r3 = -i h1 ; (1+g3): -i h0, i h1
+            r2 = FWD ? mul_i<T>(h0) : mul_mi<T>(h0);
+            r3 = FWD ? mul_mi<T>(h1) : mul_i<T>(h1);
+        } else {              // (1-g4): r2 = -h0, r3 = -h1 ; (1+g4): h0, h1
+            r2 = FWD ? mk<T>(-h0.x, -h0.y) : h0;
+            r3 = FWD ? mk<T>(-h1.x, -h1.y) : h1;
+        }
+        acc[6 + a] = cadd<T>(acc[6 + a], r2);
+        acc[9 + a] = cadd<T>(acc[9 + a], r3);
+    }
+}
+
+// h <- U h (FWD, U = U_mu(x)) or h <- U^H h (!FWD, U = U_mu(x - mu))
+template <typename T, bool FWD>
+__device__ __forceinline__ void su3_mul(const char *gl, size_t estride, int site, cplx_t<T> (&h)[2][3]) {
+    cplx_t<T> U[9];
+    const uint32_t off = (uint32_t)site * (uint32_t)sizeof(cplx_t<T>);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) U[e] = *(const cplx_t<T> *)(gl + (size_t)e * estride + off);
+    cplx_t<T> o[2][3];
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cplx_t<T> t = mk<T>(T(0), T(0));
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                if (FWD) t = cfma<T>(U[3 * a + b], h[sp][b], t);
+                else t = cfmaconj<T>(U[3 * b + a], h[sp][b], t);
+            }
+            o[sp][a] = t;
+        }
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) h[sp][a] = o[sp][a];
+}
+
+// one neighbour hop: direction MU, forward (x + mu) or backward (x - mu)
+template <typename T, int MU, bool FWD>
+__device__ __forceinline__ void hop_one(const HopArgs<T> &a, const Blk<T> &in, int jr, bool z4, uint64_t S, int s,
+                                        const int (&x)[4], cplx_t<T> (&acc)[12]) {
+    const size_t estride = (size_t)a.g.V * sizeof(cplx_t<T>);
+    const char *gl = (const char *)a.gauge + (size_t)MU * 9 * estride;
+    const bool wrap = FWD ? (x[MU] == a.g.L[MU] - 1) : (x[MU] == 0);
+    const int step = FWD ? a.g.st[MU] : -a.g.st[MU];
+    const int nb = wrap ? s - (a.g.L[MU] - 1) * step : s + step;
+    const T sign = (MU == 3 && wrap && a.g.apbc) ? T(-1) : T(1);
+    cplx_t<T> p[12];
+    load_site<T>(in, a.rb, jr, z4, S, nb, sign, p);
+    Half<T> h;
+    project<T, MU, FWD>(p, h.h);
+    // forward: U_mu(x) h ; backward: U_mu(x - mu)^H h
+    su3_mul<T, FWD>(gl, estride, FWD ? s : nb, h.h);
+    reconstruct<T, MU, FWD>(h.h, acc);
+}
+
+// acc = D psi at site s: the 8 hops run as a rolled loop so that only one
+// neighbour's loads and products are live at a time (bounded registers,
+// occupancy >= 3 waves per SIMD in FP64); acc is carried in registers.
+template <typename T>
+__device__ __forceinline__ void hop_all(const HopArgs<T> &a, const Blk<T> &in, int jr, bool z4, uint64_t S, int s,
+                                        const int (&x)[4], cplx_t<T> (&acc)[12]) {
+#pragma nounroll
+    for (int d = 0; d < 8; ++d) {
+        // Opaque copies of the loop-invariant inputs: without them the
+        // compiler hoists every direction's address arithmetic out of the
+        // loop and keeps it all live, which defeats the rolled loop.
+        int sl = s, xl[4] = {x[0], x[1], x[2], x[3]};
+        asm volatile("" : "+v"(sl), "+v"(xl[0]), "+v"(xl[1]), "+v"(xl[2]), "+v"(xl[3]));
+        Blk<T> il = in;
+        asm volatile("" : "+s"(il.base));
+        switch (d) {
+        case 0: hop_one<T, 0, true>(a, il, jr, z4, S, sl, xl, acc); break;
+        case 1: hop_one<T, 0, false>(a, il, jr, z4, S, sl, xl, acc); break;
+        case 2: hop_one<T, 1, true>(a, il, jr, z4, S, sl, xl, acc); break;
+        case 3: hop_one<T, 1, false>(a, il, jr, z4, S, sl, xl, acc); break;
+        case 4: hop_one<T, 2, true>(a, il, jr, z4, S, sl, xl, acc); break;
+        case 5: hop_one<T, 2, false>(a, il, jr, z4, S, sl, xl, acc); break;
+        case 6: hop_one<T, 3, true>(a, il, jr, z4, S, sl, xl, acc); break;
+        default: hop_one<T, 3, false>(a, il, jr, z4, S, sl, xl, acc); break;
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void get_b(const HopArgs<T> &a, int nbk, int jr, uint64_t S, int s, cplx_t<T> (&b)[12]) {
+    if (a.bvec == nullptr) {
+        const uint32_t codes = z4_site_codes(S, (unsigned)s);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) b[c] = z4_value<T>((codes >> (2 * c)) & 3u);
+    } else {
+        const Blk<T> bb = blk<T>(a.bvec, nbk, a.g.V, a.rb);
+        const uint32_t off = site_off<T>(s, a.rb, jr);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) b[c] = bb.ld(c, off);
+    }
+}
+
+// sum_c conj(b_c) w_c in FP64
+template <typename T>
+__device__ __forceinline__ double2 dot12(const cplx_t<T> (&b)[12], const cplx_t<T> (&w)[12]) {
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        const double br = (double)b[c].x, bi = (double)b[c].y, wr = (double)w[c].x, wi = (double)w[c].y;
+        re += br * wr + bi * wi;
+        im += br * wi - bi * wr;
+    }
+    double2 r;
+    r.x = re;
+    r.y = im;
+    return r;
+}
+
+__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+    double2 r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+
+}  // namespace
+
+template <typename T, bool IN_Z4, bool DOT, bool YACC, bool OUTER, bool ADDB>
+__global__ void __launch_bounds__(kBlock) k_hop(HopArgs<T> a) {
+    using C = cplx_t<T>;
+    __shared__ double2 red[DOT ? kBlock : 1];
+    const unsigned L = xcd_remap(blockIdx.x, a.G);
+    const int nbk = (int)(L / (unsigned)a.nblk), sblk = (int)(L % (unsigned)a.nblk);
+    const int lane = (int)threadIdx.x;
+    const int jr = lane & (a.rb - 1), ls = lane / a.rb;
+    const int s = sblk * a.spw + ls;
+    const bool valid = s < a.g.V;
+    const uint64_t r_global = a.first + (uint64_t)(nbk * a.rb + jr);
+    const Blk<T> in = blk<T>(a.in, nbk, a.g.V, a.rb);
+
+    // step coefficients
+    C alpha, beta;
+    double2 t_cur;
+    t_cur.x = 0.0;
+    t_cur.y = 0.0;
+    if (a.troots != nullptr) {
+        t_cur = a.troots[a.j];
+        const T tr = (T)t_cur.x, ti = (T)t_cur.y, kp = (T)a.kappa;
+        alpha = mk<T>(T(1) - tr, -ti);
+        beta = mk<T>(kp * tr, kp * ti);
+    } else {
+        alpha = mk<T>((T)a.alpha.x, (T)a.alpha.y);
+        beta = mk<T>((T)a.beta.x, (T)a.beta.y);
+    }
+
+    double2 contrib;
+    contrib.x = 0.0;
+    contrib.y = 0.0;
+    if (valid) {
+        const uint64_t S = (IN_Z4 || ((DOT || ADDB) && a.bvec == nullptr)) ? sample_state(a.key, r_global) : 0ull;
+        int x[4];
+        {
+            int r = s;
+            x[0] = r % a.g.L[0];
+            r /= a.g.L[0];
+            x[1] = r % a.g.L[1];
+            r /= a.g.L[1];
+            x[2] = r % a.g.L[2];
+            x[3] = r / a.g.L[2];
+        }
+        C acc[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) acc[c] = mk<T>(T(0), T(0));
+        hop_all<T>(a, in, jr, IN_Z4, S, s, x, acc);
+
+        const uint32_t off = site_off<T>(s, a.rb, jr);
+        C w[12];
+        load_site<T>(in, a.rb, jr, IN_Z4, S, s, T(1), w);
+        C o[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) o[c] = cfma<T>(beta, acc[c], cmul<T>(alpha, w[c]));
+        if (ADDB) {
+            C b[12];
+            get_b<T>(a, nbk, jr, S, s, b);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) o[c] = cadd<T>(o[c], b[c]);
+        }
+        if (OUTER) {
+            // composite: u_next = (1 - phi) u + phi * pi_in(A) u ; y (+)= phi u [+ phi' u_next]
+            const Blk<T> u = blk<T>(a.u, nbk, a.g.V, a.rb);
+            const Blk<T> un = blk<T>(a.u_next, nbk, a.g.V, a.rb);
+            const Blk<T> y = blk<T>(a.y, nbk, a.g.V, a.rb);
+            const double2 ph = a.phi[a.jo];
+            const C phc = mk<T>((T)ph.x, (T)ph.y);
+            const C omp = mk<T>(T(1) - (T)ph.x, -(T)ph.y);
+            C p2c = mk<T>(T(0), T(0));
+            if (a.jo_last) {
+                const double2 p2 = a.phi[a.jo + 1];
+                p2c = mk<T>((T)p2.x, (T)p2.y);
+            }
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const C uo = u.ld(c, off);
+                const C unew = cfma<T>(phc, o[c], cmul<T>(omp, uo));
+                un.st(c, off, unew);
+                C yv = a.y_first ? mk<T>(T(0), T(0)) : y.ld(c, off);
+                yv = cfma<T>(phc, uo, yv);
+                if (a.jo_last) yv = cfma<T>(p2c, unew, yv);
+                y.st(c, off, yv);
+            }
+        } else {
+            const Blk<T> out = blk<T>(a.out, nbk, a.g.V, a.rb);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) out.st(c, off, o[c]);
+            if (YACC) {
+                const Blk<T> y = blk<T>(a.y, nbk, a.g.V, a.rb);
+                const C tc = mk<T>((T)t_cur.x, (T)t_cur.y);
+                C tn = mk<T>(T(0), T(0));
+                if (a.y_last) {
+                    const double2 t2 = a.troots[a.j + 1];
+                    tn = mk<T>((T)t2.x, (T)t2.y);
+                }
+#pragma unroll
+                for (int c = 0; c < 12; ++c) {
+                    C yv = a.y_first ? mk<T>(T(0), T(0)) : y.ld(c, off);
+                    yv = cfma<T>(tc, w[c], yv);
+                    if (a.y_last) yv = cfma<T>(tn, o[c], yv);
+                    y.st(c, off, yv);
+                }
+            }
+            if (DOT) {
+                C b[12];
+                get_b<T>(a, nbk, jr, S, s, b);
+                contrib = zmul(a.troots[a.j + 1], dot12<T>(b, o));
+                if (a.dot_first) {
+                    const double2 d0 = zmul(t_cur, dot12<T>(b, w));
+                    contrib.x += d0.x;
+                    contrib.y += d0.y;
+                }
+            }
+        }
+    }
+    if (DOT) {
+        // fixed-order tree over the sites of the workgroup, per vector
+        red[lane] = contrib;
+        __syncthreads();
+        for (int stride = a.spw >> 1; stride > 0; stride >>= 1) {
+            if (ls < stride) {
+                const double2 o2 = red[lane + stride * a.rb];
+                red[lane].x += o2.x;
+                red[lane].y += o2.y;
+            }
+            __syncthreads();
+        }
+        if (ls == 0) {
+            double2 *p = a.part + (size_t)L * (size_t)a.rb + (size_t)jr;
+            double2 v = red[lane];
+            if (!a.dot_first) {
+                const double2 old = *p;
+                v.x += old.x;
+                v.y += old.y;
+            }
+            *p = v;
+        }
+    }
+}
+
+// degree-0 polynomial p = t_0: y = t_0 x and part = t_0 b^H x
+template <typename T, bool IN_Z4>
+__global__ void __launch_bounds__(kBlock) k_scale_dot(HopArgs<T> a) {
+    using C = cplx_t<T>;
+    __shared__ double2 red[kBlock];
+    const unsigned L = xcd_remap(blockIdx.x, a.G);
+    const int nbk = (int)(L / (unsigned)a.nblk), sblk = (int)(L % (unsigned)a.nblk);
+    const int lane = (int)threadIdx.x;
+    const int jr = lane & (a.rb - 1), ls = lane / a.rb;
+    const int s = sblk * a.spw + ls;
+    const uint64_t r_global = a.first + (uint64_t)(nbk * a.rb + jr);
+    const double2 t0 = a.troots[a.j];
+    const Blk<T> in = blk<T>(a.in, nbk, a.g.V, a.rb);
+    double2 contrib;
+    contrib.x = contrib.y = 0.0;
+    if (s < a.g.V) {
+        const uint64_t S = sample_state(a.key, r_global);
+        C w[12];
+        load_site<T>(in, a.rb, jr, IN_Z4, S, s, T(1), w);
+        if (a.y != nullptr) {
+            const Blk<T> y = blk<T>(a.y, nbk, a.g.V, a.rb);
+            const uint32_t off = site_off<T>(s, a.rb, jr);
+            const C tc = mk<T>((T)t0.x, (T)t0.y);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) y.st(c, off, cmul<T>(tc, w[c]));
+        }
+        if (a.part != nullptr) {
+            C b[12];
+            get_b<T>(a, nbk, jr, S, s, b);
+            contrib = zmul(t0, dot12<T>(b, w));
+        }
+    }
+    if (a.part != nullptr) {
+        red[lane] = contrib;
+        __syncthreads();
+        for (int stride = a.spw >> 1; stride > 0; stride >>= 1) {
+            if (ls < stride) {
+                const double2 o2 = red[lane + stride * a.rb];
+                red[lane].x += o2.x;
+                red[lane].y += o2.y;
+            }
+            __syncthreads();
+        }
+        if (ls == 0) a.part[(size_t)L * (size_t)a.rb + (size_t)jr] = red[lane];
+    }
+}
+
+// bhy[r] = sum over site blocks of part, fixed order
+__global__ void k_reduce_part(const double2 *part, int nblk, int rb, int nrhs, double2 *bhy) {
+    const int r = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (r >= nrhs) return;
+    const int nbk = r / rb, jr = r % rb;
+    double re = 0.0, im = 0.0;
+    const double2 *p = part + (size_t)nbk * (size_t)nblk * (size_t)rb + (size_t)jr;
+    for (int b = 0; b < nblk; ++b) {
+        const double2 v = p[(size_t)b * (size_t)rb];
+        re += v.x;
+        im += v.y;
+    }
+    double2 o;
+    o.x = re;
+    o.y = im;
+    bhy[r] = o;
+}
+
+// ------------------------------------------------------------------ host side
+
+template <typename T> static HopArgs<T> base_args(const mpmc_lattice &lat, mpmc_shape sh) {
+    HopArgs<T> a{};
+    a.g = make_geo(lat.dims, lat.antiperiodic_t);
+    const FieldTiling t = make_tiling(a.g.V, sh.nrhs, sh.rb);
+    a.rb = t.rb;
+    a.spw = t.spw;
+    a.nblk = t.nblk;
+    a.G = t.groups();
+    a.gauge = (const cplx_t<T> *)lat.gauge;
+    a.kappa = lat.kappa;
+    return a;
+}
+
+#define MPMC_LAUNCH(KERNEL, a, stream)                                                       \
+    do {                                                                                     \
+        hipLaunchKernelGGL((KERNEL), dim3((a).G), dim3(kBlock), 0, (hipStream_t)(stream), a); \
+    } while (0)
+
+template <typename T>
+static void launch_hop(const HopArgs<T> &a, bool in_z4, bool dot, bool yacc, bool outer, bool addb, void *stream) {
+    if (outer) { MPMC_LAUNCH((k_hop<T, false, false, false, true, false>), a, stream); return; }
+    if (addb) { MPMC_LAUNCH((k_hop<T, false, false, false, false, true>), a, stream); return; }
+    if (in_z4) {
+        if (dot && yacc) MPMC_LAUNCH((k_hop<T, true, true, true, false, false>), a, stream);
+        else if (dot) MPMC_LAUNCH((k_hop<T, true, true, false, false, false>), a, stream);
+        else if (yacc) MPMC_LAUNCH((k_hop<T, true, false, true, false, false>), a, stream);
+        else MPMC_LAUNCH((k_hop<T, true, false, false, false, false>), a, stream);
+    } else {
+        if (dot && yacc) MPMC_LAUNCH((k_hop<T, false, true, true, false, false>), a, stream);
+        else if (dot) MPMC_LAUNCH((k_hop<T, false, true, false, false, false>), a, stream);
+        else if (yacc) MPMC_LAUNCH((k_hop<T, false, false, true, false, false>), a, stream);
+        else MPMC_LAUNCH((k_hop<T, false, false, false, false, false>), a, stream);
+    }
+}
+
+template <typename T>
+int wilson_apply_t(const mpmc_lattice &lat, mpmc_shape sh, const void *x, void *y, void *stream) {
+    HopArgs<T> a = base_args<T>(lat, sh);
+    a.in = (const cplx_t<T> *)x;
+    a.out = (cplx_t<T> *)y;
+    a.alpha.x = 1.0;
+    a.alpha.y = 0.0;
+    a.beta.x = -lat.kappa;
+    a.beta.y = 0.0;
+    launch_hop<T>(a, false, false, false, false, false, stream);
+    return hipGetLastError() == hipSuccess ? MPMC_OK : MPMC_EHIP;
+}
+
+template <typename T>
+int residual_apply_t(const mpmc_lattice &lat, mpmc_shape sh, const void *x, const void *b, uint64_t key,
+                     uint64_t first, void *out, void *stream) {
+    // out = b - A x
+    HopArgs<T> a = base_args<T>(lat, sh);
+    a.in = (const cplx_t<T> *)x;
+    a.out = (cplx_t<T> *)out;
+    a.alpha.x = -1.0;
+    a.alpha.y = 0.0;
+    a.beta.x = lat.kappa;
+    a.beta.y = 0.0;
+    a.bvec = (const cplx_t<T> *)b;
+    a.key = key;
+    a.first = first;
+    launch_hop<T>(a, false, false, false, false, true, stream);
+    return hipGetLastError() == hipSuccess ? MPMC_OK : MPMC_EHIP;
+}
+
+// Newton-form single polynomial over n roots (n-1 operator applications).
+//   x == nullptr: input is the noise; bvec == nullptr: dot vector is the noise.
+template <typename T>
+static int newton_t(const mpmc_lattice &lat, mpmc_shape sh, int n, const double *troots, const void *x, bool x_is_noise,
+                    const void *bvec, uint64_t key, uint64_t first, void *y, double2 *part, void *w0, void *w1,
+                    void *stream) {
+    HopArgs<T> a = base_args<T>(lat, sh);
+    a.troots = (const double2 *)troots;
+    a.key = key;
+    a.first = first;
+    a.bvec = (const cplx_t<T> *)bvec;
+    a.part = part;
+    a.y = (cplx_t<T> *)y;
+    const bool dot = part != nullptr, yacc = y != nullptr;
+    if (n == 1) {
+        a.j = 0;
+        a.in = (const cplx_t<T> *)x;
+        if (x_is_noise) hipLaunchKernelGGL((k_scale_dot<T, true>), dim3(a.G), dim3(kBlock), 0, (hipStream_t)stream, a);
+        else hipLaunchKernelGGL((k_scale_dot<T, false>), dim3(a.G), dim3(kBlock), 0, (hipStream_t)stream, a);
+        return hipGetLastError() == hipSuccess ? MPMC_OK : MPMC_EHIP;
+    }
+    const int d = n - 1;
+    for (int j = 0; j < d; ++j) {
+        a.j = j;
+        a.in = (j == 0) ? (const cplx_t<T> *)x : (const cplx_t<T> *)((j - 1) % 2 == 0 ? w0 : w1);
+        a.out = (cplx_t<T> *)(j % 2 == 0 ? w0 : w1);
+        a.y_first = (j == 0);
+        a.y_last = (j == d - 1);
+        a.dot_first = (j == 0);
+        launch_hop<T>(a, j == 0 && x_is_noise, dot, yacc, false, false, stream);
+        if (hipGetLastError() != hipSuccess) return MPMC_EHIP;
+    }
+    return MPMC_OK;
+}
+
+template <typename T>
+int poly_apply_t(const mpmc_lattice &lat, const mpmc_poly &poly, mpmc_shape sh, const void *x, const mpmc_noise *noise,
+                 void *y, double *bhy, const PolyWs &ws, void *stream) {
+    const uint64_t key = noise ? noise_key(*noise) : 0ull;
+    const uint64_t first = noise ? noise->first_sample : 0ull;
+    const bool x_noise = (x == nullptr);
+    // dot vector: the noise if given, else x itself
+    const void *bvec = noise ? nullptr : x;
+    double2 *part = bhy ? (double2 *)ws.part : nullptr;
+    const FieldTiling t = make_tiling(lat.dims[0] * lat.dims[1] * lat.dims[2] * lat.dims[3], sh.nrhs, sh.rb);
+    int st;
+    if (poly.n_out == 0) {
+        st = newton_t<T>(lat, sh, poly.n_in, poly.inv_roots_in, x, x_noise, bvec, key, first, y, part, ws.f[0],
+                         ws.f[1], stream);
+        if (st != MPMC_OK) return st;
+    } else {
+        // composite p_in(A) p_out(B), B = A p_in(A) = I - pi_in(A) (Sec. 3.2)
+        HopArgs<T> a = base_args<T>(lat, sh);
+        void *U0 = ws.f[0], *U1 = ws.f[1], *V0 = ws.f[2], *V1 = ws.f[3], *Y = ws.f[4];
+        // u_0 = x
+        st = copy_or_noise_t<T>(lat, sh, x, key, first, U0, stream);
+        if (st != MPMC_OK) return st;
+        void *ucur = U0, *unext = U1;
+        const int n_in = poly.n_in, n_out = poly.n_out;
+        a.troots = (const double2 *)poly.inv_roots_in;
+        a.phi = (const double2 *)poly.inv_roots_out;
+        if (n_out == 1) {
+            HopArgs<T> s1 = base_args<T>(lat, sh);
+            s1.troots = (const double2 *)poly.inv_roots_out;
+            s1.j = 0;
+            s1.in = (const cplx_t<T> *)ucur;
+            s1.y = (cplx_t<T> *)Y;
+            hipLaunchKernelGGL((k_scale_dot<T, false>), dim3(s1.G), dim3(kBlock), 0, (hipStream_t)stream, s1);
+        }
+        for (int jo = 0; jo + 1 < n_out; ++jo) {
+            const void *vin = ucur;
+            for (int i = 0; i < n_in; ++i) {
+                a.j = i;
+                a.in = (const cplx_t<T> *)vin;
+                if (i + 1 < n_in) {
+                    void *vout = (i % 2 == 0) ? V0 : V1;
+                    a.out = (cplx_t<T> *)vout;
+                    launch_hop<T>(a, false, false, false, false, false, stream);
+                    vin = vout;
+                } else {
+                    a.u = (const cplx_t<T> *)ucur;
+                    a.u_next = (cplx_t<T> *)unext;
+                    a.y = (cplx_t<T> *)Y;
+                    a.jo = jo;
+                    a.y_first = (jo == 0);
+                    a.jo_last = (jo + 2 == n_out);
+                    launch_hop<T>(a, false, false, false, true, false, stream);
+                    void *tmp = ucur;
+                    ucur = unext;
+                    unext = tmp;
+                }
+                if (hipGetLastError() != hipSuccess) return MPMC_EHIP;
+            }
+        }
+        // final p_in(A) applied to y_out, dot against b
+        const void *bv = noise ? nullptr : x;
+        st = newton_t<T>(lat, sh, n_in, poly.inv_roots_in, Y, false, bv, key, first, y, part, V0, V1, stream);
+        if (st != MPMC_OK) return st;
+    }
+    if (bhy) {
+        const int thr = 256;
+        hipLaunchKernelGGL(k_reduce_part, dim3((sh.nrhs + thr - 1) / thr), dim3(thr), 0, (hipStream_t)stream,
+                           (const double2 *)ws.part, t.nblk, sh.rb, sh.nrhs, (double2 *)bhy);
+        if (hipGetLastError() != hipSuccess) return MPMC_EHIP;
+    }
+    return MPMC_OK;
+}
+
+template int wilson_apply_t<double>(const mpmc_lattice &, mpmc_shape, const void *, void *, void *);
+template int wilson_apply_t<float>(const mpmc_lattice &, mpmc_shape, const void *, void *, void *);
+template int residual_apply_t<double>(const mpmc_lattice &, mpmc_shape, const void *, const void *, uint64_t, uint64_t,
+                                      void *, void *);
+template int residual_apply_t<float>(const mpmc_lattice &, mpmc_shape, const void *, const void *, uint64_t, uint64_t,
+                                     void *, void *);
+template int poly_apply_t<double>(const mpmc_lattice &, const mpmc_poly &, mpmc_shape, const void *, const mpmc_noise *,
+                                  void *, double *, const PolyWs &, void *);
+template int poly_apply_t<float>(const mpmc_lattice &, const mpmc_poly &, mpmc_shape, const void *, const mpmc_noise *,
+                                 void *, double *, const PolyWs &, void *);
+
+}  // namespace mpmc

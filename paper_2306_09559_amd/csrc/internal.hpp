@@ -1,0 +1,56 @@
+// Host-side launchers shared between the libmpmc translation units.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/mpmc.h"
+
+namespace mpmc {
+
+// carve of the caller's workspace for one polynomial application
+struct PolyWs {
+    void *f[5];     // field buffers (2 for a single polynomial, 5 for a composite)
+    void *part;     // dot partials, one complex FP64 per (workgroup, vector)
+};
+
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+inline size_t field_bytes(const int32_t dims[4], int32_t prec, int32_t nrhs) {
+    const size_t V = (size_t)dims[0] * dims[1] * dims[2] * dims[3];
+    return V * 12 * (size_t)nrhs * (prec == MPMC_F64 ? 16 : 8);
+}
+
+size_t poly_ws_bytes(const int32_t dims[4], int32_t prec, const mpmc_poly &poly, mpmc_shape sh);
+PolyWs carve_poly_ws(const int32_t dims[4], int32_t prec, const mpmc_poly &poly, mpmc_shape sh, void *ws);
+
+template <typename T> int wilson_apply_t(const mpmc_lattice &, mpmc_shape, const void *x, void *y, void *stream);
+// out = b - A x, b a field or (b == nullptr) the noise (key, first)
+template <typename T>
+int residual_apply_t(const mpmc_lattice &, mpmc_shape, const void *x, const void *b, uint64_t key, uint64_t first,
+                     void *out, void *stream);
+template <typename T>
+int poly_apply_t(const mpmc_lattice &, const mpmc_poly &, mpmc_shape, const void *x, const mpmc_noise *noise, void *y,
+                 double *bhy, const PolyWs &ws, void *stream);
+
+// layout / noise kernels
+template <typename T>
+int copy_or_noise_t(const mpmc_lattice &lat, mpmc_shape sh, const void *x, uint64_t key, uint64_t first, void *out,
+                    void *stream);
+int pack_gauge_impl(const int32_t dims[4], int32_t prec, const double *canon, void *gauge, void *stream);
+int pack_fields_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, const double *canon, void *field, void *stream);
+int unpack_fields_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, const void *field, double *canon,
+                       void *stream);
+int z4_fill_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, const mpmc_noise &nz, void *field, void *stream);
+
+// deflation
+size_t defl_ws_bytes(const mpmc_lattice &lat, const mpmc_defl &df, mpmc_shape sh);
+int deflate_impl(const mpmc_lattice &lat, const mpmc_defl &df, int32_t mode, mpmc_shape sh, const void *b,
+                 const mpmc_noise *noise, double *zeta, double *omega, double *d, void *X, void *ws, void *stream);
+
+// level
+size_t level_ws_bytes(const mpmc_lattice &lat, const mpmc_level &lv, mpmc_shape sh);
+int level_impl(const mpmc_lattice &lat, const mpmc_level &lv, mpmc_shape sh, const mpmc_noise &nz, double *samples,
+               double *acc, void *ws, void *stream);
+
+}  // namespace mpmc

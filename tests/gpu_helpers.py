@@ -1,0 +1,52 @@
+"""Shared set-up for the GPU parity tests: synthetic inputs from `synth`,
+expected values from `oracle`, device calls through the C ABI binding."""
+import numpy as np
+import torch
+
+import oracle
+import synth
+
+
+def lib():
+    from paper_2306_09559_amd import _lib
+    return _lib
+
+
+def device_lattice(dims, kappa, eps, seed, antiperiodic=True, prec=0):
+    L = lib()
+    U = synth.unit_links(dims) if eps == 0 else synth.gauge_links(dims, eps, seed)
+    canon = torch.from_numpy(U).cuda()
+    V = int(np.prod(dims))
+    gauge = torch.empty(36 * V, dtype=L.complex_dtype(prec), device="cuda")
+    L.pack_gauge(dims, prec, canon, gauge)
+    dl = L.DeviceLattice(tuple(dims), kappa, antiperiodic, prec, gauge)
+    ol = oracle.Lattice(dims, kappa, U, antiperiodic)
+    return dl, ol
+
+
+def pack(dims, X: np.ndarray, rb: int, prec: int) -> torch.Tensor:
+    L = lib()
+    V = int(np.prod(dims))
+    N = X.shape[0]
+    canon = torch.from_numpy(np.ascontiguousarray(X.reshape(N, V, 4, 3).astype(np.complex128))).cuda()
+    f = L.empty_field(V, N, rb, prec)
+    L.pack_fields(dims, prec, canon, f)
+    return f
+
+
+def unpack(dims, f: torch.Tensor, prec: int) -> np.ndarray:
+    L = lib()
+    V = int(np.prod(dims))
+    N = f.shape[0] * f.shape[3]
+    canon = torch.empty((N, V, 4, 3), dtype=torch.complex128, device="cuda")
+    L.unpack_fields(dims, prec, f, canon)
+    torch.cuda.synchronize()
+    return canon.cpu().numpy().reshape(N, 12 * V)
+
+
+def dev_c128(a) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.complex128))).cuda()
+
+
+def rel(a, b) -> float:
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))

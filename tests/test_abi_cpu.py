@@ -1,0 +1,106 @@
+"""The C ABI library loads, exports every entry point declared in
+include/mpmc.h, and rejects invalid arguments on the host with status codes
+before touching a device.  No GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mpmc.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2306_09559_amd import _lib
+    return _lib
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mpmc_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 13
+    lib = ctypes.CDLL(L.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.EXPORTED)
+
+
+def test_status_strings(L):
+    for st in (L.OK, L.EINVAL, L.EUNSUPPORTED, L.EWORKSPACE, L.EHIP):
+        assert L.status_string(st)
+    assert "gfx950" in L.build_info()
+
+
+def _lat(L, dims=(4, 4, 4, 4), prec=0, gauge=1):
+    return L.mpmc_lattice((ctypes.c_int32 * 4)(*dims), 1, prec, 0.15, gauge)
+
+
+def test_validation_without_device(L):
+    lib = L._lib
+    sh = L.mpmc_shape(8, 4)
+    x, y = ctypes.c_void_p(16), ctypes.c_void_p(32)
+    assert lib.mpmc_wilson_apply(None, sh, x, y, None) == L.EINVAL
+    lat = _lat(L)
+    assert lib.mpmc_wilson_apply(ctypes.byref(lat), L.mpmc_shape(8, 3), x, y, None) == L.EINVAL   # rb not 2^k
+    assert lib.mpmc_wilson_apply(ctypes.byref(lat), L.mpmc_shape(6, 4), x, y, None) == L.EINVAL   # rb !| N
+    assert lib.mpmc_wilson_apply(ctypes.byref(lat), L.mpmc_shape(8, 512), x, y, None) == L.EINVAL
+    assert lib.mpmc_wilson_apply(ctypes.byref(lat), sh, x, x, None) == L.EINVAL                   # aliasing
+    bad = _lat(L, prec=7)
+    assert lib.mpmc_wilson_apply(ctypes.byref(bad), sh, x, y, None) == L.EUNSUPPORTED
+    zero = _lat(L, dims=(4, 0, 4, 4))
+    assert lib.mpmc_wilson_apply(ctypes.byref(zero), sh, x, y, None) == L.EINVAL
+    nog = _lat(L, gauge=None)
+    assert lib.mpmc_wilson_apply(ctypes.byref(nog), sh, x, y, None) == L.EINVAL
+    # polynomial: no roots, no outputs, workspace too small
+    roots = ctypes.c_void_p(64)
+    p0 = L.mpmc_poly(0, 0, roots, None)
+    assert lib.mpmc_poly_apply(ctypes.byref(lat), ctypes.byref(p0), sh, x, None, y, None, None, 0, None) == L.EINVAL
+    p = L.mpmc_poly(5, 0, roots, None)
+    assert lib.mpmc_poly_apply(ctypes.byref(lat), ctypes.byref(p), sh, x, None, None, None, None, 0, None) == L.EINVAL
+    assert lib.mpmc_poly_apply(ctypes.byref(lat), ctypes.byref(p), sh, None, None, y, None, None, 0, None) == L.EINVAL
+    need = lib.mpmc_poly_workspace_size(ctypes.byref(lat), ctypes.byref(p), sh)
+    assert need > 0
+    assert lib.mpmc_poly_apply(ctypes.byref(lat), ctypes.byref(p), sh, x, None, y, None,
+                               ctypes.c_void_p(128), need - 1, None) == L.EWORKSPACE
+    pc = L.mpmc_poly(5, 3, roots, None)   # composite without outer roots
+    assert lib.mpmc_poly_apply(ctypes.byref(lat), ctypes.byref(pc), sh, x, None, y, None, None, 0, None) == L.EINVAL
+    # deflation: kpad not a multiple of 16, unknown mode, PROJECT without H^{-1}
+    d = L.mpmc_defl(4, 8, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(8), None)
+    z = ctypes.c_void_p(256)
+    assert lib.mpmc_deflate_project(ctypes.byref(lat), ctypes.byref(d), 0, sh, x, None, z, z, None, None, None, 0,
+                                    None) == L.EINVAL
+    d16 = L.mpmc_defl(4, 16, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(8), None)
+    assert lib.mpmc_deflate_project(ctypes.byref(lat), ctypes.byref(d16), 9, sh, x, None, z, z, None, None, None, 0,
+                                    None) == L.EUNSUPPORTED
+    assert lib.mpmc_deflate_project(ctypes.byref(lat), ctypes.byref(d16), 2, sh, x, None, z, z, z, y, None, 0,
+                                    None) == L.EINVAL
+    # level: NONE as the high operator, deflated samples without c
+    lv = L.mpmc_level(0, 0, p, p, None, 0, None)
+    nz = L.mpmc_noise(1, 2, 3, 0)
+    assert lib.mpmc_mlmc_level_estimate(ctypes.byref(lat), ctypes.byref(lv), sh, ctypes.byref(nz), z, z, None, 0,
+                                        None) == L.EUNSUPPORTED
+    lv2 = L.mpmc_level(1, 0, p, p, ctypes.pointer(d16), 1, None)
+    assert lib.mpmc_mlmc_level_estimate(ctypes.byref(lat), ctypes.byref(lv2), sh, ctypes.byref(nz), z, z, None, 0,
+                                        None) == L.EINVAL
+
+
+def test_workspace_sizes_scale(L):
+    lib = L._lib
+    lat = _lat(L)
+    roots = ctypes.c_void_p(64)
+    single = L.mpmc_poly(21, 0, roots, None)
+    comp = L.mpmc_poly(20, 15, roots, roots)
+    sh = L.mpmc_shape(64, 16)
+    a = lib.mpmc_poly_workspace_size(ctypes.byref(lat), ctypes.byref(single), sh)
+    b = lib.mpmc_poly_workspace_size(ctypes.byref(lat), ctypes.byref(comp), sh)
+    field = 256 * 12 * 64 * 16
+    assert a >= 2 * field and b >= 5 * field
+    lat32 = _lat(L, prec=1)
+    assert lib.mpmc_poly_workspace_size(ctypes.byref(lat32), ctypes.byref(single), sh) < a

@@ -1,0 +1,415 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+FP64 bar: 1e-12 relative (normwise for vectors; per constituent for sample
+values), bit-exact for noise.  FP32 bar: the stated mixed-precision bound
+8 * d * kappa_N * u32 per constituent (kappa_N = max_j ||w_j|| / ||b||).
+Sizes span several workgroups and ragged tails (V * rb not a multiple of 256).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import deflation, dense, estimator, krylov
+
+from gpu_helpers import dev_c128, device_lattice, lib, pack, rel, unpack
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    lib()
+
+
+# ------------------------------------------------------------------ noise / layout
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("dims,nrhs,rb", [((4, 4, 4, 4), 12, 4), ((3, 2, 2, 5), 8, 8), ((2, 2, 2, 2), 5, 1)])
+def test_z4_bit_exact(dims, nrhs, rb, prec):
+    L = lib()
+    V = int(np.prod(dims))
+    f = L.empty_field(V, nrhs, rb, prec)
+    nz = L.Noise(777, 3, 2, 40)
+    L.z4_fill(dims, prec, nz, f)
+    got = unpack(dims, f, prec)
+    ref = oracle.z4(777, 3, 2, 40, nrhs, V)
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_pack_roundtrip(prec):
+    dims = (4, 2, 2, 6)
+    V = int(np.prod(dims))
+    X = synth.random_fields(6, V, 3).reshape(6, -1)
+    f = pack(dims, X, 2, prec)
+    back = unpack(dims, f, prec)
+    if prec == 0:
+        assert np.array_equal(back, X)
+    else:
+        assert np.array_equal(back, X.astype(np.complex64).astype(np.complex128))
+
+
+# ------------------------------------------------------------------ operator
+@pytest.mark.parametrize("dims,nrhs,rb,ap", [
+    ((4, 4, 4, 4), 16, 16, True),      # C1 geometry
+    ((4, 4, 4, 4), 12, 4, False),
+    ((3, 2, 2, 5), 8, 2, True),        # odd extents, ragged last workgroup
+    ((2, 4, 2, 2), 3, 1, True),
+    ((8, 4, 4, 4), 64, 64, True),      # one site per workgroup quarter
+])
+def test_wilson_apply_f64(dims, nrhs, rb, ap):
+    L = lib()
+    dl, ol = device_lattice(dims, 0.137, 0.5, 11, ap, prec=0)
+    X = synth.random_fields(nrhs, dl.V, 5).reshape(nrhs, -1)
+    x = pack(dims, X, rb, 0)
+    y = torch.empty_like(x)
+    L.wilson_apply(dl, x, y)
+    got = unpack(dims, y, 0)
+    ref = ol.apply(X)
+    for r in range(nrhs):
+        assert rel(got[r], ref[r]) < 1e-12
+
+
+def test_wilson_apply_f32():
+    L = lib()
+    dims = (4, 4, 4, 6)
+    dl, ol = device_lattice(dims, 0.15, 0.5, 12, True, prec=1)
+    X = synth.random_fields(8, dl.V, 6).reshape(8, -1)
+    x = pack(dims, X, 8, 1)
+    y = torch.empty_like(x)
+    L.wilson_apply(dl, x, y)
+    got = unpack(dims, y, 1)
+    ref = ol.apply(X)
+    # each output is a 9-term sum of O(1) products: a few units of FP32 rounding
+    assert rel(got, ref) < 30 * U32
+
+
+def test_wilson_free_field_plane_wave():
+    """Free field: a plane wave is mapped to its closed-form eigen-combination."""
+    L = lib()
+    dims, kappa = (4, 4, 2, 4), 0.13
+    dl, _ = device_lattice(dims, kappa, 0.0, 1, True, prec=0)
+    lat = oracle.Lattice(dims, kappa, synth.unit_links(dims))
+    A = dense.dense_matrix(lat)
+    ev, R = np.linalg.eig(A)
+    X = R[:, :4].T.copy()
+    x = pack(dims, X, 4, 0)
+    y = torch.empty_like(x)
+    L.wilson_apply(dl, x, y)
+    got = unpack(dims, y, 0)
+    for i in range(4):
+        assert rel(got[i], ev[i] * X[i]) < 1e-12
+
+
+# ------------------------------------------------------------------ polynomials
+def _roots(ol, degs, seed=3):
+    ps = krylov.gmres_polys(ol.apply, synth.gaussian_start(ol.n, seed), degs)
+    return ps
+
+
+@pytest.mark.parametrize("deg,nrhs,rb,z4", [(0, 4, 4, True), (1, 4, 2, False), (5, 12, 4, True),
+                                            (20, 16, 16, True), (20, 6, 2, False)])
+def test_poly_apply_f64(deg, nrhs, rb, z4):
+    L = lib()
+    dims = (4, 4, 4, 4)
+    dl, ol = device_lattice(dims, 0.15, 0.5, 101, True)
+    ps = _roots(ol, [max(deg, 1)])
+    t = ps.inv_roots[max(deg, 1)][: deg + 1]
+    poly = L.DevicePoly(dev_c128(t))
+    if z4:
+        nz = L.Noise(5, 1, 0, 10)
+        B = oracle.z4(5, 1, 0, 10, nrhs, dl.V)
+        xin = None
+    else:
+        nz = None
+        B = synth.random_fields(nrhs, dl.V, 9).reshape(nrhs, -1)
+        xin = pack(dims, B, rb, 0)
+    y = L.empty_field(dl.V, nrhs, rb, 0)
+    bhy = torch.empty(nrhs, dtype=torch.complex128, device="cuda")
+    ws = L.workspace(L.poly_workspace_size(dl, poly, nrhs, rb))
+    L.poly_apply(dl, poly, nrhs, rb, xin, nz, y, bhy, ws)
+    ref_y, ref_bhy = ol.poly_apply(t, B)
+    got = unpack(dims, y, 0)
+    gb = bhy.cpu().numpy()
+    for r in range(nrhs):
+        assert rel(got[r], ref_y[r]) < 1e-12
+        assert abs(gb[r] - ref_bhy[r]) <= 1e-12 * abs(ref_bhy[r])
+
+
+def test_poly_scalar_mode_matches_vector_mode():
+    L = lib()
+    dims = (4, 4, 4, 4)
+    dl, ol = device_lattice(dims, 0.15, 0.5, 101, True)
+    t = _roots(ol, [12]).inv_roots[12]
+    poly = L.DevicePoly(dev_c128(t))
+    nz = L.Noise(9, 1, 1, 0)
+    ws = L.workspace(L.poly_workspace_size(dl, poly, 32, 16))
+    b1 = torch.empty(32, dtype=torch.complex128, device="cuda")
+    b2 = torch.empty_like(b1)
+    L.poly_apply(dl, poly, 32, 16, None, nz, None, b1, ws)
+    L.poly_apply(dl, poly, 32, 16, None, nz, L.empty_field(dl.V, 32, 16, 0), b2, ws)
+    assert torch.equal(b1, b2)
+    _, ref = ol.poly_apply(t, oracle.z4(9, 1, 1, 0, 32, dl.V))
+    assert np.max(np.abs(b1.cpu().numpy() - ref) / np.abs(ref)) < 1e-12
+
+
+@pytest.mark.parametrize("n_in,n_out,nrhs,rb", [(4, 3, 8, 4), (5, 1, 4, 4), (1, 4, 4, 2), (6, 5, 16, 16)])
+def test_composite_f64(n_in, n_out, nrhs, rb):
+    L = lib()
+    dims = (4, 4, 4, 4)
+    dl, ol = device_lattice(dims, 0.15, 0.5, 101, True)
+    r0 = synth.gaussian_start(ol.n, 4)
+    ps = krylov.gmres_polys(ol.apply, r0, [max(n_in - 1, 1)])
+    t_in = ps.inv_roots[max(n_in - 1, 1)][:n_in]
+    opB = krylov.pp_operator(ol.apply, t_in, lambda t, v: ol.poly_apply(t, v)[0])
+    t_out, _ = krylov.pp_gmres_roots(opB, r0, n_out=n_out)
+    poly = L.DevicePoly(dev_c128(t_in), dev_c128(t_out))
+    nz = L.Noise(21, 1, 0, 0)
+    B = oracle.z4(21, 1, 0, 0, nrhs, dl.V)
+    y = L.empty_field(dl.V, nrhs, rb, 0)
+    bhy = torch.empty(nrhs, dtype=torch.complex128, device="cuda")
+    ws = L.workspace(L.poly_workspace_size(dl, poly, nrhs, rb))
+    L.poly_apply(dl, poly, nrhs, rb, None, nz, y, bhy, ws)
+    ref_y, ref_b = ol.composite_apply(t_in, t_out, B)
+    got = unpack(dims, y, 0)
+    gb = bhy.cpu().numpy()
+    for r in range(nrhs):
+        assert rel(got[r], ref_y[r]) < 1e-12
+        assert abs(gb[r] - ref_b[r]) <= 1e-12 * abs(ref_b[r])
+
+
+def _kappa_N(ol, t, B):
+    """max_j ||w_j|| / ||b|| over the Newton recurrence (the amplification of
+    rounding errors through the polynomial)."""
+    out = 1.0
+    for b in B:
+        w = b.copy()
+        nb = np.linalg.norm(b)
+        for tj in t[:-1]:
+            w = w - tj * ol.apply(w)
+            out = max(out, np.linalg.norm(w) / nb)
+    return out
+
+
+def test_poly_apply_f32_bound():
+    L = lib()
+    dims = (4, 4, 4, 4)
+    dl, ol = device_lattice(dims, 0.15, 0.5, 101, True, prec=1)
+    deg = 20
+    t = _roots(ol, [deg]).inv_roots[deg]
+    poly = L.DevicePoly(dev_c128(t))
+    nrhs = 8
+    nz = L.Noise(5, 1, 0, 0)
+    B = oracle.z4(5, 1, 0, 0, nrhs, dl.V)
+    bhy = torch.empty(nrhs, dtype=torch.complex128, device="cuda")
+    ws = L.workspace(L.poly_workspace_size(dl, poly, nrhs, 8))
+    L.poly_apply(dl, poly, nrhs, 8, None, nz, None, bhy, ws)
+    _, ref = ol.poly_apply(t, B)
+    kN = _kappa_N(ol, t, B[:2])
+    bound = 8 * deg * kN * U32
+    err = np.abs(bhy.cpu().numpy() - ref) / np.abs(ref)
+    assert np.max(err) < bound, (np.max(err), bound)
+
+
+# ------------------------------------------------------------------ deflation
+@pytest.fixture(scope="module")
+def small_defl():
+    dims = (2, 2, 2, 4)
+    dl, ol = device_lattice(dims, 0.16, 0.5, 21, True)
+    A = dense.dense_matrix(ol)
+    lam, Z, pair = deflation.dense_triplets(A, 10, ol.gamma5)
+    U = deflation.left_vectors(Z, pair, ol.gamma5)
+    H = deflation.projection_matrix(ol.apply, Z, U)
+    return dims, dl, ol, lam, Z, pair, U, H
+
+
+def _device_defl(dims, Z, pair, U, H, prec=0, kpad=16):
+    L = lib()
+    k, n = Z.shape
+    Zp = np.zeros((kpad, n), dtype=np.complex128)
+    Zp[:k] = Z
+    Vf = pack(dims, Zp, kpad, prec)
+    # scale_i: u_i = scale_i * g5 z_pair(i)
+    g5 = np.array([1] * 6 + [-1] * 6, dtype=float)
+    V = n // 12
+    g5z = (Z.reshape(k, V, 12) * g5).reshape(k, n)
+    scale = np.array([np.vdot(g5z[pair[i]], U[i]) / np.vdot(g5z[pair[i]], g5z[pair[i]]) for i in range(k)])
+    assert np.allclose(U, scale[:, None] * g5z[pair])
+    return L.DeviceDefl(k, Vf, torch.from_numpy(pair.astype(np.int32)).cuda(), dev_c128(scale),
+                        dev_c128(np.linalg.inv(H)) if H is not None else None)
+
+
+@pytest.mark.parametrize("nrhs,rb,z4", [(8, 4, True), (5, 1, False), (40, 8, True)])
+def test_deflate_coeff(small_defl, nrhs, rb, z4):
+    L = lib()
+    dims, dl, ol, lam, Z, pair, U, H = small_defl
+    D = _device_defl(dims, Z, pair, U, H)
+    if z4:
+        nz = L.Noise(3, 2, 1, 0)
+        B = oracle.z4(3, 2, 1, 0, nrhs, dl.V)
+        bf = None
+    else:
+        nz = None
+        B = synth.random_fields(nrhs, dl.V, 2).reshape(nrhs, -1)
+        bf = pack(dims, B, rb, 0)
+    k = D.k
+    zeta = torch.empty((k, nrhs), dtype=torch.complex128, device="cuda")
+    omega = torch.empty_like(zeta)
+    ws = L.workspace(L.deflate_workspace_size(dl, D, nrhs, rb))
+    L.deflate_project(dl, D, L.DEFL_COEFF, nrhs, rb, bf, nz, zeta, omega, None, None, ws)
+    rz, ro = deflation.projection_coefficients(Z, U, B)
+    nb = np.linalg.norm(B, axis=1)
+    assert np.max(np.abs(zeta.cpu().numpy() - rz) / nb) < 1e-12
+    assert np.max(np.abs(omega.cpu().numpy() - ro) / (nb * np.linalg.norm(U, axis=1)[:, None])) < 1e-12
+
+
+def test_deflate_coeff_large_random():
+    """Tall-skinny V^H b over 4^4 x 12 rows with k = 20 padded to 32, ragged N."""
+    L = lib()
+    dims = (4, 4, 4, 4)
+    dl, ol = device_lattice(dims, 0.15, 0.5, 5, True)
+    k, n = 20, 12 * dl.V
+    rng = np.random.default_rng(0)
+    Z = rng.standard_normal((k, n)) + 1j * rng.standard_normal((k, n))
+    pair = np.arange(k)
+    U = np.stack([ol.gamma5(Z[i]) for i in range(k)]) * 0.5
+    D = _device_defl(dims, Z, pair, U, None, kpad=32)
+    nrhs, rb = 100, 4
+    nz = L.Noise(8, 1, 2, 100)
+    B = oracle.z4(8, 1, 2, 100, nrhs, dl.V)
+    zeta = torch.empty((k, nrhs), dtype=torch.complex128, device="cuda")
+    omega = torch.empty_like(zeta)
+    ws = L.workspace(L.deflate_workspace_size(dl, D, nrhs, rb))
+    L.deflate_project(dl, D, L.DEFL_COEFF, nrhs, rb, None, nz, zeta, omega, None, None, ws)
+    rz, ro = deflation.projection_coefficients(Z, U, B)
+    scale = np.linalg.norm(Z, axis=1)[:, None] * np.linalg.norm(B, axis=1)[None, :]
+    assert np.max(np.abs(zeta.cpu().numpy() - rz) / scale) < 1e-13
+    assert np.max(np.abs(omega.cpu().numpy() - ro) / scale) < 1e-13
+
+
+def test_deflate_recon_and_project(small_defl):
+    L = lib()
+    dims, dl, ol, lam, Z, pair, U, H = small_defl
+    D = _device_defl(dims, Z, pair, U, H)
+    nrhs, rb = 6, 2
+    k = D.k
+    rng = np.random.default_rng(1)
+    d = rng.standard_normal((k, nrhs)) + 1j * rng.standard_normal((k, nrhs))
+    X = L.empty_field(dl.V, nrhs, rb, 0)
+    ws = L.workspace(L.deflate_workspace_size(dl, D, nrhs, rb))
+    L.deflate_project(dl, D, L.DEFL_RECON, nrhs, rb, None, None, None, None, dev_c128(d), X, ws)
+    ref = (Z.T @ d).T
+    assert rel(unpack(dims, X, 0), ref) < 1e-13
+    # projection of Z4 vectors
+    nz = L.Noise(4, 4, 4, 0)
+    B = oracle.z4(4, 4, 4, 0, nrhs, dl.V)
+    dd = torch.empty((k, nrhs), dtype=torch.complex128, device="cuda")
+    L.deflate_project(dl, D, L.DEFL_PROJECT, nrhs, rb, None, nz, None, None, dd, X, ws)
+    got = unpack(dims, X, 0)
+    for r in range(nrhs):
+        _, rr = deflation.left_right_projection(ol.apply, Z, U, H, B[r])
+        assert rel(got[r], rr) < 1e-12
+        assert np.linalg.norm(U.conj() @ got[r]) < 1e-11 * np.linalg.norm(B[r])
+
+
+# ------------------------------------------------------------------ levels
+def _run_level(dl, level, nrhs, rb, nz):
+    L = lib()
+    samples = torch.empty((nrhs, 6), dtype=torch.float64, device="cuda")
+    acc = torch.zeros(8, dtype=torch.float64, device="cuda")
+    ws = L.workspace(L.level_workspace_size(dl, level, nrhs, rb))
+    L.mlmc_level_estimate(dl, level, nrhs, rb, nz, samples, acc, ws)
+    torch.cuda.synchronize()
+    s = samples.cpu().numpy()
+    return s[:, 0] + 1j * s[:, 1], s[:, 2] + 1j * s[:, 3], s[:, 4] + 1j * s[:, 5], acc.cpu().numpy()
+
+
+def test_level_c1_two_levels():
+    """C1 geometry: Tr(p20 - p5) and Tr(p5), 100 samples each, per-sample parity."""
+    from synth.configs import C1
+    L = lib()
+    dl, ol = device_lattice(C1.dims, C1.kappa, C1.eps, C1.seed_links, True)
+    ps = krylov.gmres_polys(ol.apply, synth.gaussian_start(ol.n, C1.seed_start), [20, 5])
+    p20, p5 = L.DevicePoly(dev_c128(ps.inv_roots[20])), L.DevicePoly(dev_c128(ps.inv_roots[5]))
+    for lvl, level in enumerate([L.DeviceLevel(L.OP_POLY, p20, L.OP_POLY, p5), L.DeviceLevel(L.OP_POLY, p5)]):
+        nz = L.Noise(C1.seed_noise, C1.lattice_id, lvl, 0)
+        s, hi, lo, acc = _run_level(dl, level, 100, 4, nz)
+        B = oracle.z4(C1.seed_noise, C1.lattice_id, lvl, 0, 100, dl.V)
+        _, rh = ol.poly_apply(ps.inv_roots[20 if lvl == 0 else 5], B)
+        rl = ol.poly_apply(ps.inv_roots[5], B)[1] if lvl == 0 else np.zeros(100)
+        assert np.max(np.abs(hi - rh) / np.abs(rh)) < 1e-12
+        if lvl == 0:
+            assert np.max(np.abs(lo - rl) / np.abs(rl)) < 1e-12
+        rs = estimator.level_samples(rh, rl if lvl == 0 else None)
+        assert np.max(np.abs(s - rs) / (np.abs(rh) + np.abs(rl))) < 1e-12
+        est = estimator.level_estimate(rs)
+        assert acc[0] == 100
+        assert abs(acc[1] + 1j * acc[2] - est.mean) <= 1e-12 * (np.abs(rh).mean() + np.abs(rl).mean())
+        assert abs(acc[3] / 99 - est.var) <= 1e-9 * est.var
+        assert acc[4] == 0
+
+
+def test_level_deflated_and_q_operator(small_defl):
+    L = lib()
+    dims, dl, ol, lam, Z, pair, U, H = small_defl
+    D = _device_defl(dims, Z, pair, U, H)
+    ps = krylov.gmres_polys(ol.apply, synth.gaussian_start(ol.n, 7), [12, 3])
+    t12, t3 = ps.inv_roots[12], ps.inv_roots[3]
+    nrhs, rb = 24, 8
+    # (a) Tr(p12 - p3) with Monte Carlo deflation
+    c = deflation.deflation_coefficients(lam, lambda l: deflation.poly_eval(t12, l),
+                                         lambda l: deflation.poly_eval(t3, l))
+    lvl = L.DeviceLevel(L.OP_POLY, L.DevicePoly(dev_c128(t12)), L.OP_POLY, L.DevicePoly(dev_c128(t3)), D, True,
+                        dev_c128(c))
+    nz = L.Noise(1, 9, 1, 0)
+    s, hi, lo, acc = _run_level(dl, lvl, nrhs, rb, nz)
+    B = oracle.z4(1, 9, 1, 0, nrhs, dl.V)
+    _, rh = ol.poly_apply(t12, B)
+    _, rl = ol.poly_apply(t3, B)
+    zeta, omega = deflation.projection_coefficients(Z, U, B)
+    rs = estimator.level_samples(rh, rl, zeta, omega, c)
+    scale = np.abs(rh) + np.abs(rl) + np.einsum("i,ir->r", np.abs(c), np.abs(zeta) * np.abs(omega))
+    assert np.max(np.abs(s - rs) / scale) < 1e-12
+    # (b) Tr(Q - p3): Q the deflated polynomial built on p12
+    cq = deflation.deflation_coefficients(lam, lambda l: 1.0 / l, lambda l: deflation.poly_eval(t3, l))
+    lq = L.DeviceLevel(L.OP_DEFLATED_POLY, L.DevicePoly(dev_c128(t12)), L.OP_POLY, L.DevicePoly(dev_c128(t3)), D,
+                       True, dev_c128(cq))
+    s2, hi2, lo2, _ = _run_level(dl, lq, nrhs, rb, nz)
+    Q = deflation.DeflatedPoly(ol.apply, Z, U, H, lambda v: ol.poly_apply(t12, v)[0])
+    rq = np.array([np.vdot(B[r], Q.apply(B[r])) for r in range(nrhs)])
+    assert np.max(np.abs(hi2 - rq) / np.abs(rq)) < 1e-12
+    rs2 = estimator.level_samples(rq, rl, zeta, omega, cq)
+    scale2 = np.abs(rq) + np.abs(rl) + np.einsum("i,ir->r", np.abs(cq), np.abs(zeta) * np.abs(omega))
+    assert np.max(np.abs(s2 - rs2) / scale2) < 1e-12
+
+
+def test_level_accumulates_batches_and_is_deterministic():
+    L = lib()
+    dims = (4, 4, 4, 4)
+    dl, ol = device_lattice(dims, 0.15, 0.5, 101, True)
+    t = _roots(ol, [6]).inv_roots[6]
+    level = L.DeviceLevel(L.OP_POLY, L.DevicePoly(dev_c128(t)))
+    acc = torch.zeros(8, dtype=torch.float64, device="cuda")
+    samples = torch.empty((32, 6), dtype=torch.float64, device="cuda")
+    ws = L.workspace(L.level_workspace_size(dl, level, 32, 8))
+    allS = []
+    for b in range(3):
+        L.mlmc_level_estimate(dl, level, 32, 8, L.Noise(2, 1, 0, 32 * b), samples, acc, ws)
+        allS.append(samples.clone())
+    torch.cuda.synchronize()
+    S = torch.cat(allS).cpu().numpy()
+    s = S[:, 0] + 1j * S[:, 1]
+    est = estimator.level_estimate(s)
+    a = acc.cpu().numpy()
+    assert a[0] == 96
+    assert abs(a[1] + 1j * a[2] - est.mean) < 1e-12 * np.abs(s).mean()
+    assert abs(a[3] / 95 - est.var) < 1e-10 * est.var
+    # same inputs -> bitwise identical samples
+    L.mlmc_level_estimate(dl, level, 32, 8, L.Noise(2, 1, 0, 0), samples, acc, ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(samples.cpu().numpy(), S[:32])
