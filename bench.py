@@ -1,0 +1,189 @@
+"""Benchmark of the multipolynomial Monte Carlo hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec f64|f32]
+
+Workload: the 8^4 Wilson-Dirac lattice (n = 49152, eps = 0.3 links, periodic
+time, kappa with |lambda_min| = 1e-3), three levels Tr(p150 - p30) and
+Tr(p30 - p8) with 20 deflation eigenvectors and Tr(p8), 256 Z4 samples per
+level, FP64.  A step is one pass of every level over its batch: noise
+generation, deflation coefficient GEMMs, the polynomial applications (fused
+Wilson-Dirac + Newton + FP64 dot kernels) and the FP64 level reductions.
+Set-up (GMRES roots, PP-Arnoldi eigenvectors, on the GPU) is done before the
+timed region and reported separately.
+
+Prints one JSON line (rank 0): value = algorithmic HBM GB/s of the operator
+applications of the whole step, a roofline object for the dominant kernel
+(the fused Newton step) and a cpu_baseline object (the FP64 oracle on a
+bounded sample of the same workload, on the host cores).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL = "k_hop (fused Wilson-Dirac + Newton step + FP64 b^H w partial)"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--prec", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--rb", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("hop.hip", "common.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2306_09559_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(prec: str):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", f"k_hop_c2_{prec}_traffic.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(cfg, run_prec: str):
+    """The oracle (plain C FP64, OpenMP over sites) on a bounded sample of the
+    same workload: rounds of one Z4 sample per level (every polynomial of
+    the level applied) until about 12 s have passed, roots from the oracle's
+    own GMRES (not timed).  Scaled to the metric's unit (algorithmic GB/s)."""
+    import numpy as np
+    import oracle
+    import synth
+    from oracle import krylov as okr
+    U = synth.gauge_links(cfg.dims, cfg.eps, cfg.seed_links)
+    lat = oracle.Lattice(cfg.dims, cfg.kappa, U, cfg.antiperiodic_t)
+    degs = sorted({d for lv in cfg.levels for d in (lv.hi, lv.lo) if isinstance(d, int)})
+    ps = okr.gmres_polys(lat.apply, synth.gaussian_start(lat.n, cfg.seed_start), degs)
+    t0 = time.perf_counter()
+    mvps = 0
+    nsamp = 0
+    while time.perf_counter() - t0 < 12.0 and nsamp < cfg.levels[0].samples:
+        for li, lv in enumerate(cfg.levels):
+            b = oracle.z4(cfg.seed_noise, cfg.lattice_id, li, nsamp, 1, lat.V)
+            lat.poly_apply(ps.inv_roots[lv.hi], b)
+            mvps += lv.hi
+            if lv.lo is not None:
+                lat.poly_apply(ps.inv_roots[lv.lo], b)
+                mvps += lv.lo
+        nsamp += 1
+    dt = time.perf_counter() - t0
+    # the same algorithmic bytes per MVP on one vector as the GPU metric counts
+    # for the workload's batches of N vectors (FP64)
+    N = cfg.levels[0].samples
+    byts = mvps * lat.V * (24 * 16 + 36 * 16 / N)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(byts / dt / 1e9, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": f"{nsamp} Z4 samples of each level (p150, p30, p8 Newton applications, {mvps} MVPs), "
+                      f"no deflation GEMM, FP64; {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                          "(sample-parallel sharding across GPUs is a design note, not implemented)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2306_09559_amd import _lib as L
+    from paper_2306_09559_amd import driver
+    from synth.configs import C2
+
+    torch.cuda.set_device(0)
+    prec = L.F64 if args.prec == "f64" else L.F32
+    run = driver.build(C2, prec=prec, rb=args.rb)
+    V, N = run.dl.V, C2.levels[0].samples
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        run.step()
+    torch.cuda.synchronize()
+    run.reset()
+
+    nl = len(run.levels)
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nl)]
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        for i in range(nl):
+            ev[k][i][0].record(stream)
+            run.draw(i, C2.levels[i].samples)
+            ev[k][i][1].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lvl_ms = np.array([sum(ev[k][i][0].elapsed_time(ev[k][i][1]) for k in range(args.steps)) for i in range(nl)])
+    wall = t1 - t0
+    ms_per_step = wall / args.steps * 1e3
+    byts = run.bytes_per_step()
+    value = byts * args.steps / wall / 1e9
+
+    # dominant kernel: every operator application of a level is one k_hop launch
+    # on `stream`; its average duration over the timed region from the level events
+    launches = sum(lv.mvps_per_sample for lv in run.levels) * args.steps
+    kernel_s = lvl_ms.sum() * 1e-3
+    per_launch_bytes = driver.launch_bytes(V, N, prec)
+    achieved = per_launch_bytes / (kernel_s / launches) / 1e9
+    traffic = measured_traffic(args.prec)
+
+    est = run.estimates()
+    eps = 0.0005 * V
+    per_sample_s = [lvl_ms[i] * 1e-3 / (args.steps * C2.levels[i].samples) for i in range(len(run.levels))]
+    t_eps = driver.time_to_error([e["variance"] for e in est], per_sample_s, eps)
+    out = {
+        "metric": "p(A)B dslash HBM GB/s (% peak); time to fixed trace std-error, mixed vs FP64",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": "8^4 Wilson-Dirac n=49152, eps=0.3 links, periodic t, kappa=%.6f; levels "
+                               "Tr(p150-p30) & Tr(p30-p8) deflated (k=%d), Tr(p8); %d Z4 samples per level"
+                               % (C2.kappa, run.defl.device.k if run.defl else 0, N),
+                   "rb": args.rb, "prec": args.prec},
+        "pct_peak": round(100 * value / HBM_PEAK_GBS, 2),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": KERNEL, "bytes_per_launch": per_launch_bytes,
+                     "avg_launch_us": round(kernel_s / launches * 1e6, 3)},
+        "time_to_eps_s": round(t_eps, 4),
+        "eps": eps,
+        "levels": [{"estimate": [round(e["estimate"].real, 6), round(e["estimate"].imag, 6)],
+                    "stderr": e["stderr"], "n": e["n"]} for e in est],
+        "mvp_rhs_per_step": run.mvp_rhs_per_step(),
+        "setup_s": round(run.setup_seconds, 2),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(C2, args.prec)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

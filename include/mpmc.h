@@ -146,6 +146,28 @@ int mpmc_unpack_fields(const int32_t dims[4], int32_t prec, mpmc_shape shape, co
 int mpmc_z4_fill(const int32_t dims[4], int32_t prec, mpmc_shape shape, const mpmc_noise *noise,
                  void *field, void *stream);
 
+/* ---- vector utilities for the Krylov set-up (Sec. 5, setup step 2) ------ */
+
+/* y_r = alpha_r x_r + beta_r y_r for every vector r of a batch.
+ *   alpha  device, N complex FP64 (rounded to the field precision)
+ *   beta   device, N complex FP64, or NULL: y_r = alpha_r x_r (y is not read)
+ * x and y are device fields of the same shape; x == y is allowed. */
+int mpmc_field_axpby(const int32_t dims[4], int32_t prec, mpmc_shape shape, const double *alpha, const void *x,
+                     const double *beta, void *y, void *stream);
+
+size_t mpmc_field_dot_workspace_size(const int32_t dims[4], mpmc_shape shape);
+
+/* out_r = x_r^H y_r accumulated in FP64 in a fixed order (bitwise
+ * reproducible).  out: device, N complex FP64. */
+int mpmc_field_dot(const int32_t dims[4], int32_t prec, mpmc_shape shape, const void *x, const void *y, double *out,
+                   void *ws, size_t ws_bytes, void *stream);
+
+/* Copy vector src_index of batch src (shape src_shape) into vector
+ * dst_index of batch dst (shape dst_shape): moves single vectors in and out
+ * of an Arnoldi basis held as a batch with nrhs = rb.  src != dst. */
+int mpmc_field_copy_vector(const int32_t dims[4], int32_t prec, mpmc_shape src_shape, const void *src,
+                           int32_t src_index, mpmc_shape dst_shape, void *dst, int32_t dst_index, void *stream);
+
 /* ---- the operator ------------------------------------------------------ */
 
 /* y = A x for N vectors (the matrix-vector product every cost in the paper

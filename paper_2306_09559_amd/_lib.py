@@ -67,6 +67,11 @@ _sig = {
     "mpmc_pack_fields": (ctypes.c_int, [P(c_i32), c_i32, mpmc_shape, c_vp, c_vp, c_vp]),
     "mpmc_unpack_fields": (ctypes.c_int, [P(c_i32), c_i32, mpmc_shape, c_vp, c_vp, c_vp]),
     "mpmc_z4_fill": (ctypes.c_int, [P(c_i32), c_i32, mpmc_shape, P(mpmc_noise), c_vp, c_vp]),
+    "mpmc_field_axpby": (ctypes.c_int, [P(c_i32), c_i32, mpmc_shape, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "mpmc_field_dot_workspace_size": (c_size, [P(c_i32), mpmc_shape]),
+    "mpmc_field_dot": (ctypes.c_int, [P(c_i32), c_i32, mpmc_shape, c_vp, c_vp, c_vp, c_vp, c_size, c_vp]),
+    "mpmc_field_copy_vector": (ctypes.c_int, [P(c_i32), c_i32, mpmc_shape, c_vp, c_i32, mpmc_shape, c_vp, c_i32,
+                                              c_vp]),
     "mpmc_wilson_apply": (ctypes.c_int, [P(mpmc_lattice), mpmc_shape, c_vp, c_vp, c_vp]),
     "mpmc_poly_workspace_size": (c_size, [P(mpmc_lattice), P(mpmc_poly), mpmc_shape]),
     "mpmc_poly_apply": (ctypes.c_int, [P(mpmc_lattice), P(mpmc_poly), mpmc_shape, c_vp, P(mpmc_noise), c_vp,
@@ -241,6 +246,29 @@ def z4_fill(dims, prec: int, noise: Noise, field: torch.Tensor):
     nz = noise.c()
     _check("mpmc_z4_fill", _lib.mpmc_z4_fill(_dims(dims), prec, field_shape(field), ctypes.byref(nz), _ptr(field),
                                              _stream()))
+
+
+def field_axpby(dims, prec: int, alpha: torch.Tensor, x: torch.Tensor, beta: Optional[torch.Tensor],
+                y: torch.Tensor):
+    """y_r = alpha_r x_r + beta_r y_r (alpha, beta: complex128 device (N,))."""
+    _check("mpmc_field_axpby", _lib.mpmc_field_axpby(_dims(dims), prec, field_shape(x), _ptr(alpha), _ptr(x),
+                                                     _ptr(beta), _ptr(y), _stream()))
+
+
+def field_dot_workspace_size(dims, nrhs: int, rb: int) -> int:
+    return int(_lib.mpmc_field_dot_workspace_size(_dims(dims), mpmc_shape(nrhs, rb)))
+
+
+def field_dot(dims, prec: int, x: torch.Tensor, y: torch.Tensor, out: torch.Tensor, ws: torch.Tensor):
+    """out_r = x_r^H y_r in FP64 (out: complex128 device (N,))."""
+    _check("mpmc_field_dot", _lib.mpmc_field_dot(_dims(dims), prec, field_shape(x), _ptr(x), _ptr(y), _ptr(out),
+                                                 _ptr(ws), ws.numel(), _stream()))
+
+
+def field_copy_vector(dims, prec: int, src: torch.Tensor, src_index: int, dst: torch.Tensor, dst_index: int):
+    _check("mpmc_field_copy_vector", _lib.mpmc_field_copy_vector(
+        _dims(dims), prec, field_shape(src), _ptr(src), int(src_index), field_shape(dst), _ptr(dst),
+        int(dst_index), _stream()))
 
 
 def wilson_apply(lat: DeviceLattice, x: torch.Tensor, y: torch.Tensor):

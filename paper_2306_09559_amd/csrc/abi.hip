@@ -140,6 +140,35 @@ int mpmc_wilson_apply(const mpmc_lattice *lat, mpmc_shape shape, const void *x, 
                                  : wilson_apply_t<float>(*lat, shape, x, y, stream);
 }
 
+int mpmc_field_axpby(const int32_t dims[4], int32_t prec, mpmc_shape shape, const double *alpha, const void *x,
+                     const double *beta, void *y, void *stream) {
+    if (!valid_dims(dims) || !valid_shape(shape) || !alpha || !x || !y) return MPMC_EINVAL;
+    if (!valid_prec(prec)) return MPMC_EUNSUPPORTED;
+    return field_axpby_impl(dims, prec, shape, alpha, x, beta, y, stream);
+}
+
+size_t mpmc_field_dot_workspace_size(const int32_t dims[4], mpmc_shape shape) {
+    if (!valid_dims(dims) || !valid_shape(shape)) return 0;
+    return field_dot_ws_bytes(dims, shape);
+}
+
+int mpmc_field_dot(const int32_t dims[4], int32_t prec, mpmc_shape shape, const void *x, const void *y, double *out,
+                   void *ws, size_t ws_bytes, void *stream) {
+    if (!valid_dims(dims) || !valid_shape(shape) || !x || !y || !out) return MPMC_EINVAL;
+    if (!valid_prec(prec)) return MPMC_EUNSUPPORTED;
+    MPMC_TRY(check_ws(ws, ws_bytes, field_dot_ws_bytes(dims, shape)));
+    return field_dot_impl(dims, prec, shape, x, y, out, ws, stream);
+}
+
+int mpmc_field_copy_vector(const int32_t dims[4], int32_t prec, mpmc_shape src_shape, const void *src,
+                           int32_t src_index, mpmc_shape dst_shape, void *dst, int32_t dst_index, void *stream) {
+    if (!valid_dims(dims) || !valid_shape(src_shape) || !valid_shape(dst_shape) || !src || !dst) return MPMC_EINVAL;
+    if (!valid_prec(prec)) return MPMC_EUNSUPPORTED;
+    if (src_index < 0 || src_index >= src_shape.nrhs || dst_index < 0 || dst_index >= dst_shape.nrhs) return MPMC_EINVAL;
+    if (src == dst) return MPMC_EINVAL;
+    return field_copy_vector_impl(dims, prec, src_shape, src, src_index, dst_shape, dst, dst_index, stream);
+}
+
 size_t mpmc_poly_workspace_size(const mpmc_lattice *lat, const mpmc_poly *poly, mpmc_shape shape) {
     if (check_lattice(lat) != MPMC_OK || check_poly(poly) != MPMC_OK || !valid_shape(shape)) return 0;
     return poly_ws_bytes(lat->dims, lat->prec, *poly, shape);

@@ -43,6 +43,15 @@ int unpack_fields_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, const
                        void *stream);
 int z4_fill_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, const mpmc_noise &nz, void *field, void *stream);
 
+// field utilities (Krylov set-up)
+int field_axpby_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, const double *alpha, const void *x,
+                     const double *beta, void *y, void *stream);
+size_t field_dot_ws_bytes(const int32_t dims[4], mpmc_shape sh);
+int field_dot_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, const void *x, const void *y, double *out,
+                   void *ws, void *stream);
+int field_copy_vector_impl(const int32_t dims[4], int32_t prec, mpmc_shape ssh, const void *src, int32_t si,
+                           mpmc_shape dsh, void *dst, int32_t di, void *stream);
+
 // deflation
 size_t defl_ws_bytes(const mpmc_lattice &lat, const mpmc_defl &df, mpmc_shape sh);
 int deflate_impl(const mpmc_lattice &lat, const mpmc_defl &df, int32_t mode, mpmc_shape sh, const void *b,

@@ -1,0 +1,171 @@
+"""Per-lattice state and the multilevel sampling loop on the GPU.
+
+A `LatticeRun` owns the device lattice, the polynomial roots and the
+deflation triplets of one workload, builds one `DeviceLevel` per term of the
+multilevel formula (eq. multpolytr, Sec. 3.1) with Monte Carlo deflation on
+the polynomial-difference levels (Sec. 4.1), and draws batches of Z4
+samples through `mpmc_mlmc_level_estimate`.
+
+Levels are numbered from the top (0 = highest degree).  The estimate of a
+level is the accumulator mean plus the exact deflation correction sum_i c_i
+(u_i^H z_i = 1 by the scaling, Sec. 4.1).
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional
+
+import numpy as np
+import torch
+
+import synth
+from synth.configs import LatticeConfig, poly_mvps
+
+from . import _lib as L
+from . import krylov
+
+
+@dataclass
+class LevelState:
+    index: int
+    device: L.DeviceLevel
+    mvps_per_sample: int
+    c: Optional[np.ndarray]
+    acc: torch.Tensor
+    samples: torch.Tensor
+    ws: torch.Tensor
+    drawn: int = 0
+
+
+@dataclass
+class LatticeRun:
+    cfg: LatticeConfig
+    prec: int
+    rb: int
+    dl: L.DeviceLattice
+    roots: krylov.RootSet
+    defl: Optional[krylov.Deflation]
+    levels: List[LevelState] = field(default_factory=list)
+    setup_seconds: float = 0.0
+
+    # -- sampling --------------------------------------------------------
+    def draw(self, level: int, nsamples: int):
+        """Enqueue nsamples more samples of one level (one batch)."""
+        lv = self.levels[level]
+        nz = L.Noise(self.cfg.seed_noise, self.cfg.lattice_id, lv.index, lv.drawn)
+        L.mlmc_level_estimate(self.dl, lv.device, nsamples, self.rb, nz, lv.samples[:nsamples], lv.acc, lv.ws)
+        lv.drawn += nsamples
+
+    def step(self, batch: Optional[Dict[int, int]] = None):
+        """One pass of the hot path: every level draws its configured batch."""
+        for i, lv in enumerate(self.levels):
+            self.draw(i, (batch or {}).get(i, self.cfg.levels[i].samples))
+
+    def reset(self):
+        for lv in self.levels:
+            lv.acc.zero_()
+            lv.drawn = 0
+
+    def estimates(self):
+        """Per-level (estimate, stderr, variance, n) on the host."""
+        out = []
+        for lv in self.levels:
+            a = lv.acc.cpu().numpy()
+            n = a[0]
+            mean = a[1] + 1j * a[2]
+            var = a[3] / (n - 1) if n > 1 else float("nan")
+            corr = complex(np.sum(lv.c)) if lv.c is not None else 0.0
+            out.append(dict(estimate=mean + corr, stderr=float(np.sqrt(var / n)) if n > 1 else float("nan"),
+                            variance=float(var), n=int(n), nonfinite=int(a[4])))
+        return out
+
+    # -- work accounting -------------------------------------------------
+    def bytes_per_step(self) -> int:
+        """Algorithmic HBM bytes of the operator applications of one step."""
+        return sum(lv.mvps_per_sample * launch_bytes(self.dl.V, self.cfg.levels[i].samples, self.prec)
+                   for i, lv in enumerate(self.levels))
+
+    def mvp_rhs_per_step(self) -> int:
+        return sum(lv.mvps_per_sample * self.cfg.levels[i].samples for i, lv in enumerate(self.levels))
+
+
+def launch_bytes(V: int, nrhs: int, prec: int) -> int:
+    """Algorithmic HBM bytes of one operator application to nrhs vectors:
+    read w and write w' (2 x 12 complex per site and vector) and read the
+    links once (4 x 9 complex per site); the noise b of the fused dot is
+    regenerated in registers and costs no traffic."""
+    c = 16 if prec == L.F64 else 8
+    return V * nrhs * 24 * c + V * 36 * c
+
+
+def _device_poly(roots: krylov.RootSet, p) -> L.DevicePoly:
+    if isinstance(p, tuple):
+        raise NotImplementedError("composite levels are built by the caller")
+    return roots.device[p]
+
+
+def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optional[int] = None,
+          arnoldi_m: int = 90, nev: int = 40, verbose: bool = False) -> LatticeRun:
+    """Set up a lattice workload: links, GMRES roots, PP-Arnoldi deflation
+    (FP64 on the GPU) and the level descriptors in precision `prec`."""
+    t0 = time.perf_counter()
+    U = synth.gauge_links(cfg.dims, cfg.eps, cfg.seed_links)
+    canon = torch.from_numpy(U).cuda()
+    V = cfg.volume
+
+    def lattice(p):
+        g = torch.empty(36 * V, dtype=L.complex_dtype(p), device="cuda")
+        L.pack_gauge(cfg.dims, p, canon, g)
+        return L.DeviceLattice(tuple(cfg.dims), cfg.kappa, cfg.antiperiodic_t, p, g)
+
+    dl64 = lattice(L.F64)
+    degrees = sorted({d for lv in cfg.levels for d in (lv.hi, lv.lo) if isinstance(d, int)})
+    start = synth.gaussian_start(cfg.n, cfg.seed_start)
+    roots = krylov.gmres_roots(dl64, degrees, start)
+    defl = None
+    if cfg.k_defl > 0:
+        pd = pin_degree if pin_degree is not None else degrees[len(degrees) // 2]
+        if pd not in roots.device:
+            extra = krylov.gmres_roots(dl64, [pd], start)
+            roots.inv_roots[pd], roots.device[pd] = extra.inv_roots[pd], extra.device[pd]
+        defl = krylov.pp_arnoldi_deflation(dl64, roots.device[pd], start, arnoldi_m, nev, cfg.k_defl)
+    dl = dl64 if prec == L.F64 else lattice(prec)
+    if defl is not None and prec != L.F64:
+        kp = defl.device.kpad
+        canon_v = torch.empty((kp, V, 4, 3), dtype=torch.complex128, device="cuda")
+        L.unpack_fields(cfg.dims, L.F64, defl.device.V, canon_v)
+        Vp = torch.empty((1, 12, V, kp), dtype=L.complex_dtype(prec), device="cuda")
+        L.pack_fields(cfg.dims, prec, canon_v, Vp)    # eigenvectors rounded to the field precision
+        defl.device = L.DeviceDefl(defl.device.k, Vp, defl.device.pair, defl.device.scale, defl.device.hinv)
+    run = LatticeRun(cfg, prec, rb, dl, roots, defl)
+    for i, lv in enumerate(cfg.levels):
+        hi = _device_poly(roots, lv.hi)
+        lo = _device_poly(roots, lv.lo) if lv.lo is not None else None
+        c = None
+        if lv.deflated and defl is not None:
+            c = krylov.newton_value(roots.inv_roots[lv.hi], defl.lam)
+            if lv.lo is not None:
+                c = c - krylov.newton_value(roots.inv_roots[lv.lo], defl.lam)
+        dlev = L.DeviceLevel(L.OP_POLY, hi, L.OP_POLY if lo is not None else L.OP_NONE, lo,
+                             defl.device if c is not None else None, c is not None,
+                             krylov._c(c) if c is not None else None)
+        N = lv.samples
+        ws = L.workspace(L.level_workspace_size(dl, dlev, N, rb))
+        run.levels.append(LevelState(i, dlev, poly_mvps(lv.hi) + poly_mvps(lv.lo), c,
+                                     torch.zeros(8, dtype=torch.float64, device="cuda"),
+                                     torch.empty((N, 6), dtype=torch.float64, device="cuda"), ws))
+    torch.cuda.synchronize()
+    run.setup_seconds = time.perf_counter() - t0
+    if verbose:
+        print(f"setup {cfg.name}: {run.setup_seconds:.1f} s, k_defl={defl.device.k if defl else 0}, "
+              f"GMRES residuals {roots.residual}", flush=True)
+    return run
+
+
+def time_to_error(variances, seconds_per_sample, eps: float) -> float:
+    """Wall time to a combined standard error eps with the optimal sample
+    allocation of multilevel Monte Carlo: T = eps^-2 (sum_l sqrt(V_l t_l))^2
+    (the cost formula eq. mlevcost of Sec. 5 with measured time as cost)."""
+    s = sum(np.sqrt(max(v, 0.0) * t) for v, t in zip(variances, seconds_per_sample))
+    return float(s * s / eps ** 2)
