@@ -128,6 +128,16 @@ const char *mpmc_status_string(int status);
 /* Library version and the gfx target it was built for. */
 const char *mpmc_build_info(void);
 
+/* Process-wide kernel-selection options (set them before enqueueing work;
+ * not synchronised with concurrent calls).
+ *   MPMC_OPT_PLANE_SWEEP  1 (default): scalar-mode single polynomials on a
+ *     lattice whose xyz-plane (Lx*Ly*Lz a multiple of 64, at most 512 sites
+ *     and 160 KiB of LDS at the field precision) run as a t-sweep with one
+ *     workgroup per vector; 0: always use the streaming site-parallel kernel.
+ * Both paths compute the same values up to the order of floating-point sums. */
+enum { MPMC_OPT_PLANE_SWEEP = 1 };
+int mpmc_set_option(int32_t option, int32_t value);
+
 /* ---- layout conversion and noise ------------------------------------- */
 
 /* canon: device complex128 (4, V, 3, 3) = U[mu][s][a][b] -> gauge (lattice

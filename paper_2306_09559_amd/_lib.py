@@ -29,6 +29,7 @@ OK, EINVAL, EUNSUPPORTED, EWORKSPACE, EHIP = 0, -1, -2, -3, -4
 F64, F32 = 0, 1
 DEFL_COEFF, DEFL_RECON, DEFL_PROJECT = 0, 1, 2
 OP_NONE, OP_POLY, OP_DEFLATED_POLY = 0, 1, 2
+OPT_PLANE_SWEEP = 1
 
 c_i32, c_u64, c_f64, c_vp, c_size = ctypes.c_int32, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 
@@ -63,6 +64,7 @@ P = ctypes.POINTER
 _sig = {
     "mpmc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "mpmc_build_info": (ctypes.c_char_p, []),
+    "mpmc_set_option": (ctypes.c_int, [c_i32, c_i32]),
     "mpmc_pack_gauge": (ctypes.c_int, [P(c_i32), c_i32, c_vp, c_vp, c_vp]),
     "mpmc_pack_fields": (ctypes.c_int, [P(c_i32), c_i32, mpmc_shape, c_vp, c_vp, c_vp]),
     "mpmc_unpack_fields": (ctypes.c_int, [P(c_i32), c_i32, mpmc_shape, c_vp, c_vp, c_vp]),
@@ -103,6 +105,10 @@ def status_string(status: int) -> str:
 
 def build_info() -> str:
     return _lib.mpmc_build_info().decode()
+
+
+def set_option(option: int, value: int):
+    _check("mpmc_set_option", _lib.mpmc_set_option(int(option), int(value)))
 
 
 def _check(fn: str, st: int):

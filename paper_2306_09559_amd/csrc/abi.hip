@@ -7,6 +7,8 @@
 
 namespace mpmc {
 
+int g_opt_sweep = 1;
+
 size_t poly_ws_bytes(const int32_t dims[4], int32_t prec, const mpmc_poly &poly, mpmc_shape sh) {
     const size_t fb = align256(field_bytes(dims, prec, sh.nrhs));
     const int V = dims[0] * dims[1] * dims[2] * dims[3];
@@ -105,6 +107,16 @@ const char *mpmc_status_string(int status) {
 }
 
 const char *mpmc_build_info(void) { return "libmpmc 0.1 gfx950"; }
+
+int mpmc_set_option(int32_t option, int32_t value) {
+    switch (option) {
+    case MPMC_OPT_PLANE_SWEEP:
+        if (value != 0 && value != 1) return MPMC_EINVAL;
+        g_opt_sweep = value;
+        return MPMC_OK;
+    default: return MPMC_EUNSUPPORTED;
+    }
+}
 
 int mpmc_pack_gauge(const int32_t dims[4], int32_t prec, const double *canon, void *gauge, void *stream) {
     if (!valid_dims(dims) || !canon || !gauge) return MPMC_EINVAL;

@@ -29,6 +29,16 @@ template <typename T> int wilson_apply_t(const mpmc_lattice &, mpmc_shape, const
 template <typename T>
 int residual_apply_t(const mpmc_lattice &, mpmc_shape, const void *x, const void *b, uint64_t key, uint64_t first,
                      void *out, void *stream);
+// t-sweep Newton steps (plane per workgroup); see sweep.hip
+bool sweep_fits(const mpmc_lattice &lat);
+template <typename T>
+int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, int n, const double *troots, const void *x, bool x_is_noise,
+                   const void *bvec, uint64_t key, uint64_t first, double2 *part, double2 *bhy, void *w0, void *w1,
+                   void *stream);
+
+// process-wide options (mpmc_set_option)
+extern int g_opt_sweep;
+
 template <typename T>
 int poly_apply_t(const mpmc_lattice &, const mpmc_poly &, mpmc_shape, const void *x, const mpmc_noise *noise, void *y,
                  double *bhy, const PolyWs &ws, void *stream);

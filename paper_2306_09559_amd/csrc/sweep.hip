@@ -1,0 +1,481 @@
+// Newton step of a GMRES polynomial (Sec. 3.1) as a t-sweep: one workgroup
+// owns one vector and one whole xyz-plane of the lattice (one thread per
+// (x, y, z)), and marches through t = 0 .. Lt-1.
+//
+//   * The current plane is staged in LDS; the +-x, +-y, +-z neighbours are
+//     read from there (periodic wrap inside the plane).
+//   * The +t neighbour is the next plane, prefetched into registers one
+//     step ahead; the -t term of a site is formed one step early from the
+//     plane below it and carried as a spin-projected half spinor.
+//   * Every spinor of the input is therefore read from HBM once and the
+//     output written once (plus one re-read of plane 0 for the periodic
+//     wrap): the compulsory traffic of the step.
+//
+// The step computes out = (1 - t_j) w + kappa t_j D w and the FP64 partial
+// t_{j+1} b^H out (plus t_0 b^H w on the first step) of the scalar-mode
+// Newton recurrence, exactly as the streaming kernel does; only the order of
+// the floating-point sums inside a site differs.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace mpmc {
+
+template <typename T> struct SweepArgs {
+    int L[4];
+    int P, V;                  // plane sites Lx*Ly*Lz, volume
+    int apbc;
+    const cplx_t<T> *in;       // input field (layout rb_in), unused for noise input
+    int rb_in;
+    cplx_t<T> *out;            // output field, rb = 1
+    const cplx_t<T> *gauge;    // [mu][9][V]
+    const double2 *troots;
+    int j;
+    double kappa;
+    uint64_t key, first;       // noise (input when IN_Z4; dot vector when bvec == nullptr)
+    const cplx_t<T> *bvec;     // dot vector field (layout rb_b), or nullptr
+    int rb_b;
+    double2 *part;             // N partial sums, one per vector
+    double2 *bhy;              // final sums (last step), or nullptr
+    int dot_first;
+};
+
+namespace {
+
+template <typename T> __device__ __forceinline__ cplx_t<T> neg(cplx_t<T> a) { return mk<T>(-a.x, -a.y); }
+
+// Component c of vector r of a batch with block width rb, site s, lives at
+// byte  cbase(r, c) + s * rb * sizeof(C)  where cbase is wavefront-uniform
+// (scalar registers) and the per-site offset fits 32 bits (V * rb * sizeof(C)
+// < 4 GiB is checked on the host).
+template <typename T> struct Plane {
+    const char *base;   // vector r, component 0
+    size_t cstride;     // bytes between components
+    uint32_t sstride;   // bytes between sites
+    __device__ __forceinline__ cplx_t<T> ld(int c, int s) const {
+        return *(const cplx_t<T> *)(base + (size_t)c * cstride + (uint32_t)s * sstride);
+    }
+    __device__ __forceinline__ void st(int c, int s, cplx_t<T> v) const {
+        *(cplx_t<T> *)(const_cast<char *>(base) + (size_t)c * cstride + (uint32_t)s * sstride) = v;
+    }
+};
+
+template <typename T> __device__ __forceinline__ Plane<T> plane_of(const void *f, int r, int V, int rb) {
+    Plane<T> p;
+    const size_t csz = sizeof(cplx_t<T>);
+    p.cstride = (size_t)V * (size_t)rb * csz;
+    p.sstride = (uint32_t)(rb * csz);
+    p.base = (const char *)f + (size_t)(r / rb) * 12 * p.cstride + (size_t)(r % rb) * csz;
+    return p;
+}
+
+template <typename T>
+__device__ __forceinline__ void load_plane_site(const Plane<T> &in, bool z4, uint64_t S, int s, cplx_t<T> (&p)[12]) {
+    if (z4) {
+        const uint32_t codes = z4_site_codes(S, (unsigned)s);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) p[c] = z4_value<T>((codes >> (2 * c)) & 3u);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) p[c] = in.ld(c, s);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_link(const char *g, size_t estride, int site, cplx_t<T> (&U)[9]) {
+    const uint32_t off = (uint32_t)site * (uint32_t)sizeof(cplx_t<T>);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) U[e] = *(const cplx_t<T> *)(g + (size_t)e * estride + off);
+}
+
+// half spinor h (2 x 3) <- U h or U^H h
+template <typename T, bool HERM>
+__device__ __forceinline__ void mul_link(const cplx_t<T> (&U)[9], cplx_t<T> (&h)[2][3]) {
+    cplx_t<T> o[2][3];
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cplx_t<T> t = mk<T>(T(0), T(0));
+#pragma unroll
+            for (int b = 0; b < 3; ++b) t = HERM ? cfmaconj<T>(U[3 * b + a], h[sp][b], t) : cfma<T>(U[3 * a + b], h[sp][b], t);
+            o[sp][a] = t;
+        }
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) h[sp][a] = o[sp][a];
+}
+
+// spin projections (1 -+ g_mu) to a half spinor and the matching
+// reconstruction; DeGrand-Rossi basis (same algebra as the streaming kernel)
+template <typename T, int MU, bool FWD>
+__device__ __forceinline__ void proj(const cplx_t<T> (&p)[12], cplx_t<T> (&h)[2][3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const cplx_t<T> p0 = p[a], p1 = p[3 + a], p2 = p[6 + a], p3 = p[9 + a];
+        if (MU == 0) {
+            h[0][a] = FWD ? cadd<T>(p0, mul_mi<T>(p3)) : cadd<T>(p0, mul_i<T>(p3));
+            h[1][a] = FWD ? cadd<T>(p1, mul_mi<T>(p2)) : cadd<T>(p1, mul_i<T>(p2));
+        } else if (MU == 1) {
+            h[0][a] = FWD ? cadd<T>(p0, p3) : csub<T>(p0, p3);
+            h[1][a] = FWD ? csub<T>(p1, p2) : cadd<T>(p1, p2);
+        } else if (MU == 2) {
+            h[0][a] = FWD ? cadd<T>(p0, mul_mi<T>(p2)) : cadd<T>(p0, mul_i<T>(p2));
+            h[1][a] = FWD ? cadd<T>(p1, mul_i<T>(p3)) : cadd<T>(p1, mul_mi<T>(p3));
+        } else {
+            h[0][a] = FWD ? csub<T>(p0, p2) : cadd<T>(p0, p2);
+            h[1][a] = FWD ? csub<T>(p1, p3) : cadd<T>(p1, p3);
+        }
+    }
+}
+
+template <typename T, int MU, bool FWD>
+__device__ __forceinline__ void recon(const cplx_t<T> (&h)[2][3], cplx_t<T> (&acc)[12]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const cplx_t<T> h0 = h[0][a], h1 = h[1][a];
+        acc[a] = cadd<T>(acc[a], h0);
+        acc[3 + a] = cadd<T>(acc[3 + a], h1);
+        cplx_t<T> r2, r3;
+        if (MU == 0) {
+            r2 = FWD ? mul_i<T>(h1) : mul_mi<T>(h1);
+            r3 = FWD ? mul_i<T>(h0) : mul_mi<T>(h0);
+        } else if (MU == 1) {
+            r2 = FWD ? neg<T>(h1) : h1;
+            r3 = FWD ? h0 : neg<T>(h0);
+        } else if (MU == 2) {
+            r2 = FWD ? mul_i<T>(h0) : mul_mi<T>(h0);
+            r3 = FWD ? mul_mi<T>(h1) : mul_i<T>(h1);
+        } else {
+            r2 = FWD ? neg<T>(h0) : h0;
+            r3 = FWD ? neg<T>(h1) : h1;
+        }
+        acc[6 + a] = cadd<T>(acc[6 + a], r2);
+        acc[9 + a] = cadd<T>(acc[9 + a], r3);
+    }
+}
+
+// one spatial hop read from the LDS plane (component-major: lds[c*P + q])
+// projection read straight from the LDS plane, one spin pair at a time
+template <typename T, int MU, bool FWD>
+__device__ __forceinline__ void proj_lds(const cplx_t<T> *lds, int P, int q, cplx_t<T> (&h)[2][3]) {
+    // partner spin of spin 0 and of spin 1 under g_mu
+    constexpr int k0 = (MU == 0 || MU == 1) ? 3 : 2;
+    constexpr int k1 = (MU == 0 || MU == 1) ? 2 : 3;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const cplx_t<T> p0 = lds[a * P + q], pk = lds[(3 * k0 + a) * P + q];
+        cplx_t<T> v[12];
+        v[a] = p0;
+        v[3 * k0 + a] = pk;
+        cplx_t<T> hh[2][3];
+        // only h[0][a] is formed from this pair
+        if (MU == 0) hh[0][a] = FWD ? cadd<T>(p0, mul_mi<T>(pk)) : cadd<T>(p0, mul_i<T>(pk));
+        else if (MU == 1) hh[0][a] = FWD ? cadd<T>(p0, pk) : csub<T>(p0, pk);
+        else if (MU == 2) hh[0][a] = FWD ? cadd<T>(p0, mul_mi<T>(pk)) : cadd<T>(p0, mul_i<T>(pk));
+        else hh[0][a] = FWD ? csub<T>(p0, pk) : cadd<T>(p0, pk);
+        h[0][a] = hh[0][a];
+        (void)v;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const cplx_t<T> p1 = lds[(3 + a) * P + q], pk = lds[(3 * k1 + a) * P + q];
+        if (MU == 0) h[1][a] = FWD ? cadd<T>(p1, mul_mi<T>(pk)) : cadd<T>(p1, mul_i<T>(pk));
+        else if (MU == 1) h[1][a] = FWD ? csub<T>(p1, pk) : cadd<T>(p1, pk);
+        else if (MU == 2) h[1][a] = FWD ? cadd<T>(p1, mul_i<T>(pk)) : cadd<T>(p1, mul_mi<T>(pk));
+        else h[1][a] = FWD ? csub<T>(p1, pk) : cadd<T>(p1, pk);
+    }
+}
+
+// accumulate the reconstruction of colour a of the rotated half spinor (g0, g1)
+template <typename T, int MU, bool FWD>
+__device__ __forceinline__ void recon_a(int a, cplx_t<T> g0, cplx_t<T> g1, cplx_t<T> (&acc)[12]) {
+    acc[a] = cadd<T>(acc[a], g0);
+    acc[3 + a] = cadd<T>(acc[3 + a], g1);
+    cplx_t<T> r2, r3;
+    if (MU == 0) {
+        r2 = FWD ? mul_i<T>(g1) : mul_mi<T>(g1);
+        r3 = FWD ? mul_i<T>(g0) : mul_mi<T>(g0);
+    } else if (MU == 1) {
+        r2 = FWD ? neg<T>(g1) : g1;
+        r3 = FWD ? g0 : neg<T>(g0);
+    } else if (MU == 2) {
+        r2 = FWD ? mul_i<T>(g0) : mul_mi<T>(g0);
+        r3 = FWD ? mul_mi<T>(g1) : mul_i<T>(g1);
+    } else {
+        r2 = FWD ? neg<T>(g0) : g0;
+        r3 = FWD ? neg<T>(g1) : g1;
+    }
+    acc[6 + a] = cadd<T>(acc[6 + a], r2);
+    acc[9 + a] = cadd<T>(acc[9 + a], r3);
+}
+
+// one spatial hop: projection from LDS, then the link applied one output
+// colour at a time (row a of U, or column a of U for U^H) straight into acc
+template <typename T, int MU, bool FWD>
+__device__ __forceinline__ void plane_hop(const cplx_t<T> *lds, int P, int q, const char *glmu, size_t estride,
+                                          int gsite, cplx_t<T> (&acc)[12]) {
+    cplx_t<T> h[2][3];
+    proj_lds<T, MU, FWD>(lds, P, q, h);
+    const uint32_t off = (uint32_t)gsite * (uint32_t)sizeof(cplx_t<T>);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cplx_t<T> u[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const int e = FWD ? 3 * a + b : 3 * b + a;
+            u[b] = *(const cplx_t<T> *)(glmu + (size_t)e * estride + off);
+        }
+        cplx_t<T> g0 = mk<T>(T(0), T(0)), g1 = mk<T>(T(0), T(0));
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            if (FWD) {
+                g0 = cfma<T>(u[b], h[0][b], g0);
+                g1 = cfma<T>(u[b], h[1][b], g1);
+            } else {
+                g0 = cfmaconj<T>(u[b], h[0][b], g0);
+                g1 = cfmaconj<T>(u[b], h[1][b], g1);
+            }
+        }
+        recon_a<T, MU, FWD>(a, g0, g1, acc);
+    }
+}
+
+__device__ __forceinline__ double2 zmul2(double2 a, double2 b) {
+    double2 r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void dot_acc(const cplx_t<T> (&b)[12], const cplx_t<T> (&w)[12], double &re, double &im) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        const double br = (double)b[c].x, bi = (double)b[c].y, wr = (double)w[c].x, wi = (double)w[c].y;
+        re += br * wr + bi * wi;
+        im += br * wi - bi * wr;
+    }
+}
+
+}  // namespace
+
+template <typename T, bool IN_Z4, bool DOT>
+__global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
+    using C = cplx_t<T>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    C *lds = reinterpret_cast<C *>(smem);
+    const int r = (int)blockIdx.x;
+    const int q = (int)threadIdx.x;               // site within the plane
+    const int P = a.P, Lt = a.L[3];
+    const size_t V = (size_t)a.V;
+    const int x = q % a.L[0], y = (q / a.L[0]) % a.L[1], z = q / (a.L[0] * a.L[1]);
+    const int Lx = a.L[0], Ly = a.L[1], Lz = a.L[2];
+    // in-plane neighbours (periodic)
+    const int qxp = x + 1 == Lx ? q - x : q + 1, qxm = x == 0 ? q + Lx - 1 : q - 1;
+    const int qyp = y + 1 == Ly ? q - y * Lx : q + Lx, qym = y == 0 ? q + (Ly - 1) * Lx : q - Lx;
+    const int qzp = z + 1 == Lz ? q - z * Lx * Ly : q + Lx * Ly, qzm = z == 0 ? q + (Lz - 1) * Lx * Ly : q - Lx * Ly;
+    const size_t estride = V * sizeof(C);
+    const char *g0 = (const char *)a.gauge;
+    const char *gx = g0, *gy = g0 + 9 * estride, *gz = g0 + 18 * estride, *gt = g0 + 27 * estride;
+
+    const double2 tj = a.troots[a.j];
+    const T tr = (T)tj.x, ti = (T)tj.y, kp = (T)a.kappa;
+    const C alpha = mk<T>(T(1) - tr, -ti), beta = mk<T>(kp * tr, kp * ti);
+    const uint64_t S = sample_state(a.key, a.first + (uint64_t)r);
+    const Plane<T> inp = plane_of<T>(a.in, r, a.V, a.rb_in);
+    const Plane<T> outp = plane_of<T>(a.out, r, a.V, 1);
+
+    // prologue: -t term of plane 0 from plane Lt-1 (kept as the colour-rotated
+    // half spinor (1 + g_t) U_t^H psi, sign included); cur = plane 0
+    C stash[2][3];
+    {
+        C p[12];
+        load_plane_site<T>(inp, IN_Z4, S, q + (Lt - 1) * P, p);
+        proj<T, 3, false>(p, stash);
+        C U[9];
+        load_link<T>(gt, estride, q + (Lt - 1) * P, U);
+        mul_link<T, true>(U, stash);
+        const T sg = a.apbc ? T(-1) : T(1);
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+            for (int aa = 0; aa < 3; ++aa) stash[sp][aa] = mk<T>(sg * stash[sp][aa].x, sg * stash[sp][aa].y);
+    }
+    C cur[12];
+    load_plane_site<T>(inp, IN_Z4, S, q, cur);
+
+    double dre = 0.0, dim = 0.0, d0re = 0.0, d0im = 0.0;
+    for (int t = 0; t < Lt; ++t) {
+        const int s = q + t * P;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) lds[c * P + q] = cur[c];
+        // prefetch the +t plane (plane 0 again after the last one)
+        const int tn = t + 1 == Lt ? 0 : t + 1;
+        C nxt[12];
+        load_plane_site<T>(inp, IN_Z4, S, q + tn * P, nxt);
+        __syncthreads();
+
+        C acc[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) acc[c] = mk<T>(T(0), T(0));
+        recon<T, 3, false>(stash, acc);
+        // Each hop's addresses pass through an opaque copy so the compiler cannot
+        // issue all six hops' loads up front (that would exhaust the registers).
+#define MPMC_HOP(MU, FWD, QN, GL, SITE)                                \
+        {                                                              \
+            int qq = (QN), ss = (SITE);                                \
+            const char *gg = (GL);                                     \
+            asm volatile("" : "+v"(qq), "+v"(ss), "+s"(gg));           \
+            plane_hop<T, MU, FWD>(lds, P, qq, gg, estride, ss, acc);   \
+        }
+        MPMC_HOP(0, true, qxp, gx, s)
+        MPMC_HOP(0, false, qxm, gx, qxm + t * P)
+        MPMC_HOP(1, true, qyp, gy, s)
+        MPMC_HOP(1, false, qym, gy, qym + t * P)
+        MPMC_HOP(2, true, qzp, gz, s)
+        MPMC_HOP(2, false, qzm, gz, qzm + t * P)
+#undef MPMC_HOP
+
+        // +t hop with U_t(x, t); the same link gives the -t term of (x, t+1)
+        C U[9];
+        load_link<T>(gt, estride, s, U);
+        const T sg = (t + 1 == Lt && a.apbc) ? T(-1) : T(1);
+        {
+            C h[2][3];
+            proj<T, 3, true>(nxt, h);
+            mul_link<T, false>(U, h);
+#pragma unroll
+            for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+                for (int aa = 0; aa < 3; ++aa) h[sp][aa] = mk<T>(sg * h[sp][aa].x, sg * h[sp][aa].y);
+            recon<T, 3, true>(h, acc);
+        }
+        // the current site again, from LDS (not held in registers across the hops)
+#pragma unroll
+        for (int c = 0; c < 12; ++c) cur[c] = lds[c * P + q];
+        proj<T, 3, false>(cur, stash);
+        mul_link<T, true>(U, stash);
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+            for (int aa = 0; aa < 3; ++aa) stash[sp][aa] = mk<T>(sg * stash[sp][aa].x, sg * stash[sp][aa].y);
+
+        C o[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) o[c] = cfma<T>(beta, acc[c], cmul<T>(alpha, cur[c]));
+#pragma unroll
+        for (int c = 0; c < 12; ++c) outp.st(c, s, o[c]);
+        if (DOT) {
+            C b[12];
+            if (a.bvec == nullptr) {
+                const uint32_t codes = z4_site_codes(S, (unsigned)s);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) b[c] = z4_value<T>((codes >> (2 * c)) & 3u);
+            } else {
+                const Plane<T> bp = plane_of<T>(a.bvec, r, a.V, a.rb_b);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) b[c] = bp.ld(c, s);
+            }
+            dot_acc<T>(b, o, dre, dim);
+            if (a.dot_first) dot_acc<T>(b, cur, d0re, d0im);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 12; ++c) cur[c] = nxt[c];
+    }
+
+    if (DOT) {
+        // fixed-order tree over the plane's threads (LDS plane buffer reused)
+        double2 *red = reinterpret_cast<double2 *>(smem);
+        double2 v = zmul2(a.troots[a.j + 1], make_double2(dre, dim));
+        if (a.dot_first) {
+            const double2 v0 = zmul2(tj, make_double2(d0re, d0im));
+            v.x += v0.x;
+            v.y += v0.y;
+        }
+        red[q] = v;
+        __syncthreads();
+        int n = P;
+        while (n > 1) {
+            const int h = (n + 1) >> 1;
+            if (q < n - h) {
+                red[q].x += red[q + h].x;
+                red[q].y += red[q + h].y;
+            }
+            __syncthreads();
+            n = h;
+        }
+        if (q == 0) {
+            double2 tot = red[0];
+            if (!a.dot_first) {
+                tot.x += a.part[r].x;
+                tot.y += a.part[r].y;
+            }
+            a.part[r] = tot;
+            if (a.bhy) a.bhy[r] = tot;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ host side
+
+bool sweep_fits(const mpmc_lattice &lat) {
+    const int P = lat.dims[0] * lat.dims[1] * lat.dims[2];
+    const size_t lds = (size_t)P * 12 * (lat.prec == MPMC_F64 ? 16 : 8);
+    return P >= 64 && P <= 512 && P % 64 == 0 && lds <= 160 * 1024;
+}
+
+template <typename T>
+int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, int n, const double *troots, const void *x, bool x_is_noise,
+                   const void *bvec, uint64_t key, uint64_t first, double2 *part, double2 *bhy, void *w0, void *w1,
+                   void *stream) {
+    SweepArgs<T> a{};
+    for (int d = 0; d < 4; ++d) a.L[d] = lat.dims[d];
+    a.P = lat.dims[0] * lat.dims[1] * lat.dims[2];
+    a.V = a.P * lat.dims[3];
+    a.apbc = lat.antiperiodic_t;
+    a.gauge = (const cplx_t<T> *)lat.gauge;
+    a.troots = (const double2 *)troots;
+    a.kappa = lat.kappa;
+    a.key = key;
+    a.first = first;
+    a.bvec = (const cplx_t<T> *)bvec;
+    a.rb_b = sh.rb;
+    a.part = part;
+    const size_t lds = (size_t)a.P * 12 * sizeof(cplx_t<T>);
+    static bool attr_set[2] = {false, false};
+    auto kz = k_sweep<T, true, true>;
+    auto kf = k_sweep<T, false, true>;
+    const int pi = sizeof(T) == 8 ? 0 : 1;
+    if (!attr_set[pi]) {
+        if (hipFuncSetAttribute((const void *)kz, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
+            return MPMC_EHIP;
+        if (hipFuncSetAttribute((const void *)kf, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
+            return MPMC_EHIP;
+        attr_set[pi] = true;
+    }
+    const int d = n - 1;
+    for (int j = 0; j < d; ++j) {
+        a.j = j;
+        const bool first_step = (j == 0);
+        a.in = (const cplx_t<T> *)(first_step ? x : (((j - 1) % 2 == 0) ? w0 : w1));
+        a.rb_in = first_step ? sh.rb : 1;
+        a.out = (cplx_t<T> *)(j % 2 == 0 ? w0 : w1);
+        a.dot_first = first_step;
+        a.bhy = (j == d - 1) ? bhy : nullptr;
+        if (first_step && x_is_noise)
+            hipLaunchKernelGGL(kz, dim3(sh.nrhs), dim3(a.P), lds, (hipStream_t)stream, a);
+        else
+            hipLaunchKernelGGL(kf, dim3(sh.nrhs), dim3(a.P), lds, (hipStream_t)stream, a);
+        if (hipGetLastError() != hipSuccess) return MPMC_EHIP;
+    }
+    return MPMC_OK;
+}
+
+template int sweep_newton_t<double>(const mpmc_lattice &, mpmc_shape, int, const double *, const void *, bool,
+                                    const void *, uint64_t, uint64_t, double2 *, double2 *, void *, void *, void *);
+template int sweep_newton_t<float>(const mpmc_lattice &, mpmc_shape, int, const double *, const void *, bool,
+                                   const void *, uint64_t, uint64_t, double2 *, double2 *, void *, void *, void *);
+
+}  // namespace mpmc
