@@ -29,7 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL = "k_hop (fused Wilson-Dirac + Newton step + FP64 b^H w partial)"
+KERNEL = "k_sweep (t-sweep Wilson-Dirac + Newton step + FP64 b^H w partial)"
+KERNEL_SOURCES = ("sweep.hip", "common.hpp")
 
 
 def parse():
@@ -40,26 +41,49 @@ def parse():
     ap.add_argument("--prec", choices=["f64", "f32"], default="f64")
     ap.add_argument("--rb", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-bulk (mixed) comparison run")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for the HBM byte counters)")
     return ap.parse_args()
 
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("hop.hip", "common.hpp"):
+    for f in KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, "paper_2306_09559_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
 def measured_traffic(prec: str):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", f"k_hop_c2_{prec}_traffic.json")
+    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), if it
+    was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", f"k_sweep_c2_{prec}_traffic.md")
     if not os.path.exists(p):
         return None
-    d = json.load(open(p))
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    kv = {}
+    for line in open(p):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            kv[k.strip()] = v.strip().strip("`")
+    if kv.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return d.get("bytes_per_launch")
+    try:
+        return int(float(kv["traffic_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
+def calibrate_copy():
+    """A plain device copy of 1 GiB (read 1 GiB, write 1 GiB), three times:
+    the reference that scales the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
 
 
 def cpu_baseline(cfg, run_prec: str):
@@ -98,6 +122,28 @@ def cpu_baseline(cfg, run_prec: str):
                       f"no deflation GEMM, FP64; {dt:.1f} s"}
 
 
+def timed_steps(run, steps, stream):
+    """Run `steps` steps from sample 0 with per-level HIP events on `stream`.
+    Returns (wall seconds, per-level milliseconds summed over steps)."""
+    import numpy as np
+    import torch
+    nl = len(run.levels)
+    run.reset()
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nl)]
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        for i in range(nl):
+            ev[k][i][0].record(stream)
+            run.draw(i, run.cfg.levels[i].samples)
+            ev[k][i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lvl_ms = np.array([sum(ev[k][i][0].elapsed_time(ev[k][i][1]) for k in range(steps)) for i in range(nl)])
+    return wall, lvl_ms
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -119,22 +165,7 @@ def main():
     for _ in range(args.warmup):
         run.step()
     torch.cuda.synchronize()
-    run.reset()
-
-    nl = len(run.levels)
-    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nl)]
-          for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        for i in range(nl):
-            ev[k][i][0].record(stream)
-            run.draw(i, C2.levels[i].samples)
-            ev[k][i][1].record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    lvl_ms = np.array([sum(ev[k][i][0].elapsed_time(ev[k][i][1]) for k in range(args.steps)) for i in range(nl)])
-    wall = t1 - t0
+    wall, lvl_ms = timed_steps(run, args.steps, stream)
     ms_per_step = wall / args.steps * 1e3
     byts = run.bytes_per_step()
     value = byts * args.steps / wall / 1e9
@@ -180,8 +211,35 @@ def main():
         "mvp_rhs_per_step": run.mvp_rhs_per_step(),
         "setup_s": round(run.setup_seconds, 2),
     }
+    if not args.no_mixed and prec == L.F64:
+        # mixed precision: FP32 fields, links, eigenvectors and vector updates,
+        # FP64 roots, dots, samples and accumulators; same set-up, same samples
+        run32 = driver.build(C2, prec=L.F32, rb=args.rb, reuse=run)
+        for _ in range(args.warmup):
+            run32.step()
+        wall32, lvl_ms32 = timed_steps(run32, args.steps, stream)
+        est32 = run32.estimates()
+        targets = driver.level_targets(eps, [e["stderr"] for e in est])
+        ps32 = [lvl_ms32[i] * 1e-3 / (args.steps * C2.levels[i].samples) for i in range(len(run32.levels))]
+        out["mixed"] = {
+            "value": round(run32.bytes_per_step() * args.steps / wall32 / 1e9, 2), "unit": "GB/s",
+            "ms_per_step": round(wall32 / args.steps * 1e3, 3),
+            "time_to_eps_s": round(driver.time_to_error([e["variance"] for e in est32], ps32, eps), 4),
+            "level_error": [float(f"{abs(a['estimate'] - b['estimate']):.4g}") for a, b in zip(est32, est)],
+            "level_target": [round(t, 4) for t in targets],
+            "level_error_over_target": [round(abs(a["estimate"] - b["estimate"]) / t, 5)
+                                        for a, b, t in zip(est32, est, targets)],
+            "level_error_over_stderr": [round(abs(a["estimate"] - b["estimate"]) / b["stderr"], 5)
+                                        for a, b in zip(est32, est)],
+            "bound": "per level |T_mixed - T_fp64| <= 0.1 x the level's standard-error target "
+                     "(eps = 0.0005 V split over the levels), same noise",
+            "bound_met": all(abs(a["estimate"] - b["estimate"]) <= 0.1 * t for a, b, t in zip(est32, est, targets)),
+        }
+        out["time_to_eps_s"] = {"f64": out["time_to_eps_s"], "mixed": out["mixed"]["time_to_eps_s"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(C2, args.prec)
+    if args.calibrate_copy:
+        calibrate_copy()
     print(json.dumps(out), flush=True)
 
 

@@ -34,6 +34,29 @@ template <typename T> __device__ __forceinline__ cplx_t<T> cfma(cplx_t<T> a, cpl
 template <typename T> __device__ __forceinline__ cplx_t<T> cfmaconj(cplx_t<T> a, cplx_t<T> b, cplx_t<T> acc) {
     return mk<T>(acc.x + a.x * b.x + a.y * b.y, acc.y + a.x * b.y - a.y * b.x);
 }
+// Products with a coefficient held in FP64.  The step coefficients of a
+// polynomial (t_j, kappa t_j, phi_j, ...) are never rounded to the field
+// precision: in FP32 mode the entries are widened, combined in FP64 and
+// rounded once, so the polynomial applied is exactly the FP64 one and only
+// the vector entries carry FP32 rounding (a rounded coefficient would shift
+// every sample's result the same way).
+// a * x
+template <typename T> __device__ __forceinline__ cplx_t<T> cmul_d(double2 a, cplx_t<T> x) {
+    const double xr = (double)x.x, xi = (double)x.y;
+    return mk<T>((T)(a.x * xr - a.y * xi), (T)(a.x * xi + a.y * xr));
+}
+// a * x + b * y
+template <typename T>
+__device__ __forceinline__ cplx_t<T> lin2_d(double2 a, cplx_t<T> x, double2 b, cplx_t<T> y) {
+    const double xr = (double)x.x, xi = (double)x.y, yr = (double)y.x, yi = (double)y.y;
+    return mk<T>((T)(a.x * xr - a.y * xi + (b.x * yr - b.y * yi)), (T)(a.x * xi + a.y * xr + (b.x * yi + b.y * yr)));
+}
+// y + a * x
+template <typename T> __device__ __forceinline__ cplx_t<T> axpy_d(double2 a, cplx_t<T> x, cplx_t<T> y) {
+    const double xr = (double)x.x, xi = (double)x.y;
+    return mk<T>((T)((double)y.x + (a.x * xr - a.y * xi)), (T)((double)y.y + (a.x * xi + a.y * xr)));
+}
+
 // i * a and -i * a
 template <typename T> __device__ __forceinline__ cplx_t<T> mul_i(cplx_t<T> a) { return mk<T>(-a.y, a.x); }
 template <typename T> __device__ __forceinline__ cplx_t<T> mul_mi(cplx_t<T> a) { return mk<T>(a.y, -a.x); }

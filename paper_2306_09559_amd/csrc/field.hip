@@ -25,13 +25,7 @@ __global__ void k_axpby(const double2 *alpha, const cplx_t<T> *x, const double2 
     const int r = nbk * rb + j;
     const double2 a = alpha[r];
     const cplx_t<T> xv = x[e];
-    const cplx_t<T> ac = mk<T>((T)a.x, (T)a.y);
-    cplx_t<T> o = cmul<T>(ac, xv);
-    if (beta != nullptr) {
-        const double2 b = beta[r];
-        o = cfma<T>(mk<T>((T)b.x, (T)b.y), y[e], o);
-    }
-    y[e] = o;
+    y[e] = beta != nullptr ? lin2_d<T>(a, xv, beta[r], y[e]) : cmul_d<T>(a, xv);
 }
 
 // partial inner products: workgroup covers 256/rb sites of one RHS block

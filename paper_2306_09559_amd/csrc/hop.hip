@@ -276,18 +276,18 @@ __global__ void __launch_bounds__(kBlock) k_hop(HopArgs<T> a) {
     const Blk<T> in = blk<T>(a.in, nbk, a.g.V, a.rb);
 
     // step coefficients
-    C alpha, beta;
+    // step coefficients, kept in FP64 (applied through cmul_d / lin2_d)
+    double2 alpha, beta;
     double2 t_cur;
     t_cur.x = 0.0;
     t_cur.y = 0.0;
     if (a.troots != nullptr) {
         t_cur = a.troots[a.j];
-        const T tr = (T)t_cur.x, ti = (T)t_cur.y, kp = (T)a.kappa;
-        alpha = mk<T>(T(1) - tr, -ti);
-        beta = mk<T>(kp * tr, kp * ti);
+        alpha = make_double2(1.0 - t_cur.x, -t_cur.y);
+        beta = make_double2(a.kappa * t_cur.x, a.kappa * t_cur.y);
     } else {
-        alpha = mk<T>((T)a.alpha.x, (T)a.alpha.y);
-        beta = mk<T>((T)a.beta.x, (T)a.beta.y);
+        alpha = a.alpha;
+        beta = a.beta;
     }
 
     double2 contrib;
@@ -315,7 +315,7 @@ __global__ void __launch_bounds__(kBlock) k_hop(HopArgs<T> a) {
         load_site<T>(in, a.rb, jr, IN_Z4, S, s, T(1), w);
         C o[12];
 #pragma unroll
-        for (int c = 0; c < 12; ++c) o[c] = cfma<T>(beta, acc[c], cmul<T>(alpha, w[c]));
+        for (int c = 0; c < 12; ++c) o[c] = lin2_d<T>(alpha, w[c], beta, acc[c]);
         if (ADDB) {
             C b[12];
             get_b<T>(a, nbk, jr, S, s, b);
@@ -328,21 +328,16 @@ __global__ void __launch_bounds__(kBlock) k_hop(HopArgs<T> a) {
             const Blk<T> un = blk<T>(a.u_next, nbk, a.g.V, a.rb);
             const Blk<T> y = blk<T>(a.y, nbk, a.g.V, a.rb);
             const double2 ph = a.phi[a.jo];
-            const C phc = mk<T>((T)ph.x, (T)ph.y);
-            const C omp = mk<T>(T(1) - (T)ph.x, -(T)ph.y);
-            C p2c = mk<T>(T(0), T(0));
-            if (a.jo_last) {
-                const double2 p2 = a.phi[a.jo + 1];
-                p2c = mk<T>((T)p2.x, (T)p2.y);
-            }
+            const double2 omp = make_double2(1.0 - ph.x, -ph.y);
+            const double2 p2 = a.jo_last ? a.phi[a.jo + 1] : make_double2(0.0, 0.0);
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
                 const C uo = u.ld(c, off);
-                const C unew = cfma<T>(phc, o[c], cmul<T>(omp, uo));
+                const C unew = lin2_d<T>(ph, o[c], omp, uo);
                 un.st(c, off, unew);
                 C yv = a.y_first ? mk<T>(T(0), T(0)) : y.ld(c, off);
-                yv = cfma<T>(phc, uo, yv);
-                if (a.jo_last) yv = cfma<T>(p2c, unew, yv);
+                yv = axpy_d<T>(ph, uo, yv);
+                if (a.jo_last) yv = axpy_d<T>(p2, unew, yv);
                 y.st(c, off, yv);
             }
         } else {
@@ -351,17 +346,12 @@ __global__ void __launch_bounds__(kBlock) k_hop(HopArgs<T> a) {
             for (int c = 0; c < 12; ++c) out.st(c, off, o[c]);
             if (YACC) {
                 const Blk<T> y = blk<T>(a.y, nbk, a.g.V, a.rb);
-                const C tc = mk<T>((T)t_cur.x, (T)t_cur.y);
-                C tn = mk<T>(T(0), T(0));
-                if (a.y_last) {
-                    const double2 t2 = a.troots[a.j + 1];
-                    tn = mk<T>((T)t2.x, (T)t2.y);
-                }
+                const double2 tn = a.y_last ? a.troots[a.j + 1] : make_double2(0.0, 0.0);
 #pragma unroll
                 for (int c = 0; c < 12; ++c) {
                     C yv = a.y_first ? mk<T>(T(0), T(0)) : y.ld(c, off);
-                    yv = cfma<T>(tc, w[c], yv);
-                    if (a.y_last) yv = cfma<T>(tn, o[c], yv);
+                    yv = axpy_d<T>(t_cur, w[c], yv);
+                    if (a.y_last) yv = axpy_d<T>(tn, o[c], yv);
                     y.st(c, off, yv);
                 }
             }
@@ -424,9 +414,8 @@ __global__ void __launch_bounds__(kBlock) k_scale_dot(HopArgs<T> a) {
         if (a.y != nullptr) {
             const Blk<T> y = blk<T>(a.y, nbk, a.g.V, a.rb);
             const uint32_t off = site_off<T>(s, a.rb, jr);
-            const C tc = mk<T>((T)t0.x, (T)t0.y);
 #pragma unroll
-            for (int c = 0; c < 12; ++c) y.st(c, off, cmul<T>(tc, w[c]));
+            for (int c = 0; c < 12; ++c) y.st(c, off, cmul_d<T>(t0, w[c]));
         }
         if (a.part != nullptr) {
             C b[12];

@@ -260,7 +260,9 @@ __device__ __forceinline__ void dot_acc(const cplx_t<T> (&b)[12], const cplx_t<T
 
 }  // namespace
 
-template <typename T, bool IN_Z4, bool DOT>
+// IN_Z4: the input is the noise itself; FIRST: also accumulate t_0 b^H w
+// (first Newton step); BFIELD: the dot vector b is a field, not the noise
+template <typename T, bool IN_Z4, bool DOT, bool FIRST, bool BFIELD>
 __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
     using C = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -280,14 +282,16 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
     const char *gx = g0, *gy = g0 + 9 * estride, *gz = g0 + 18 * estride, *gt = g0 + 27 * estride;
 
     const double2 tj = a.troots[a.j];
-    const T tr = (T)tj.x, ti = (T)tj.y, kp = (T)a.kappa;
-    const C alpha = mk<T>(T(1) - tr, -ti), beta = mk<T>(kp * tr, kp * ti);
+    const double2 beta = make_double2(a.kappa * tj.x, a.kappa * tj.y);   // kappa t_j
     const uint64_t S = sample_state(a.key, a.first + (uint64_t)r);
     const Plane<T> inp = plane_of<T>(a.in, r, a.V, a.rb_in);
     const Plane<T> outp = plane_of<T>(a.out, r, a.V, 1);
 
-    // prologue: -t term of plane 0 from plane Lt-1 (kept as the colour-rotated
-    // half spinor (1 + g_t) U_t^H psi, sign included); cur = plane 0
+    // The -t term of the next plane is carried in LDS behind the plane (as the
+    // colour-rotated half spinor (1 + g_t) U_t^H psi, sign included), which
+    // keeps it out of the registers during the hops.
+    C *stl = lds + 12 * P;
+    // prologue: -t term of plane 0 from plane Lt-1; cur = plane 0
     C stash[2][3];
     {
         C p[12];
@@ -300,48 +304,96 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
 #pragma unroll
         for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
-            for (int aa = 0; aa < 3; ++aa) stash[sp][aa] = mk<T>(sg * stash[sp][aa].x, sg * stash[sp][aa].y);
+            for (int aa = 0; aa < 3; ++aa) stl[(sp * 3 + aa) * P + q] = mk<T>(sg * stash[sp][aa].x, sg * stash[sp][aa].y);
     }
     C cur[12];
     load_plane_site<T>(inp, IN_Z4, S, q, cur);
 
+    // out = alpha w + beta D w is formed as beta * ((alpha/beta) w + D w): the
+    // current spinor then enters the accumulator at the start of the step and
+    // is dead during the hops (beta = kappa t_j is never 0 for finite roots)
+    double2 aob;
+    {
+        // (1 - t) / (kappa t) = (1 - t) conj(t) / (kappa |t|^2)
+        const double den = a.kappa * (tj.x * tj.x + tj.y * tj.y);
+        const double ar = 1.0 - tj.x, ai = -tj.y;
+        aob.x = (ar * tj.x + ai * tj.y) / den;
+        aob.y = (ai * tj.x - ar * tj.y) / den;
+    }
+
     double dre = 0.0, dim = 0.0, d0re = 0.0, d0im = 0.0;
     for (int t = 0; t < Lt; ++t) {
         const int s = q + t * P;
+        const T sg = (t + 1 == Lt && a.apbc) ? T(-1) : T(1);
 #pragma unroll
         for (int c = 0; c < 12; ++c) lds[c * P + q] = cur[c];
+        // accumulator: (alpha/beta) w + the -t term carried from plane t-1
+        C acc[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) acc[c] = cmul_d<T>(aob, cur[c]);
+        {
+            C st[2][3];
+#pragma unroll
+            for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+                for (int aa = 0; aa < 3; ++aa) st[sp][aa] = stl[(sp * 3 + aa) * P + q];
+            recon<T, 3, false>(st, acc);
+        }
+        // the -t term of (x, t+1): (1 + g_t) U_t(x, t)^H w(x, t)
+        {
+            C U[9];
+            C st[2][3];
+            load_link<T>(gt, estride, s, U);
+            proj<T, 3, false>(cur, st);
+            mul_link<T, true>(U, st);
+#pragma unroll
+            for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+                for (int aa = 0; aa < 3; ++aa) stl[(sp * 3 + aa) * P + q] = mk<T>(sg * st[sp][aa].x, sg * st[sp][aa].y);
+        }
+        if (DOT && FIRST) {
+            C b[12];
+            if (!BFIELD) {
+                const uint32_t codes = z4_site_codes(S, (unsigned)s);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) b[c] = z4_value<T>((codes >> (2 * c)) & 3u);
+            } else {
+                const Plane<T> bp = plane_of<T>(a.bvec, r, a.V, a.rb_b);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) b[c] = bp.ld(c, s);
+            }
+            dot_acc<T>(b, cur, d0re, d0im);
+        }
         // prefetch the +t plane (plane 0 again after the last one)
         const int tn = t + 1 == Lt ? 0 : t + 1;
         C nxt[12];
         load_plane_site<T>(inp, IN_Z4, S, q + tn * P, nxt);
         __syncthreads();
 
-        C acc[12];
-#pragma unroll
-        for (int c = 0; c < 12; ++c) acc[c] = mk<T>(T(0), T(0));
-        recon<T, 3, false>(stash, acc);
-        // Each hop's addresses pass through an opaque copy so the compiler cannot
-        // issue all six hops' loads up front (that would exhaust the registers).
-#define MPMC_HOP(MU, FWD, QN, GL, SITE)                                \
-        {                                                              \
-            int qq = (QN), ss = (SITE);                                \
-            const char *gg = (GL);                                     \
-            asm volatile("" : "+v"(qq), "+v"(ss), "+s"(gg));           \
-            plane_hop<T, MU, FWD>(lds, P, qq, gg, estride, ss, acc);   \
+        // The six spatial hops run as a rolled loop with opaque copies of the
+        // loop-invariant inputs: the compiler can then neither interleave the
+        // hops nor hoist their addresses, which bounds the live registers.
+#pragma nounroll
+        for (int k = 0; k < 6; ++k) {
+            int qn = k == 0 ? qxp : k == 1 ? qxm : k == 2 ? qyp : k == 3 ? qym : k == 4 ? qzp : qzm;
+            int gs = (k & 1) ? qn + t * P : s;
+            const char *gg = k < 2 ? gx : k < 4 ? gy : gz;
+            asm volatile("" : "+v"(qn), "+v"(gs), "+s"(gg));
+            switch (k) {
+            case 0: plane_hop<T, 0, true>(lds, P, qn, gg, estride, gs, acc); break;
+            case 1: plane_hop<T, 0, false>(lds, P, qn, gg, estride, gs, acc); break;
+            case 2: plane_hop<T, 1, true>(lds, P, qn, gg, estride, gs, acc); break;
+            case 3: plane_hop<T, 1, false>(lds, P, qn, gg, estride, gs, acc); break;
+            case 4: plane_hop<T, 2, true>(lds, P, qn, gg, estride, gs, acc); break;
+            default: plane_hop<T, 2, false>(lds, P, qn, gg, estride, gs, acc); break;
+            }
         }
-        MPMC_HOP(0, true, qxp, gx, s)
-        MPMC_HOP(0, false, qxm, gx, qxm + t * P)
-        MPMC_HOP(1, true, qyp, gy, s)
-        MPMC_HOP(1, false, qym, gy, qym + t * P)
-        MPMC_HOP(2, true, qzp, gz, s)
-        MPMC_HOP(2, false, qzm, gz, qzm + t * P)
-#undef MPMC_HOP
-
-        // +t hop with U_t(x, t); the same link gives the -t term of (x, t+1)
-        C U[9];
-        load_link<T>(gt, estride, s, U);
-        const T sg = (t + 1 == Lt && a.apbc) ? T(-1) : T(1);
+        // +t hop: (1 - g_t) U_t(x, t) w(x, t+1)
         {
+            C U[9];
+            int ss = s;
+            asm volatile("" : "+v"(ss));
+            load_link<T>(gt, estride, ss, U);
             C h[2][3];
             proj<T, 3, true>(nxt, h);
             mul_link<T, false>(U, h);
@@ -351,24 +403,14 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
                 for (int aa = 0; aa < 3; ++aa) h[sp][aa] = mk<T>(sg * h[sp][aa].x, sg * h[sp][aa].y);
             recon<T, 3, true>(h, acc);
         }
-        // the current site again, from LDS (not held in registers across the hops)
 #pragma unroll
-        for (int c = 0; c < 12; ++c) cur[c] = lds[c * P + q];
-        proj<T, 3, false>(cur, stash);
-        mul_link<T, true>(U, stash);
-#pragma unroll
-        for (int sp = 0; sp < 2; ++sp)
-#pragma unroll
-            for (int aa = 0; aa < 3; ++aa) stash[sp][aa] = mk<T>(sg * stash[sp][aa].x, sg * stash[sp][aa].y);
-
-        C o[12];
-#pragma unroll
-        for (int c = 0; c < 12; ++c) o[c] = cfma<T>(beta, acc[c], cmul<T>(alpha, cur[c]));
-#pragma unroll
-        for (int c = 0; c < 12; ++c) outp.st(c, s, o[c]);
+        for (int c = 0; c < 12; ++c) {
+            acc[c] = cmul_d<T>(beta, acc[c]);
+            outp.st(c, s, acc[c]);
+        }
         if (DOT) {
             C b[12];
-            if (a.bvec == nullptr) {
+            if (!BFIELD) {
                 const uint32_t codes = z4_site_codes(S, (unsigned)s);
 #pragma unroll
                 for (int c = 0; c < 12; ++c) b[c] = z4_value<T>((codes >> (2 * c)) & 3u);
@@ -377,8 +419,7 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
 #pragma unroll
                 for (int c = 0; c < 12; ++c) b[c] = bp.ld(c, s);
             }
-            dot_acc<T>(b, o, dre, dim);
-            if (a.dot_first) dot_acc<T>(b, cur, d0re, d0im);
+            dot_acc<T>(b, acc, dre, dim);
         }
         __syncthreads();
 #pragma unroll
@@ -389,7 +430,7 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
         // fixed-order tree over the plane's threads (LDS plane buffer reused)
         double2 *red = reinterpret_cast<double2 *>(smem);
         double2 v = zmul2(a.troots[a.j + 1], make_double2(dre, dim));
-        if (a.dot_first) {
+        if (FIRST) {
             const double2 v0 = zmul2(tj, make_double2(d0re, d0im));
             v.x += v0.x;
             v.y += v0.y;
@@ -408,7 +449,7 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
         }
         if (q == 0) {
             double2 tot = red[0];
-            if (!a.dot_first) {
+            if (!FIRST) {
                 tot.x += a.part[r].x;
                 tot.y += a.part[r].y;
             }
@@ -422,7 +463,7 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
 
 bool sweep_fits(const mpmc_lattice &lat) {
     const int P = lat.dims[0] * lat.dims[1] * lat.dims[2];
-    const size_t lds = (size_t)P * 12 * (lat.prec == MPMC_F64 ? 16 : 8);
+    const size_t lds = (size_t)P * 18 * (lat.prec == MPMC_F64 ? 16 : 8);   // plane + carried half spinors
     return P >= 64 && P <= 512 && P % 64 == 0 && lds <= 160 * 1024;
 }
 
@@ -443,18 +484,25 @@ int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, int n, const double *
     a.bvec = (const cplx_t<T> *)bvec;
     a.rb_b = sh.rb;
     a.part = part;
-    const size_t lds = (size_t)a.P * 12 * sizeof(cplx_t<T>);
+    const size_t lds = (size_t)a.P * 18 * sizeof(cplx_t<T>);
+    // kernels of this precision: (noise input, first), (field, first), (field, later),
+    // each with the dot vector as noise or as a field
+    const void *kern[2][3] = {
+        {(const void *)k_sweep<T, true, true, true, false>, (const void *)k_sweep<T, false, true, true, false>,
+         (const void *)k_sweep<T, false, true, false, false>},
+        {(const void *)k_sweep<T, true, true, true, true>, (const void *)k_sweep<T, false, true, true, true>,
+         (const void *)k_sweep<T, false, true, false, true>}};
     static bool attr_set[2] = {false, false};
-    auto kz = k_sweep<T, true, true>;
-    auto kf = k_sweep<T, false, true>;
     const int pi = sizeof(T) == 8 ? 0 : 1;
     if (!attr_set[pi]) {
-        if (hipFuncSetAttribute((const void *)kz, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
-            return MPMC_EHIP;
-        if (hipFuncSetAttribute((const void *)kf, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
-            return MPMC_EHIP;
+        for (int bf = 0; bf < 2; ++bf)
+            for (int v = 0; v < 3; ++v)
+                if (hipFuncSetAttribute(kern[bf][v], hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) !=
+                    hipSuccess)
+                    return MPMC_EHIP;
         attr_set[pi] = true;
     }
+    const int bf = bvec != nullptr ? 1 : 0;
     const int d = n - 1;
     for (int j = 0; j < d; ++j) {
         a.j = j;
@@ -464,10 +512,10 @@ int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, int n, const double *
         a.out = (cplx_t<T> *)(j % 2 == 0 ? w0 : w1);
         a.dot_first = first_step;
         a.bhy = (j == d - 1) ? bhy : nullptr;
-        if (first_step && x_is_noise)
-            hipLaunchKernelGGL(kz, dim3(sh.nrhs), dim3(a.P), lds, (hipStream_t)stream, a);
-        else
-            hipLaunchKernelGGL(kf, dim3(sh.nrhs), dim3(a.P), lds, (hipStream_t)stream, a);
+        const int v = first_step ? (x_is_noise ? 0 : 1) : 2;
+        void *args[] = {&a};
+        if (hipLaunchKernel(kern[bf][v], dim3(sh.nrhs), dim3(a.P), args, lds, (hipStream_t)stream) != hipSuccess)
+            return MPMC_EHIP;
         if (hipGetLastError() != hipSuccess) return MPMC_EHIP;
     }
     return MPMC_OK;

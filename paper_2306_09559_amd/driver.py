@@ -48,6 +48,7 @@ class LatticeRun:
     defl: Optional[krylov.Deflation]
     levels: List[LevelState] = field(default_factory=list)
     setup_seconds: float = 0.0
+    defl64_V: Optional[torch.Tensor] = None     # FP64 eigenvectors of the set-up
 
     # -- sampling --------------------------------------------------------
     def draw(self, level: int, nsamples: int):
@@ -106,9 +107,12 @@ def _device_poly(roots: krylov.RootSet, p) -> L.DevicePoly:
 
 
 def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optional[int] = None,
-          arnoldi_m: int = 90, nev: int = 40, verbose: bool = False) -> LatticeRun:
+          arnoldi_m: int = 90, nev: int = 40, verbose: bool = False,
+          reuse: Optional["LatticeRun"] = None) -> LatticeRun:
     """Set up a lattice workload: links, GMRES roots, PP-Arnoldi deflation
-    (FP64 on the GPU) and the level descriptors in precision `prec`."""
+    (FP64 on the GPU) and the level descriptors in precision `prec`.  With
+    `reuse`, the roots and eigen-triplets of an earlier set-up of the same
+    workload are taken over (the set-up is always FP64)."""
     t0 = time.perf_counter()
     U = synth.gauge_links(cfg.dims, cfg.eps, cfg.seed_links)
     canon = torch.from_numpy(U).cuda()
@@ -119,18 +123,29 @@ def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optio
         L.pack_gauge(cfg.dims, p, canon, g)
         return L.DeviceLattice(tuple(cfg.dims), cfg.kappa, cfg.antiperiodic_t, p, g)
 
-    dl64 = lattice(L.F64)
     degrees = sorted({d for lv in cfg.levels for d in (lv.hi, lv.lo) if isinstance(d, int)})
-    start = synth.gaussian_start(cfg.n, cfg.seed_start)
-    roots = krylov.gmres_roots(dl64, degrees, start)
-    defl = None
-    if cfg.k_defl > 0:
-        pd = pin_degree if pin_degree is not None else degrees[len(degrees) // 2]
-        if pd not in roots.device:
-            extra = krylov.gmres_roots(dl64, [pd], start)
-            roots.inv_roots[pd], roots.device[pd] = extra.inv_roots[pd], extra.device[pd]
-        defl = krylov.pp_arnoldi_deflation(dl64, roots.device[pd], start, arnoldi_m, nev, cfg.k_defl)
-    dl = dl64 if prec == L.F64 else lattice(prec)
+    if reuse is not None:
+        roots = reuse.roots
+        defl = None
+        if reuse.defl is not None:
+            d0 = reuse.defl
+            defl = krylov.Deflation(L.DeviceDefl(d0.device.k, reuse.defl64_V, d0.device.pair, d0.device.scale,
+                                                 d0.device.hinv), d0.lam, d0.pair, d0.res_right, d0.res_left,
+                                    d0.candidates)
+        dl64 = None
+    else:
+        dl64 = lattice(L.F64)
+        start = synth.gaussian_start(cfg.n, cfg.seed_start)
+        roots = krylov.gmres_roots(dl64, degrees, start)
+        defl = None
+        if cfg.k_defl > 0:
+            pd = pin_degree if pin_degree is not None else degrees[len(degrees) // 2]
+            if pd not in roots.device:
+                extra = krylov.gmres_roots(dl64, [pd], start)
+                roots.inv_roots[pd], roots.device[pd] = extra.inv_roots[pd], extra.device[pd]
+            defl = krylov.pp_arnoldi_deflation(dl64, roots.device[pd], start, arnoldi_m, nev, cfg.k_defl)
+    defl64_V = defl.device.V if defl is not None else None
+    dl = dl64 if (prec == L.F64 and dl64 is not None) else lattice(prec)
     if defl is not None and prec != L.F64:
         kp = defl.device.kpad
         canon_v = torch.empty((kp, V, 4, 3), dtype=torch.complex128, device="cuda")
@@ -139,6 +154,7 @@ def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optio
         L.pack_fields(cfg.dims, prec, canon_v, Vp)    # eigenvectors rounded to the field precision
         defl.device = L.DeviceDefl(defl.device.k, Vp, defl.device.pair, defl.device.scale, defl.device.hinv)
     run = LatticeRun(cfg, prec, rb, dl, roots, defl)
+    run.defl64_V = defl64_V
     for i, lv in enumerate(cfg.levels):
         hi = _device_poly(roots, lv.hi)
         lo = _device_poly(roots, lv.lo) if lv.lo is not None else None
@@ -169,3 +185,17 @@ def time_to_error(variances, seconds_per_sample, eps: float) -> float:
     (the cost formula eq. mlevcost of Sec. 5 with measured time as cost)."""
     s = sum(np.sqrt(max(v, 0.0) * t) for v, t in zip(variances, seconds_per_sample))
     return float(s * s / eps ** 2)
+
+
+def level_targets(eps: float, stderrs) -> List[float]:
+    """Standard-error targets of the levels, top first, for a total error eps
+    (Sec. 5 step 3): level l gets sqrt(eps^2 - e^2) / sqrt(L - l), e^2 the
+    summed squared standard errors of the levels before it.  With three
+    levels this is eps/sqrt(3), then sqrt(eps^2 - e_1^2)/sqrt(2), then
+    sqrt(eps^2 - e_1^2 - e_2^2)."""
+    nl = len(stderrs)
+    out, e2 = [], 0.0
+    for l in range(nl):
+        out.append(float(np.sqrt(max(eps * eps - e2, 0.0)) / np.sqrt(nl - l)))
+        e2 += float(stderrs[l]) ** 2
+    return out

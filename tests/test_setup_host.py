@@ -58,3 +58,16 @@ def test_gmres_residual_matches_oracle(pk, m):
     H = _hess(15, m + 7)
     _, res = okr.gmres_ls(H, 2.5, m)
     assert pk.gmres_residual(H, 2.5, m) == pytest.approx(res, rel=1e-10)
+
+
+def test_level_targets_match_oracle(pk):
+    """The driver's split of eps over the levels equals the oracle's three
+    targets of Sec. 5 step 3, and the targets of a spent budget are zero."""
+    from paper_2306_09559_amd import driver
+    from oracle import estimator
+    for eps, errs in ((2.048, [0.3, 0.5, 0.1]), (1.0, [0.0, 0.0, 0.0]), (0.5, [0.45, 0.3, 0.2])):
+        got = driver.level_targets(eps, errs)
+        assert np.allclose(got, estimator.level_tolerances(eps, errs), rtol=1e-15, atol=0)
+    # two levels: eps/sqrt(2), then what the first left
+    assert np.allclose(driver.level_targets(1.0, [0.6, 0.1]), [1 / np.sqrt(2), 0.8])
+    assert driver.level_targets(1.0, [1.5, 0.1])[1] == 0.0
