@@ -21,9 +21,11 @@
  *            The paper names the quenched Wilson-Dirac matrix (Sec. 5,
  *            Example 2); this hopping-parameter form is the reading used.
  * Precision  MPMC_F64: fields, links and eigenvectors are complex128.
- *            MPMC_F32: they are complex64; inverse roots are rounded to FP32
- *            for vector updates, while every dot product, sample value,
- *            deflation coefficient and accumulator stays FP64.
+ *            MPMC_F32: they are complex64.  Step coefficients (inverse
+ *            roots, kappa t_j, axpby coefficients) stay FP64: the entries of
+ *            a vector update are widened, combined in FP64 and rounded once,
+ *            so the polynomial applied is the FP64 one.  Every dot product,
+ *            sample value, deflation coefficient and accumulator is FP64.
  * Field      a batch of N vectors in "field layout" with RHS block width rb
  *            (a power of two, 1..256, dividing N): unknown (spin,colour) =
  *            c in 0..11 of site s of vector r = nb*rb + j is the complex
@@ -159,11 +161,17 @@ int mpmc_z4_fill(const int32_t dims[4], int32_t prec, mpmc_shape shape, const mp
 /* ---- vector utilities for the Krylov set-up (Sec. 5, setup step 2) ------ */
 
 /* y_r = alpha_r x_r + beta_r y_r for every vector r of a batch.
- *   alpha  device, N complex FP64 (rounded to the field precision)
+ *   alpha  device, N complex FP64 (applied in FP64, result rounded once)
  *   beta   device, N complex FP64, or NULL: y_r = alpha_r x_r (y is not read)
  * x and y are device fields of the same shape; x == y is allowed. */
 int mpmc_field_axpby(const int32_t dims[4], int32_t prec, mpmc_shape shape, const double *alpha, const void *x,
                      const double *beta, void *y, void *stream);
+
+/* The same update with x and y in different precisions (x_prec, y_prec):
+ * moves residuals and corrections between the FP64 outer and the FP32 inner
+ * iteration of iterative refinement.  x and y must not overlap. */
+int mpmc_field_axpby_mixed(const int32_t dims[4], mpmc_shape shape, int32_t x_prec, const double *alpha,
+                           const void *x, int32_t y_prec, const double *beta, void *y, void *stream);
 
 size_t mpmc_field_dot_workspace_size(const int32_t dims[4], mpmc_shape shape);
 
@@ -177,6 +185,26 @@ int mpmc_field_dot(const int32_t dims[4], int32_t prec, mpmc_shape shape, const 
  * of an Arnoldi basis held as a batch with nrhs = rb.  src != dst. */
 int mpmc_field_copy_vector(const int32_t dims[4], int32_t prec, mpmc_shape src_shape, const void *src,
                            int32_t src_index, mpmc_shape dst_shape, void *dst, int32_t dst_index, void *stream);
+
+/* ---- Krylov bases of a batch (GMRES cycles, Sec. 2.1, Sec. 5 step 3a) --
+ * A basis is k fields of one shape stored back to back: vector i of the
+ * basis starts N*12*V complex numbers after vector i-1.  Every vector r of
+ * the batch has its own basis (v_0)_r .. (v_{k-1})_r, as in k independent
+ * GMRES runs. */
+
+size_t mpmc_field_block_dot_workspace_size(const int32_t dims[4], mpmc_shape shape, int32_t k);
+
+/* out[i*N + r] = (v_i)_r^H x_r for i < k, accumulated in FP64 in a fixed
+ * order (bitwise reproducible); one pass over x for up to 8 basis vectors.
+ *   basis  device, k fields;  x  device field;  out  device, k x N complex FP64 */
+int mpmc_field_block_dot(const int32_t dims[4], int32_t prec, mpmc_shape shape, int32_t k, const void *basis,
+                         const void *x, double *out, void *ws, size_t ws_bytes, void *stream);
+
+/* y_r = sum_{i<k} coeff[i*N + r] (v_i)_r  (+ y_r when accumulate = 1; y is
+ * not read when accumulate = 0), summed in FP64 and rounded once.
+ *   coeff  device, k x N complex FP64.  y must not overlap the basis. */
+int mpmc_field_block_axpy(const int32_t dims[4], int32_t prec, mpmc_shape shape, int32_t k, const void *basis,
+                          const double *coeff, int32_t accumulate, void *y, void *stream);
 
 /* ---- the operator ------------------------------------------------------ */
 
@@ -229,7 +257,9 @@ int mpmc_deflate_project(const mpmc_lattice *lat, const mpmc_defl *defl, int32_t
 enum {
     MPMC_OP_NONE = 0,            /* operator 0                                          */
     MPMC_OP_POLY = 1,            /* p(A): single or composite polynomial               */
-    MPMC_OP_DEFLATED_POLY = 2    /* Q = V H^{-1} U^H + p(A)(I - A V H^{-1} U^H) (Sec. 4.3) */
+    MPMC_OP_DEFLATED_POLY = 2,   /* Q = V H^{-1} U^H + p(A)(I - A V H^{-1} U^H) (Sec. 4.3) */
+    MPMC_OP_SOLVE = 3            /* A^{-1}: b^H x with x = solve_x, a solution of A x = b
+                                    computed beforehand (Sec. 5 step 3a); kind_hi only */
 };
 
 typedef struct {
@@ -238,6 +268,8 @@ typedef struct {
     const mpmc_defl *defl;       /* eigen-triplets, or NULL; required by DEFLATED_POLY */
     int32_t deflate_samples;     /* 1: subtract sum_i c_i conj(zeta_i) omega_i from each sample */
     const double *c;             /* device, k complex FP64 c_i = f_hi(l_i) - f_lo(l_i) (Sec. 4.1) */
+    const void *solve_x;         /* device field of the batch shape (kind_hi = SOLVE): x_r with
+                                    A x_r = b_r for the level's noise; NULL otherwise */
 } mpmc_level;
 
 size_t mpmc_level_workspace_size(const mpmc_lattice *lat, const mpmc_level *level, mpmc_shape shape);

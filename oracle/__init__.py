@@ -16,6 +16,8 @@ Contents
                  polynomial operator, deflation coefficients
   estimator.py   level samples, level estimates, stopping rule, cost formula
   dense.py       dense matrices and free-field closed forms for tiny lattices
+  solve.py       the top level Tr(A^{-1} - p_1(A)): dense solves, residuals,
+                 top-level samples
 """
 from __future__ import annotations
 

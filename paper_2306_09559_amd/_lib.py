@@ -28,7 +28,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 OK, EINVAL, EUNSUPPORTED, EWORKSPACE, EHIP = 0, -1, -2, -3, -4
 F64, F32 = 0, 1
 DEFL_COEFF, DEFL_RECON, DEFL_PROJECT = 0, 1, 2
-OP_NONE, OP_POLY, OP_DEFLATED_POLY = 0, 1, 2
+OP_NONE, OP_POLY, OP_DEFLATED_POLY, OP_SOLVE = 0, 1, 2, 3
 OPT_PLANE_SWEEP = 1
 
 c_i32, c_u64, c_f64, c_vp, c_size = ctypes.c_int32, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
@@ -57,7 +57,7 @@ class mpmc_defl(ctypes.Structure):
 
 class mpmc_level(ctypes.Structure):
     _fields_ = [("kind_hi", c_i32), ("kind_lo", c_i32), ("poly_hi", mpmc_poly), ("poly_lo", mpmc_poly),
-                ("defl", ctypes.POINTER(mpmc_defl)), ("deflate_samples", c_i32), ("c", c_vp)]
+                ("defl", ctypes.POINTER(mpmc_defl)), ("deflate_samples", c_i32), ("c", c_vp), ("solve_x", c_vp)]
 
 
 P = ctypes.POINTER
@@ -74,6 +74,11 @@ _sig = {
     "mpmc_field_dot": (ctypes.c_int, [P(c_i32), c_i32, mpmc_shape, c_vp, c_vp, c_vp, c_vp, c_size, c_vp]),
     "mpmc_field_copy_vector": (ctypes.c_int, [P(c_i32), c_i32, mpmc_shape, c_vp, c_i32, mpmc_shape, c_vp, c_i32,
                                               c_vp]),
+    "mpmc_field_axpby_mixed": (ctypes.c_int, [P(c_i32), mpmc_shape, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp]),
+    "mpmc_field_block_dot_workspace_size": (c_size, [P(c_i32), mpmc_shape, c_i32]),
+    "mpmc_field_block_dot": (ctypes.c_int, [P(c_i32), c_i32, mpmc_shape, c_i32, c_vp, c_vp, c_vp, c_vp, c_size,
+                                            c_vp]),
+    "mpmc_field_block_axpy": (ctypes.c_int, [P(c_i32), c_i32, mpmc_shape, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp]),
     "mpmc_wilson_apply": (ctypes.c_int, [P(mpmc_lattice), mpmc_shape, c_vp, c_vp, c_vp]),
     "mpmc_poly_workspace_size": (c_size, [P(mpmc_lattice), P(mpmc_poly), mpmc_shape]),
     "mpmc_poly_apply": (ctypes.c_int, [P(mpmc_lattice), P(mpmc_poly), mpmc_shape, c_vp, P(mpmc_noise), c_vp,
@@ -200,19 +205,21 @@ class DeviceDefl:
 @dataclass
 class DeviceLevel:
     kind_hi: int
-    poly_hi: DevicePoly
+    poly_hi: Optional[DevicePoly]       # None for OP_SOLVE
     kind_lo: int = OP_NONE
     poly_lo: Optional[DevicePoly] = None
     defl: Optional[DeviceDefl] = None
     deflate_samples: bool = False
     c: Optional[torch.Tensor] = None   # complex128 (k,)
+    solve_x: Optional[torch.Tensor] = None   # field of the batch (OP_SOLVE)
 
     def cstruct(self):
         dref = self.defl.c() if self.defl is not None else None
+        hi = self.poly_hi.c() if self.poly_hi is not None else mpmc_poly(0, 0, None, None)
         lo = self.poly_lo.c() if self.poly_lo is not None else mpmc_poly(0, 0, None, None)
-        lv = mpmc_level(int(self.kind_hi), int(self.kind_lo), self.poly_hi.c(), lo,
+        lv = mpmc_level(int(self.kind_hi), int(self.kind_lo), hi, lo,
                         ctypes.pointer(dref) if dref is not None else None, int(self.deflate_samples),
-                        None if self.c is None else self.c.data_ptr())
+                        None if self.c is None else self.c.data_ptr(), _ptr(self.solve_x))
         return lv, dref
 
 
@@ -275,6 +282,44 @@ def field_copy_vector(dims, prec: int, src: torch.Tensor, src_index: int, dst: t
     _check("mpmc_field_copy_vector", _lib.mpmc_field_copy_vector(
         _dims(dims), prec, field_shape(src), _ptr(src), int(src_index), field_shape(dst), _ptr(dst),
         int(dst_index), _stream()))
+
+
+def field_axpby_mixed(dims, alpha: torch.Tensor, x: torch.Tensor, beta: Optional[torch.Tensor], y: torch.Tensor):
+    """y_r = alpha_r x_r + beta_r y_r with x, y of different precisions."""
+    xp, yp = _prec_of(x), _prec_of(y)
+    _check("mpmc_field_axpby_mixed", _lib.mpmc_field_axpby_mixed(
+        _dims(dims), field_shape(x), xp, _ptr(alpha), _ptr(x), yp, _ptr(beta), _ptr(y), _stream()))
+
+
+def field_block_dot_workspace_size(dims, nrhs: int, rb: int, k: int) -> int:
+    return int(_lib.mpmc_field_block_dot_workspace_size(_dims(dims), mpmc_shape(nrhs, rb), int(k)))
+
+
+def field_block_dot(dims, prec: int, basis: torch.Tensor, k: int, x: torch.Tensor, out: torch.Tensor,
+                    ws: torch.Tensor):
+    """out[i, r] = (basis_i)_r^H x_r for i < k (basis: (K, nb, 12, V, rb); out complex128 (k, N))."""
+    assert basis.is_contiguous() and basis.shape[0] >= k and basis.shape[1:] == x.shape
+    _check("mpmc_field_block_dot", _lib.mpmc_field_block_dot(
+        _dims(dims), prec, field_shape(x), int(k), _ptr(basis), _ptr(x), _ptr(out), _ptr(ws), ws.numel(),
+        _stream()))
+
+
+def field_block_axpy(dims, prec: int, basis: torch.Tensor, k: int, coeff: torch.Tensor, y: torch.Tensor,
+                     accumulate: bool = True):
+    """y_r = [y_r +] sum_{i<k} coeff[i, r] (basis_i)_r (coeff complex128 (k, N))."""
+    assert basis.is_contiguous() and basis.shape[0] >= k and basis.shape[1:] == y.shape
+    assert coeff.is_contiguous() and coeff.shape[0] >= k
+    _check("mpmc_field_block_axpy", _lib.mpmc_field_block_axpy(
+        _dims(dims), prec, field_shape(y), int(k), _ptr(basis), _ptr(coeff), int(bool(accumulate)), _ptr(y),
+        _stream()))
+
+
+def _prec_of(t: torch.Tensor) -> int:
+    if t.dtype == torch.complex128:
+        return F64
+    if t.dtype == torch.complex64:
+        return F32
+    raise TypeError(f"field dtype {t.dtype}")
 
 
 def wilson_apply(lat: DeviceLattice, x: torch.Tensor, y: torch.Tensor):

@@ -172,6 +172,41 @@ int mpmc_field_dot(const int32_t dims[4], int32_t prec, mpmc_shape shape, const 
     return field_dot_impl(dims, prec, shape, x, y, out, ws, stream);
 }
 
+int mpmc_field_axpby_mixed(const int32_t dims[4], mpmc_shape shape, int32_t x_prec, const double *alpha,
+                           const void *x, int32_t y_prec, const double *beta, void *y, void *stream) {
+    if (!valid_dims(dims) || !valid_shape(shape) || !alpha || !x || !y) return MPMC_EINVAL;
+    if (!valid_prec(x_prec) || !valid_prec(y_prec)) return MPMC_EUNSUPPORTED;
+    // x and y must not overlap (the sizes of the two precisions differ)
+    const size_t xb = field_bytes(dims, x_prec, shape.nrhs), yb = field_bytes(dims, y_prec, shape.nrhs);
+    const char *xc = (const char *)x, *yc = (const char *)y;
+    if (xc < yc + yb && yc < xc + xb) return MPMC_EINVAL;
+    return field_axpby_mixed_impl(dims, shape, x_prec, alpha, x, y_prec, beta, y, stream);
+}
+
+size_t mpmc_field_block_dot_workspace_size(const int32_t dims[4], mpmc_shape shape, int32_t k) {
+    if (!valid_dims(dims) || !valid_shape(shape) || k < 1) return 0;
+    return block_dot_ws_bytes(dims, shape, k);
+}
+
+int mpmc_field_block_dot(const int32_t dims[4], int32_t prec, mpmc_shape shape, int32_t k, const void *basis,
+                         const void *x, double *out, void *ws, size_t ws_bytes, void *stream) {
+    if (!valid_dims(dims) || !valid_shape(shape) || k < 1 || !basis || !x || !out) return MPMC_EINVAL;
+    if (!valid_prec(prec)) return MPMC_EUNSUPPORTED;
+    MPMC_TRY(check_ws(ws, ws_bytes, block_dot_ws_bytes(dims, shape, k)));
+    return field_block_dot_impl(dims, prec, shape, k, basis, x, out, ws, stream);
+}
+
+int mpmc_field_block_axpy(const int32_t dims[4], int32_t prec, mpmc_shape shape, int32_t k, const void *basis,
+                          const double *coeff, int32_t accumulate, void *y, void *stream) {
+    if (!valid_dims(dims) || !valid_shape(shape) || k < 1 || !basis || !coeff || !y) return MPMC_EINVAL;
+    if (accumulate != 0 && accumulate != 1) return MPMC_EINVAL;
+    if (!valid_prec(prec)) return MPMC_EUNSUPPORTED;
+    const size_t fb = field_bytes(dims, prec, shape.nrhs);
+    const char *bc = (const char *)basis, *yc = (const char *)y;
+    if (yc < bc + (size_t)k * fb && bc < yc + fb) return MPMC_EINVAL;
+    return field_block_axpy_impl(dims, prec, shape, k, basis, coeff, accumulate, y, stream);
+}
+
 int mpmc_field_copy_vector(const int32_t dims[4], int32_t prec, mpmc_shape src_shape, const void *src,
                            int32_t src_index, mpmc_shape dst_shape, void *dst, int32_t dst_index, void *stream) {
     if (!valid_dims(dims) || !valid_shape(src_shape) || !valid_shape(dst_shape) || !src || !dst) return MPMC_EINVAL;
@@ -222,7 +257,7 @@ int mpmc_deflate_project(const mpmc_lattice *lat, const mpmc_defl *defl, int32_t
 
 size_t mpmc_level_workspace_size(const mpmc_lattice *lat, const mpmc_level *level, mpmc_shape shape) {
     if (check_lattice(lat) != MPMC_OK || !level || !valid_shape(shape)) return 0;
-    if (check_poly(&level->poly_hi) != MPMC_OK) return 0;
+    if (level->kind_hi != MPMC_OP_SOLVE && check_poly(&level->poly_hi) != MPMC_OK) return 0;
     if (level->kind_lo != MPMC_OP_NONE && check_poly(&level->poly_lo) != MPMC_OK) return 0;
     return level_ws_bytes(*lat, *level, shape);
 }
@@ -234,9 +269,13 @@ int mpmc_mlmc_level_estimate(const mpmc_lattice *lat, const mpmc_level *level, m
     if (!level || !noise || !samples || !acc || !valid_shape(shape)) return MPMC_EINVAL;
     if (!plane_fits(lat->dims, lat->prec, shape)) return MPMC_EINVAL;
     const int kh = level->kind_hi, kl = level->kind_lo;
-    if (kh != MPMC_OP_POLY && kh != MPMC_OP_DEFLATED_POLY) return MPMC_EUNSUPPORTED;
+    if (kh != MPMC_OP_POLY && kh != MPMC_OP_DEFLATED_POLY && kh != MPMC_OP_SOLVE) return MPMC_EUNSUPPORTED;
     if (kl != MPMC_OP_NONE && kl != MPMC_OP_POLY && kl != MPMC_OP_DEFLATED_POLY) return MPMC_EUNSUPPORTED;
-    MPMC_TRY(check_poly(&level->poly_hi));
+    if (kh == MPMC_OP_SOLVE) {
+        if (!level->solve_x) return MPMC_EINVAL;
+    } else {
+        MPMC_TRY(check_poly(&level->poly_hi));
+    }
     if (kl != MPMC_OP_NONE) MPMC_TRY(check_poly(&level->poly_lo));
     const bool proj = kh == MPMC_OP_DEFLATED_POLY || kl == MPMC_OP_DEFLATED_POLY;
     if (proj || level->deflate_samples) MPMC_TRY(check_defl(level->defl, proj));

@@ -82,6 +82,135 @@ __global__ void k_copy_vector(const cplx_t<T> *src, int src_rb, int src_r, cplx_
     dst[fidx(dst_r, c, s, V, dst_rb)] = src[fidx(src_r, c, s, V, src_rb)];
 }
 
+// y = alpha x + beta y across precisions, coefficients applied in FP64
+template <typename TX, typename TY>
+__global__ void k_axpby_mixed(const double2 *alpha, const cplx_t<TX> *x, const double2 *beta, cplx_t<TY> *y, int V,
+                              int rb, int nrhs) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t total = (size_t)nrhs * 12 * (size_t)V;
+    if (e >= total) return;
+    const int j = (int)(e % (size_t)rb);
+    const int r = (int)(e / ((size_t)rb * 12 * (size_t)V)) * rb + j;
+    const double2 a = alpha[r];
+    const double xr = (double)x[e].x, xi = (double)x[e].y;
+    double re = a.x * xr - a.y * xi, im = a.x * xi + a.y * xr;
+    if (beta != nullptr) {
+        const double2 b = beta[r];
+        const double yr = (double)y[e].x, yi = (double)y[e].y;
+        re += b.x * yr - b.y * yi;
+        im += b.x * yi + b.y * yr;
+    }
+    y[e] = mk<TY>((TY)re, (TY)im);
+}
+
+// Block inner products out[i][r] = (v_i)_r^H x_r: a workgroup covers the
+// sites of tiles sb, sb + SB, ... of one RHS block for basis vectors
+// i0 .. i0+7 (blockIdx.y = chunk), holding x in registers while it streams
+// the basis vectors; partials per (RHS block, sb, i) are summed by
+// k_block_dot_finish in a fixed order.
+constexpr int kDotChunk = 8;
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_block_dot(const cplx_t<T> *basis, size_t F, int k, const cplx_t<T> *x,
+                                                      int V, int rb, int SB, double2 *part) {
+    __shared__ double2 red[kBlock];
+    const int spw = kBlock / rb;
+    const int ntiles = (V + spw - 1) / spw;
+    const int nbk = (int)blockIdx.x / SB, sb = (int)blockIdx.x % SB;
+    const int i0 = (int)blockIdx.y * kDotChunk;
+    const int lane = (int)threadIdx.x, jr = lane & (rb - 1), ls = lane / rb;
+    const int r = nbk * rb + jr;
+    double2 acc[kDotChunk];
+#pragma unroll
+    for (int ii = 0; ii < kDotChunk; ++ii) acc[ii] = make_double2(0.0, 0.0);
+    for (int t = sb; t < ntiles; t += SB) {
+        const int s = t * spw + ls;
+        if (s >= V) continue;
+        cplx_t<T> xv[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) xv[c] = x[fidx(r, c, s, V, rb)];
+#pragma unroll
+        for (int ii = 0; ii < kDotChunk; ++ii) {
+            if (i0 + ii < k) {
+                const cplx_t<T> *v = basis + (size_t)(i0 + ii) * F;
+                double re = 0.0, im = 0.0;
+#pragma unroll
+                for (int c = 0; c < 12; ++c) {
+                    const cplx_t<T> vv = v[fidx(r, c, s, V, rb)];
+                    const double vr = (double)vv.x, vi = (double)vv.y, xr = (double)xv[c].x, xi = (double)xv[c].y;
+                    re += vr * xr + vi * xi;
+                    im += vr * xi - vi * xr;
+                }
+                acc[ii].x += re;
+                acc[ii].y += im;
+            }
+        }
+    }
+    for (int ii = 0; ii < kDotChunk; ++ii) {
+        if (i0 + ii >= k) break;   // uniform across the workgroup
+        red[lane] = acc[ii];
+        __syncthreads();
+        for (int stride = spw >> 1; stride > 0; stride >>= 1) {
+            if (ls < stride) {
+                red[lane].x += red[lane + stride * rb].x;
+                red[lane].y += red[lane + stride * rb].y;
+            }
+            __syncthreads();
+        }
+        if (ls == 0) part[(((size_t)nbk * SB + sb) * k + (i0 + ii)) * rb + jr] = red[lane];
+        __syncthreads();
+    }
+}
+
+__global__ void k_block_dot_finish(const double2 *part, int k, int rb, int nrhs, int SB, double2 *out) {
+    const int e = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (e >= k * nrhs) return;
+    const int i = e / nrhs, r = e % nrhs;
+    const int nbk = r / rb, jr = r % rb;
+    double re = 0.0, im = 0.0;
+    for (int sb = 0; sb < SB; ++sb) {
+        const double2 v = part[(((size_t)nbk * SB + sb) * k + i) * rb + jr];
+        re += v.x;
+        im += v.y;
+    }
+    out[e] = make_double2(re, im);
+}
+
+// y = [y +] sum_i coeff[i][r] (v_i)_r, in FP64, rounded once
+template <typename T>
+__global__ void k_block_axpy(const cplx_t<T> *basis, size_t F, int k, const double2 *coeff, int accumulate,
+                             cplx_t<T> *y, int V, int rb, int nrhs) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= F) return;
+    const int j = (int)(e % (size_t)rb);
+    const int r = (int)(e / ((size_t)rb * 12 * (size_t)V)) * rb + j;
+    double re = 0.0, im = 0.0;
+    if (accumulate) {
+        re = (double)y[e].x;
+        im = (double)y[e].y;
+    }
+    for (int i = 0; i < k; ++i) {
+        const double2 a = coeff[(size_t)i * nrhs + r];
+        const cplx_t<T> v = basis[(size_t)i * F + e];
+        const double vr = (double)v.x, vi = (double)v.y;
+        re += a.x * vr - a.y * vi;
+        im += a.x * vi + a.y * vr;
+    }
+    y[e] = mk<T>((T)re, (T)im);
+}
+
+// site-block groups of the block dot: enough workgroups to fill the chip
+int block_dot_groups(int V, mpmc_shape sh, int k) {
+    const int spw = kBlock / sh.rb;
+    const int ntiles = (V + spw - 1) / spw;
+    const int nb = sh.nrhs / sh.rb;
+    const int chunks = (k + kDotChunk - 1) / kDotChunk;
+    int SB = 2048 / (nb * chunks);
+    if (SB < 1) SB = 1;
+    if (SB > ntiles) SB = ntiles;
+    return SB;
+}
+
 inline int st() { return hipGetLastError() == hipSuccess ? MPMC_OK : MPMC_EHIP; }
 
 }  // namespace
@@ -119,6 +248,68 @@ int field_dot_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, const voi
     if (hipGetLastError() != hipSuccess) return MPMC_EHIP;
     hipLaunchKernelGGL(k_dot_finish, dim3((sh.nrhs + 255) / 256), dim3(256), 0, (hipStream_t)stream,
                        (const double2 *)ws, t.nblk, sh.rb, sh.nrhs, (double2 *)out);
+    return st();
+}
+
+int field_axpby_mixed_impl(const int32_t dims[4], mpmc_shape sh, int32_t xp, const double *alpha, const void *x,
+                           int32_t yp, const double *beta, void *y, void *stream) {
+    const int V = dims[0] * dims[1] * dims[2] * dims[3];
+    const size_t total = (size_t)sh.nrhs * 12 * V;
+    const unsigned g = (unsigned)((total + 255) / 256);
+    const double2 *a = (const double2 *)alpha, *b = (const double2 *)beta;
+    hipStream_t s = (hipStream_t)stream;
+    if (xp == MPMC_F64 && yp == MPMC_F64)
+        hipLaunchKernelGGL((k_axpby_mixed<double, double>), dim3(g), dim3(256), 0, s, a, (const double2 *)x, b,
+                           (double2 *)y, V, sh.rb, sh.nrhs);
+    else if (xp == MPMC_F64)
+        hipLaunchKernelGGL((k_axpby_mixed<double, float>), dim3(g), dim3(256), 0, s, a, (const double2 *)x, b,
+                           (float2 *)y, V, sh.rb, sh.nrhs);
+    else if (yp == MPMC_F64)
+        hipLaunchKernelGGL((k_axpby_mixed<float, double>), dim3(g), dim3(256), 0, s, a, (const float2 *)x, b,
+                           (double2 *)y, V, sh.rb, sh.nrhs);
+    else
+        hipLaunchKernelGGL((k_axpby_mixed<float, float>), dim3(g), dim3(256), 0, s, a, (const float2 *)x, b,
+                           (float2 *)y, V, sh.rb, sh.nrhs);
+    return st();
+}
+
+size_t block_dot_ws_bytes(const int32_t dims[4], mpmc_shape sh, int k) {
+    const int V = dims[0] * dims[1] * dims[2] * dims[3];
+    const int SB = block_dot_groups(V, sh, k);
+    return align256((size_t)(sh.nrhs / sh.rb) * SB * (size_t)k * sh.rb * sizeof(double2));
+}
+
+int field_block_dot_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, int k, const void *basis, const void *x,
+                         double *out, void *ws, void *stream) {
+    const int V = dims[0] * dims[1] * dims[2] * dims[3];
+    const size_t F = (size_t)sh.nrhs * 12 * (size_t)V;
+    const int SB = block_dot_groups(V, sh, k);
+    const dim3 grid((unsigned)((sh.nrhs / sh.rb) * SB), (unsigned)((k + kDotChunk - 1) / kDotChunk));
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == MPMC_F64)
+        hipLaunchKernelGGL(k_block_dot<double>, grid, dim3(kBlock), 0, s, (const double2 *)basis, F, k,
+                           (const double2 *)x, V, sh.rb, SB, (double2 *)ws);
+    else
+        hipLaunchKernelGGL(k_block_dot<float>, grid, dim3(kBlock), 0, s, (const float2 *)basis, F, k,
+                           (const float2 *)x, V, sh.rb, SB, (double2 *)ws);
+    if (hipGetLastError() != hipSuccess) return MPMC_EHIP;
+    hipLaunchKernelGGL(k_block_dot_finish, dim3((k * sh.nrhs + 255) / 256), dim3(256), 0, s, (const double2 *)ws, k,
+                       sh.rb, sh.nrhs, SB, (double2 *)out);
+    return st();
+}
+
+int field_block_axpy_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, int k, const void *basis,
+                          const double *coeff, int accumulate, void *y, void *stream) {
+    const int V = dims[0] * dims[1] * dims[2] * dims[3];
+    const size_t F = (size_t)sh.nrhs * 12 * (size_t)V;
+    const unsigned g = (unsigned)((F + 255) / 256);
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == MPMC_F64)
+        hipLaunchKernelGGL(k_block_axpy<double>, dim3(g), dim3(256), 0, s, (const double2 *)basis, F, k,
+                           (const double2 *)coeff, accumulate, (double2 *)y, V, sh.rb, sh.nrhs);
+    else
+        hipLaunchKernelGGL(k_block_axpy<float>, dim3(g), dim3(256), 0, s, (const float2 *)basis, F, k,
+                           (const double2 *)coeff, accumulate, (float2 *)y, V, sh.rb, sh.nrhs);
     return st();
 }
 

@@ -61,6 +61,13 @@ int field_dot_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, const voi
                    void *ws, void *stream);
 int field_copy_vector_impl(const int32_t dims[4], int32_t prec, mpmc_shape ssh, const void *src, int32_t si,
                            mpmc_shape dsh, void *dst, int32_t di, void *stream);
+int field_axpby_mixed_impl(const int32_t dims[4], mpmc_shape sh, int32_t xp, const double *alpha, const void *x,
+                           int32_t yp, const double *beta, void *y, void *stream);
+size_t block_dot_ws_bytes(const int32_t dims[4], mpmc_shape sh, int k);
+int field_block_dot_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, int k, const void *basis, const void *x,
+                         double *out, void *ws, void *stream);
+int field_block_axpy_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, int k, const void *basis,
+                          const double *coeff, int accumulate, void *y, void *stream);
 
 // deflation
 size_t defl_ws_bytes(const mpmc_lattice &lat, const mpmc_defl &df, mpmc_shape sh);

@@ -25,6 +25,33 @@ bool needs_project(const mpmc_level &lv) {
     return lv.kind_hi == MPMC_OP_DEFLATED_POLY || lv.kind_lo == MPMC_OP_DEFLATED_POLY;
 }
 
+// x = A^{-1} b is supplied (MPMC_OP_SOLVE): b^H x is the degree-0 polynomial
+// p = 1 applied to x and dotted against the noise
+__device__ double2 g_unit_root = {1.0, 0.0};
+
+int unit_poly(mpmc_poly *p) {
+    static const double *addr[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return MPMC_EHIP;
+    if (!addr[dev]) {
+        void *a = nullptr;
+        if (hipGetSymbolAddress(&a, HIP_SYMBOL(g_unit_root)) != hipSuccess || !a) return MPMC_EHIP;
+        addr[dev] = (const double *)a;
+    }
+    p->n_in = 1;
+    p->n_out = 0;
+    p->inv_roots_in = addr[dev];
+    p->inv_roots_out = nullptr;
+    return MPMC_OK;
+}
+
+mpmc_poly hi_poly_shape(const mpmc_level &lv) {
+    if (lv.kind_hi != MPMC_OP_SOLVE) return lv.poly_hi;
+    mpmc_poly p{};
+    p.n_in = 1;
+    return p;
+}
+
 size_t carve(const mpmc_lattice &lat, const mpmc_level &lv, mpmc_shape sh, void *base, LevelWs *out) {
     char *w = (char *)base;
     size_t off = 0;
@@ -42,7 +69,7 @@ size_t carve(const mpmc_lattice &lat, const mpmc_level &lv, mpmc_shape sh, void 
     ws.lo = (double *)take((size_t)sh.nrhs * 16);
     if (k) ws.defl = take(defl_ws_bytes(lat, *lv.defl, sh));
     if (needs_project(lv)) ws.rfield = take(field_bytes(lat.dims, lat.prec, sh.nrhs));
-    size_t pb = poly_ws_bytes(lat.dims, lat.prec, lv.poly_hi, sh);
+    size_t pb = poly_ws_bytes(lat.dims, lat.prec, hi_poly_shape(lv), sh);
     if (lv.kind_lo != MPMC_OP_NONE) {
         const size_t pl = poly_ws_bytes(lat.dims, lat.prec, lv.poly_lo, sh);
         pb = pl > pb ? pl : pb;
@@ -150,9 +177,15 @@ int level_t(const mpmc_lattice &lat, const mpmc_level &lv, mpmc_shape sh, const 
                               ws.defl, stream);
         if (st != MPMC_OK) return st;
     }
-    const PolyWs phi = carve_poly_ws(lat.dims, lat.prec, lv.poly_hi, sh, ws.poly);
+    mpmc_poly ph = lv.poly_hi;
     const void *xin_hi = lv.kind_hi == MPMC_OP_DEFLATED_POLY ? ws.rfield : nullptr;
-    st = poly_apply_t<T>(lat, lv.poly_hi, sh, xin_hi, &nz, nullptr, ws.hi, phi, stream);
+    if (lv.kind_hi == MPMC_OP_SOLVE) {
+        st = unit_poly(&ph);
+        if (st != MPMC_OK) return st;
+        xin_hi = lv.solve_x;
+    }
+    const PolyWs phi = carve_poly_ws(lat.dims, lat.prec, ph, sh, ws.poly);
+    st = poly_apply_t<T>(lat, ph, sh, xin_hi, &nz, nullptr, ws.hi, phi, stream);
     if (st != MPMC_OK) return st;
     if (lv.kind_lo != MPMC_OP_NONE) {
         const PolyWs plo = carve_poly_ws(lat.dims, lat.prec, lv.poly_lo, sh, ws.poly);

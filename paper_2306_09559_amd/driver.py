@@ -22,8 +22,11 @@ import torch
 import synth
 from synth.configs import LatticeConfig, poly_mvps
 
+from synth.configs import SOLVE
+
 from . import _lib as L
 from . import krylov
+from .solve import MixedPPGMRES, SolveStats
 
 
 @dataclass
@@ -36,6 +39,13 @@ class LevelState:
     samples: torch.Tensor
     ws: torch.Tensor
     drawn: int = 0
+    # top level Tr(A^{-1} - p_1(A)): the solver and its batch fields
+    solver: Optional[MixedPPGMRES] = None
+    b64: Optional[torch.Tensor] = None
+    x64: Optional[torch.Tensor] = None
+    xl: Optional[torch.Tensor] = None       # x in the level precision
+    last_solve: Optional[SolveStats] = None
+    solve_tol: float = 1e-6
 
 
 @dataclass
@@ -49,12 +59,21 @@ class LatticeRun:
     levels: List[LevelState] = field(default_factory=list)
     setup_seconds: float = 0.0
     defl64_V: Optional[torch.Tensor] = None     # FP64 eigenvectors of the set-up
+    composites: Dict[tuple, krylov.OuterRoots] = field(default_factory=dict)
 
     # -- sampling --------------------------------------------------------
     def draw(self, level: int, nsamples: int):
         """Enqueue nsamples more samples of one level (one batch)."""
         lv = self.levels[level]
         nz = L.Noise(self.cfg.seed_noise, self.cfg.lattice_id, lv.index, lv.drawn)
+        if lv.solver is not None:
+            # x = A^{-1} b for this batch's noise, then b^H x - b^H P_lo b
+            if nsamples != lv.solver.N:
+                raise ValueError(f"level {level} solves batches of {lv.solver.N} vectors")
+            L.z4_fill(self.cfg.dims, L.F64, nz, lv.b64)
+            lv.last_solve = lv.solver.solve(lv.b64, lv.x64, tol=lv.solve_tol)
+            if lv.xl is not lv.x64:
+                L.field_axpby_mixed(self.cfg.dims, lv.solver.ones, lv.x64, None, lv.xl)
         L.mlmc_level_estimate(self.dl, lv.device, nsamples, self.rb, nz, lv.samples[:nsamples], lv.acc, lv.ws)
         lv.drawn += nsamples
 
@@ -100,19 +119,28 @@ def launch_bytes(V: int, nrhs: int, prec: int) -> int:
     return V * nrhs * 24 * c + V * 36 * c
 
 
-def _device_poly(roots: krylov.RootSet, p) -> L.DevicePoly:
+def _device_poly(roots: krylov.RootSet, comps: Dict[tuple, krylov.OuterRoots], p) -> L.DevicePoly:
     if isinstance(p, tuple):
-        raise NotImplementedError("composite levels are built by the caller")
+        return comps[p].device
     return roots.device[p]
+
+
+def _poly_value(roots: krylov.RootSet, comps: Dict[tuple, krylov.OuterRoots], p, lam) -> np.ndarray:
+    if isinstance(p, tuple):
+        return krylov.composite_value(roots.inv_roots[p[0] - 1], comps[p].inv_roots, lam)
+    return krylov.newton_value(roots.inv_roots[p], lam)
 
 
 def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optional[int] = None,
           arnoldi_m: int = 90, nev: int = 40, verbose: bool = False,
-          reuse: Optional["LatticeRun"] = None) -> LatticeRun:
-    """Set up a lattice workload: links, GMRES roots, PP-Arnoldi deflation
-    (FP64 on the GPU) and the level descriptors in precision `prec`.  With
-    `reuse`, the roots and eigen-triplets of an earlier set-up of the same
-    workload are taken over (the set-up is always FP64)."""
+          reuse: Optional["LatticeRun"] = None, gmres_m: int = 30, solve_tol: float = 1e-6) -> LatticeRun:
+    """Set up a lattice workload: links, GMRES roots, PP-Arnoldi deflation,
+    outer roots of composite polynomials (FP64 on the GPU, Sec. 5 setup
+    step 2) and the level descriptors in precision `prec`.  With `reuse`,
+    the roots and eigen-triplets of an earlier set-up of the same workload
+    are taken over (the set-up is always FP64).  A top level with hi = SOLVE
+    gets a deflated PP-GMRES(gmres_m) solver (FP32 inner cycles when prec is
+    FP32, FP64 residual) converging to solve_tol (rtolle)."""
     t0 = time.perf_counter()
     U = synth.gauge_links(cfg.dims, cfg.eps, cfg.seed_links)
     canon = torch.from_numpy(U).cuda()
@@ -123,7 +151,12 @@ def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optio
         L.pack_gauge(cfg.dims, p, canon, g)
         return L.DeviceLattice(tuple(cfg.dims), cfg.kappa, cfg.antiperiodic_t, p, g)
 
-    degrees = sorted({d for lv in cfg.levels for d in (lv.hi, lv.lo) if isinstance(d, int)})
+    polys = [p for lv in cfg.levels for p in (lv.hi, lv.lo) if p is not None and p != SOLVE]
+    comp_keys = sorted({p for p in polys if isinstance(p, tuple)})
+    degrees = sorted({p for p in polys if isinstance(p, int)} | {p[0] - 1 for p in comp_keys})
+    if comp_keys and pin_degree is None:
+        pin_degree = comp_keys[0][0] - 1          # PP(dp_in + 1) of the composite (Sec. 5 step 2b)
+    comps: Dict[tuple, krylov.OuterRoots] = {}
     if reuse is not None:
         roots = reuse.roots
         defl = None
@@ -132,6 +165,7 @@ def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optio
             defl = krylov.Deflation(L.DeviceDefl(d0.device.k, reuse.defl64_V, d0.device.pair, d0.device.scale,
                                                  d0.device.hinv), d0.lam, d0.pair, d0.res_right, d0.res_left,
                                     d0.candidates)
+        comps = reuse.composites
         dl64 = None
     else:
         dl64 = lattice(L.F64)
@@ -144,6 +178,10 @@ def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optio
                 extra = krylov.gmres_roots(dl64, [pd], start)
                 roots.inv_roots[pd], roots.device[pd] = extra.inv_roots[pd], extra.device[pd]
             defl = krylov.pp_arnoldi_deflation(dl64, roots.device[pd], start, arnoldi_m, nev, cfg.k_defl)
+        for key in comp_keys:
+            n_in, n_out = key
+            comps[key] = krylov.pp_outer_roots(dl64, roots.device[n_in - 1], roots.inv_roots[n_in - 1], defl,
+                                               n_out, L.Noise(cfg.seed_noise, cfg.lattice_id, 1000, 0))
     defl64_V = defl.device.V if defl is not None else None
     dl = dl64 if (prec == L.F64 and dl64 is not None) else lattice(prec)
     if defl is not None and prec != L.F64:
@@ -155,18 +193,39 @@ def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optio
         defl.device = L.DeviceDefl(defl.device.k, Vp, defl.device.pair, defl.device.scale, defl.device.hinv)
     run = LatticeRun(cfg, prec, rb, dl, roots, defl)
     run.defl64_V = defl64_V
+    run.composites = comps
     for i, lv in enumerate(cfg.levels):
-        hi = _device_poly(roots, lv.hi)
-        lo = _device_poly(roots, lv.lo) if lv.lo is not None else None
+        N = lv.samples
+        if lv.hi == SOLVE:
+            # Tr(A^{-1} - Q) with Q the deflated p_1 (Sec. 4.3): the deflation is in Q,
+            # so the samples carry no Monte Carlo deflation term
+            lo = _device_poly(roots, comps, lv.lo)
+            kind_lo = L.OP_DEFLATED_POLY if (lv.deflated and defl is not None) else L.OP_POLY
+            x64 = L.empty_field(V, N, rb, L.F64)
+            xl = x64 if prec == L.F64 else L.empty_field(V, N, rb, prec)
+            dlev = L.DeviceLevel(L.OP_SOLVE, None, kind_lo, lo, defl.device if defl is not None else None,
+                                 False, None, xl)
+            n_in = lv.lo[0] if isinstance(lv.lo, tuple) else (pin_degree or lv.lo) + 1
+            l64 = dl64 if dl64 is not None else (dl if prec == L.F64 else lattice(L.F64))
+            dl64 = l64
+            solver = MixedPPGMRES(l64, dl, roots.device[n_in - 1], defl.device if defl is not None else None,
+                                  gmres_m, N, rb)
+            ws = L.workspace(L.level_workspace_size(dl, dlev, N, rb))
+            st = LevelState(i, dlev, poly_mvps(lv.lo), None, torch.zeros(8, dtype=torch.float64, device="cuda"),
+                            torch.empty((N, 6), dtype=torch.float64, device="cuda"), ws, solver=solver,
+                            b64=L.empty_field(V, N, rb, L.F64), x64=x64, xl=xl, solve_tol=solve_tol)
+            run.levels.append(st)
+            continue
+        hi = _device_poly(roots, comps, lv.hi)
+        lo = _device_poly(roots, comps, lv.lo) if lv.lo is not None else None
         c = None
         if lv.deflated and defl is not None:
-            c = krylov.newton_value(roots.inv_roots[lv.hi], defl.lam)
+            c = _poly_value(roots, comps, lv.hi, defl.lam)
             if lv.lo is not None:
-                c = c - krylov.newton_value(roots.inv_roots[lv.lo], defl.lam)
+                c = c - _poly_value(roots, comps, lv.lo, defl.lam)
         dlev = L.DeviceLevel(L.OP_POLY, hi, L.OP_POLY if lo is not None else L.OP_NONE, lo,
                              defl.device if c is not None else None, c is not None,
                              krylov._c(c) if c is not None else None)
-        N = lv.samples
         ws = L.workspace(L.level_workspace_size(dl, dlev, N, rb))
         run.levels.append(LevelState(i, dlev, poly_mvps(lv.hi) + poly_mvps(lv.lo), c,
                                      torch.zeros(8, dtype=torch.float64, device="cuda"),

@@ -171,6 +171,12 @@ def newton_value(inv_roots: np.ndarray, lam) -> np.ndarray:
     return acc
 
 
+def composite_value(inv_in: np.ndarray, inv_out: np.ndarray, lam) -> np.ndarray:
+    """p_1(lambda) = p_in(lambda) p_out(lambda p_in(lambda)) (Sec. 3.2)."""
+    pin = newton_value(inv_in, lam)
+    return pin * newton_value(inv_out, np.asarray(lam) * pin)
+
+
 # ------------------------------------------------------------------ operators
 class Operators:
     """A and B = A p_in(A) on single vectors, through the library."""
@@ -333,3 +339,38 @@ def pp_arnoldi_deflation(dl: L.DeviceLattice, pin: L.DevicePoly, start: np.ndarr
     defl.hinv = _c(np.linalg.inv(Hm))
     torch.cuda.synchronize()
     return Deflation(defl, lam, pr, np.array(rrs), np.array(rls), k)
+
+
+@dataclass
+class OuterRoots:
+    inv_roots: np.ndarray        # Leja-ordered 1/phi (host)
+    device: L.DevicePoly         # composite p_in(A) p_out(A p_in(A))
+    residual: float              # PP-GMRES relative residual after n_out steps
+
+
+def pp_outer_roots(dl: L.DeviceLattice, pin: L.DevicePoly, inv_in: np.ndarray, defl: Optional[Deflation],
+                   n_out: int, noise: L.Noise) -> OuterRoots:
+    """Setup step 2(c): the deflated double polynomial.  A Z4 start vector is
+    deflated with one Left-right Projection (Sec. 2.1) when triplets are
+    given, then n_out steps of PP-GMRES on B = A p_in(A) from it; the
+    harmonic Ritz values of that step are the roots phi_j of the outer
+    residual polynomial pi_out(beta), beta = a p_in(a) (Sec. 3.2, Sec. 4.3)."""
+    dims, V = dl.dims, dl.V
+    b = L.empty_field(V, 1, 1, F64)
+    L.z4_fill(dims, F64, noise, b)
+    if defl is not None:
+        r = L.empty_field(V, 1, 1, F64)
+        d = torch.empty((defl.device.k, 1), dtype=torch.complex128, device="cuda")
+        ws = L.workspace(L.deflate_workspace_size(dl, defl.device, 1, 1))
+        L.deflate_project(dl, defl.device, L.DEFL_PROJECT, 1, 1, b, None, None, None, d, r, ws)
+        b = r
+    canon = torch.empty((1, V, 4, 3), dtype=torch.complex128, device="cuda")
+    L.unpack_fields(dims, F64, b, canon)
+    start = canon.cpu().numpy().reshape(-1)
+    ops = Operators(dl)
+    ops.set_pin(pin)
+    arn = DeviceArnoldi(dl, n_out)
+    H, beta, m, _ = arn.run(ops.B, start)
+    phi = leja(harmonic_ritz_values(H, m))
+    inv = 1.0 / phi
+    return OuterRoots(inv, L.DevicePoly(_c(inv_in), _c(inv)), gmres_residual(H, beta, m) / beta)

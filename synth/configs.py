@@ -15,7 +15,11 @@ from __future__ import annotations
 from dataclasses import dataclass, field
 from typing import Optional, Tuple, Union
 
-Poly = Union[int, Tuple[int, int]]  # degree of a single polynomial, or (n_in, n_out) composite
+Poly = Union[int, Tuple[int, int], str]  # degree of a single polynomial, (n_in, n_out) composite, or SOLVE
+
+# The operator A^{-1} of the top level Tr(A^{-1} - p_1(A)) (Sec. 5 step 3a):
+# its samples b^H A^{-1} b need a linear solve per noise vector.
+SOLVE = "solve"
 
 
 @dataclass(frozen=True)
@@ -54,8 +58,8 @@ class LatticeConfig:
 
 def poly_mvps(p: Optional[Poly]) -> int:
     """Matrix-vector products per application (Sec. 3.1, Sec. 3.2)."""
-    if p is None:
-        return 0
+    if p is None or p == SOLVE:
+        return 0          # a solve's cost depends on its convergence; counted by the solver
     if isinstance(p, tuple):
         n_in, n_out = p
         return n_in * n_out - 1
@@ -84,7 +88,7 @@ C2 = LatticeConfig(
 
 C3 = LatticeConfig(
     name="C3", dims=(16, 16, 16, 32), eps=0.5, kappa=0.150,
-    levels=(Level((20, 15), None, 64, deflated=True),),
+    levels=(Level(SOLVE, (20, 15), 64, deflated=True),),
     k_defl=32, seed_links=301, seed_start=302, seed_noise=303, lattice_id=3,
     description="16^3x32, n=1.57M, composite poly 20x15 (deg 299), 64 RHS, FP32 bulk / FP64 sums",
 )

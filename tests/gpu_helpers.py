@@ -50,3 +50,20 @@ def dev_c128(a) -> torch.Tensor:
 
 def rel(a, b) -> float:
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+def device_defl(dims, Z, pair, U, H, prec=0, kpad=16):
+    """Oracle triplets (rows of Z, left vectors U, H = U^H A V) as a DeviceDefl."""
+    L = lib()
+    k, n = Z.shape
+    Zp = np.zeros((kpad, n), dtype=np.complex128)
+    Zp[:k] = Z
+    Vf = pack(dims, Zp, kpad, prec)
+    # scale_i: u_i = scale_i * g5 z_pair(i)
+    g5 = np.array([1] * 6 + [-1] * 6, dtype=float)
+    V = n // 12
+    g5z = (Z.reshape(k, V, 12) * g5).reshape(k, n)
+    scale = np.array([np.vdot(g5z[pair[i]], U[i]) / np.vdot(g5z[pair[i]], g5z[pair[i]]) for i in range(k)])
+    assert np.allclose(U, scale[:, None] * g5z[pair])
+    return L.DeviceDefl(k, Vf, torch.from_numpy(pair.astype(np.int32)).cuda(), dev_c128(scale),
+                        dev_c128(np.linalg.inv(H)) if H is not None else None)

@@ -13,7 +13,7 @@ import oracle
 import synth
 from oracle import deflation, dense, estimator, krylov
 
-from gpu_helpers import dev_c128, device_lattice, lib, pack, rel, unpack
+from gpu_helpers import dev_c128, device_defl, device_lattice, lib, pack, rel, unpack
 
 pytestmark = pytest.mark.gpu
 
@@ -230,19 +230,7 @@ def small_defl():
 
 
 def _device_defl(dims, Z, pair, U, H, prec=0, kpad=16):
-    L = lib()
-    k, n = Z.shape
-    Zp = np.zeros((kpad, n), dtype=np.complex128)
-    Zp[:k] = Z
-    Vf = pack(dims, Zp, kpad, prec)
-    # scale_i: u_i = scale_i * g5 z_pair(i)
-    g5 = np.array([1] * 6 + [-1] * 6, dtype=float)
-    V = n // 12
-    g5z = (Z.reshape(k, V, 12) * g5).reshape(k, n)
-    scale = np.array([np.vdot(g5z[pair[i]], U[i]) / np.vdot(g5z[pair[i]], g5z[pair[i]]) for i in range(k)])
-    assert np.allclose(U, scale[:, None] * g5z[pair])
-    return L.DeviceDefl(k, Vf, torch.from_numpy(pair.astype(np.int32)).cuda(), dev_c128(scale),
-                        dev_c128(np.linalg.inv(H)) if H is not None else None)
+    return device_defl(dims, Z, pair, U, H, prec, kpad)
 
 
 @pytest.mark.parametrize("nrhs,rb,z4", [(8, 4, True), (5, 1, False), (40, 8, True)])

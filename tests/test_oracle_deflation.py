@@ -111,3 +111,28 @@ def test_mc_levels_within_4_sigma_of_exact():
         est = estimator.level_estimate(estimator.level_samples(h, l))
         target = exact[hi] - (exact[lo] if lo else 0)
         assert abs(est.estimate - target) < 4 * est.stderr
+
+
+def test_top_level_trace_identity(small):
+    """Tr(A^{-1} - Q) summed from unit-vector samples b^H A^{-1} b - b^H Q b
+    (dense solve, deflated composite Q) equals sum over the eigenvalues not
+    deflated of 1/lambda - p_1(lambda) (LAPACK spectrum): Q is 1/lambda_i on
+    the deflated z_i and p_1(lambda_j) on every other eigenvector."""
+    from oracle import solve
+    lat, A, lam, Z, pair, U = small
+    H = deflation.projection_matrix(lat.apply, Z, U)
+    rng = np.random.default_rng(5)
+    inv_in = 0.4 + 0.3 * rng.standard_normal(4) + 0.1j * rng.standard_normal(4)
+    inv_out = 0.5 + 0.2 * rng.standard_normal(3) + 0.1j * rng.standard_normal(3)
+    Q = deflation.DeflatedPoly(lat.apply, Z, U, H, lambda v: lat.composite_apply(inv_in, inv_out, v)[0])
+    E = np.eye(lat.n, dtype=np.complex128)
+    X = solve.dense_solve(lat, E)
+    QE = np.array([Q.apply(e) for e in E])
+    s = solve.top_level_samples(E, X, QE)
+    mu = np.linalg.eigvals(A)
+    keep = np.ones(len(mu), dtype=bool)
+    for l in lam:
+        keep[np.argmin(np.abs(mu - l) + (~keep) * 1e9)] = False
+    want = np.sum(1.0 / mu[keep] - deflation.composite_eval(inv_in, inv_out, mu[keep]))
+    assert abs(np.sum(s) - want) < 1e-9 * np.sum(np.abs(1.0 / mu))
+    assert np.max(solve.residual(lat, E[:5], X[:5])) < 1e-13
