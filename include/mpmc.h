@@ -100,7 +100,10 @@ typedef struct {
     uint64_t seed;
     uint64_t lattice;       /* lattice id */
     uint64_t level;         /* level id */
-    uint64_t first_sample;  /* vector r of a batch is global sample first_sample + r */
+    uint64_t first_sample;  /* vector r of a batch is global sample first_sample + r (+ *sample_offset) */
+    const uint64_t *sample_offset;  /* device counter added to first_sample when the kernels run, or
+                                       NULL.  Lets a captured HIP graph draw new samples on every
+                                       replay: advance it with mpmc_counter_add inside the graph. */
 } mpmc_noise;
 
 typedef struct {
@@ -139,6 +142,11 @@ const char *mpmc_build_info(void);
  * Both paths compute the same values up to the order of floating-point sums. */
 enum { MPMC_OPT_PLANE_SWEEP = 1 };
 int mpmc_set_option(int32_t option, int32_t value);
+
+/* *counter += increment, enqueued on `stream` as a one-thread kernel (plain
+ * vector store; capturable in a HIP graph, unlike a memset or memcpy node).
+ * counter: device, caller-owned. */
+int mpmc_counter_add(uint64_t *counter, uint64_t increment, void *stream);
 
 /* ---- layout conversion and noise ------------------------------------- */
 

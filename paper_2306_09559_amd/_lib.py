@@ -44,7 +44,8 @@ class mpmc_shape(ctypes.Structure):
 
 
 class mpmc_noise(ctypes.Structure):
-    _fields_ = [("seed", c_u64), ("lattice", c_u64), ("level", c_u64), ("first_sample", c_u64)]
+    _fields_ = [("seed", c_u64), ("lattice", c_u64), ("level", c_u64), ("first_sample", c_u64),
+                ("sample_offset", c_vp)]
 
 
 class mpmc_poly(ctypes.Structure):
@@ -65,6 +66,7 @@ _sig = {
     "mpmc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "mpmc_build_info": (ctypes.c_char_p, []),
     "mpmc_set_option": (ctypes.c_int, [c_i32, c_i32]),
+    "mpmc_counter_add": (ctypes.c_int, [c_vp, c_u64, c_vp]),
     "mpmc_pack_gauge": (ctypes.c_int, [P(c_i32), c_i32, c_vp, c_vp, c_vp]),
     "mpmc_pack_fields": (ctypes.c_int, [P(c_i32), c_i32, mpmc_shape, c_vp, c_vp, c_vp]),
     "mpmc_unpack_fields": (ctypes.c_int, [P(c_i32), c_i32, mpmc_shape, c_vp, c_vp, c_vp]),
@@ -148,9 +150,10 @@ class Noise:
     lattice: int
     level: int
     first_sample: int = 0
+    sample_offset: Optional[torch.Tensor] = None   # device int64 (1,) counter added to first_sample
 
     def c(self) -> mpmc_noise:
-        return mpmc_noise(self.seed, self.lattice, self.level, self.first_sample)
+        return mpmc_noise(self.seed, self.lattice, self.level, self.first_sample, _ptr(self.sample_offset))
 
 
 @dataclass
@@ -239,6 +242,12 @@ def workspace(nbytes: int, device="cuda") -> torch.Tensor:
 
 
 # ------------------------------------------------------------------ entry points
+def counter_add(counter: torch.Tensor, increment: int):
+    """counter[0] += increment on the device (int64 tensor; capturable)."""
+    assert counter.dtype == torch.int64
+    _check("mpmc_counter_add", _lib.mpmc_counter_add(_ptr(counter), int(increment), _stream()))
+
+
 def pack_gauge(dims, prec: int, canon: torch.Tensor, gauge: torch.Tensor):
     assert canon.dtype == torch.complex128 and canon.is_contiguous()
     _check("mpmc_pack_gauge", _lib.mpmc_pack_gauge(_dims(dims), prec, _ptr(canon), _ptr(gauge), _stream()))

@@ -118,6 +118,11 @@ int mpmc_set_option(int32_t option, int32_t value) {
     }
 }
 
+int mpmc_counter_add(uint64_t *counter, uint64_t increment, void *stream) {
+    if (!counter) return MPMC_EINVAL;
+    return counter_add_impl(counter, increment, stream);
+}
+
 int mpmc_pack_gauge(const int32_t dims[4], int32_t prec, const double *canon, void *gauge, void *stream) {
     if (!valid_dims(dims) || !canon || !gauge) return MPMC_EINVAL;
     if (!valid_prec(prec)) return MPMC_EUNSUPPORTED;

@@ -92,6 +92,13 @@ __host__ __device__ __forceinline__ uint64_t sm_mix(uint64_t z) {
 }
 __host__ __device__ __forceinline__ uint64_t sm_out(uint64_t x, uint64_t k) { return sm_mix(x + k * kGolden); }
 
+// Global index of vector 0 of a noise batch: first_sample, plus the device
+// counter sample_offset when one is given (read by the kernels, so a captured
+// graph draws new samples on every replay once the counter is advanced).
+__device__ __forceinline__ uint64_t sample_base(uint64_t first, const uint64_t *off) {
+    return off ? first + *off : first;
+}
+
 inline uint64_t noise_key(const mpmc_noise &nz) {
     uint64_t k = sm_out(nz.seed, 1);
     k = sm_out(k ^ nz.lattice, 1);

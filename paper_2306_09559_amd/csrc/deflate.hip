@@ -48,6 +48,7 @@ template <typename T> struct CoeffArgs {
     const cplx_t<T> *V;                // [12][Vol][kpad]
     const cplx_t<T> *b;                // field, or nullptr -> Z4
     uint64_t key, first;
+    const uint64_t *off;
     double2 *part;                     // [split][2][kpad][ntr*16]
 };
 
@@ -68,7 +69,7 @@ __global__ void __launch_bounds__(kWaves * 64) k_coeff(CoeffArgs<T> a) {
     uint64_t S = 0;
     size_t bfb = 0;
     if (rvalid) {
-        if (a.b == nullptr) S = sample_state(a.key, a.first + (uint64_t)r);
+        if (a.b == nullptr) S = sample_state(a.key, sample_base(a.first, a.off) + (uint64_t)r);
         else bfb = (size_t)(r / a.rb) * 12 * (size_t)a.Vol * (size_t)a.rb + (size_t)(r % a.rb);
     }
     acc_t cre[2], cim[2];
@@ -273,6 +274,7 @@ int coeff_t(const mpmc_lattice &lat, const mpmc_defl &df, mpmc_shape sh, const v
     a.b = (const cplx_t<T> *)b;
     a.key = noise ? noise_key(*noise) : 0ull;
     a.first = noise ? noise->first_sample : 0ull;
+    a.off = noise ? noise->sample_offset : nullptr;
     a.part = (double2 *)ws;
     hipLaunchKernelGGL(k_coeff<T>, dim3(p.nti * p.ntr, p.nsplit), dim3(kWaves * 64), 0, (hipStream_t)stream, a);
     if (hipGetLastError() != hipSuccess) return MPMC_EHIP;
@@ -346,8 +348,9 @@ int deflate_impl(const mpmc_lattice &lat, const mpmc_defl &df, int32_t mode, mpm
     if (st != MPMC_OK) return st;
     const uint64_t key = noise ? noise_key(*noise) : 0ull;
     const uint64_t first = noise ? noise->first_sample : 0ull;
-    return f64 ? residual_apply_t<double>(lat, sh, xh, b, key, first, X, stream)
-               : residual_apply_t<float>(lat, sh, xh, b, key, first, X, stream);
+    const uint64_t *off = noise ? noise->sample_offset : nullptr;
+    return f64 ? residual_apply_t<double>(lat, sh, xh, b, key, first, off, X, stream)
+               : residual_apply_t<float>(lat, sh, xh, b, key, first, off, X, stream);
 }
 
 }  // namespace mpmc

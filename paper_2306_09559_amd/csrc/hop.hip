@@ -36,6 +36,7 @@ template <typename T> struct HopArgs {
     double2 alpha, beta;
     // noise (input when IN_Z4, dot/add vector when bvec == nullptr)
     uint64_t key, first;
+    const uint64_t *off;       // device sample counter added to first, or nullptr
     const cplx_t<T> *bvec;
     // Newton accumulator y (YACC)
     cplx_t<T> *y;
@@ -272,7 +273,7 @@ __global__ void __launch_bounds__(kBlock) k_hop(HopArgs<T> a) {
     const int jr = lane & (a.rb - 1), ls = lane / a.rb;
     const int s = sblk * a.spw + ls;
     const bool valid = s < a.g.V;
-    const uint64_t r_global = a.first + (uint64_t)(nbk * a.rb + jr);
+    const uint64_t r_global = sample_base(a.first, a.off) + (uint64_t)(nbk * a.rb + jr);
     const Blk<T> in = blk<T>(a.in, nbk, a.g.V, a.rb);
 
     // step coefficients
@@ -402,7 +403,7 @@ __global__ void __launch_bounds__(kBlock) k_scale_dot(HopArgs<T> a) {
     const int lane = (int)threadIdx.x;
     const int jr = lane & (a.rb - 1), ls = lane / a.rb;
     const int s = sblk * a.spw + ls;
-    const uint64_t r_global = a.first + (uint64_t)(nbk * a.rb + jr);
+    const uint64_t r_global = sample_base(a.first, a.off) + (uint64_t)(nbk * a.rb + jr);
     const double2 t0 = a.troots[a.j];
     const Blk<T> in = blk<T>(a.in, nbk, a.g.V, a.rb);
     double2 contrib;
@@ -508,7 +509,7 @@ int wilson_apply_t(const mpmc_lattice &lat, mpmc_shape sh, const void *x, void *
 
 template <typename T>
 int residual_apply_t(const mpmc_lattice &lat, mpmc_shape sh, const void *x, const void *b, uint64_t key,
-                     uint64_t first, void *out, void *stream) {
+                     uint64_t first, const uint64_t *off, void *out, void *stream) {
     // out = b - A x
     HopArgs<T> a = base_args<T>(lat, sh);
     a.in = (const cplx_t<T> *)x;
@@ -520,6 +521,7 @@ int residual_apply_t(const mpmc_lattice &lat, mpmc_shape sh, const void *x, cons
     a.bvec = (const cplx_t<T> *)b;
     a.key = key;
     a.first = first;
+    a.off = off;
     launch_hop<T>(a, false, false, false, false, true, stream);
     return hipGetLastError() == hipSuccess ? MPMC_OK : MPMC_EHIP;
 }
@@ -528,12 +530,13 @@ int residual_apply_t(const mpmc_lattice &lat, mpmc_shape sh, const void *x, cons
 //   x == nullptr: input is the noise; bvec == nullptr: dot vector is the noise.
 template <typename T>
 static int newton_t(const mpmc_lattice &lat, mpmc_shape sh, int n, const double *troots, const void *x, bool x_is_noise,
-                    const void *bvec, uint64_t key, uint64_t first, void *y, double2 *part, void *w0, void *w1,
+                    const void *bvec, uint64_t key, uint64_t first, const uint64_t *off, void *y, double2 *part, void *w0, void *w1,
                     void *stream) {
     HopArgs<T> a = base_args<T>(lat, sh);
     a.troots = (const double2 *)troots;
     a.key = key;
     a.first = first;
+    a.off = off;
     a.bvec = (const cplx_t<T> *)bvec;
     a.part = part;
     a.y = (cplx_t<T> *)y;
@@ -564,6 +567,7 @@ int poly_apply_t(const mpmc_lattice &lat, const mpmc_poly &poly, mpmc_shape sh, 
                  void *y, double *bhy, const PolyWs &ws, void *stream) {
     const uint64_t key = noise ? noise_key(*noise) : 0ull;
     const uint64_t first = noise ? noise->first_sample : 0ull;
+    const uint64_t *off = noise ? noise->sample_offset : nullptr;
     const bool x_noise = (x == nullptr);
     // dot vector: the noise if given, else x itself
     const void *bvec = noise ? nullptr : x;
@@ -572,11 +576,11 @@ int poly_apply_t(const mpmc_lattice &lat, const mpmc_poly &poly, mpmc_shape sh, 
     int st;
     if (poly.n_out == 0 && y == nullptr && bhy != nullptr && poly.n_in >= 2 && g_opt_sweep && sweep_fits(lat)) {
         // scalar mode on a lattice whose xyz-plane fits one workgroup: t-sweep
-        return sweep_newton_t<T>(lat, sh, poly.n_in, poly.inv_roots_in, x, x_noise, bvec, key, first, part,
+        return sweep_newton_t<T>(lat, sh, poly.n_in, poly.inv_roots_in, x, x_noise, bvec, key, first, off, part,
                                  (double2 *)bhy, ws.f[0], ws.f[1], stream);
     }
     if (poly.n_out == 0) {
-        st = newton_t<T>(lat, sh, poly.n_in, poly.inv_roots_in, x, x_noise, bvec, key, first, y, part, ws.f[0],
+        st = newton_t<T>(lat, sh, poly.n_in, poly.inv_roots_in, x, x_noise, bvec, key, first, off, y, part, ws.f[0],
                          ws.f[1], stream);
         if (st != MPMC_OK) return st;
     } else {
@@ -584,7 +588,7 @@ int poly_apply_t(const mpmc_lattice &lat, const mpmc_poly &poly, mpmc_shape sh, 
         HopArgs<T> a = base_args<T>(lat, sh);
         void *U0 = ws.f[0], *U1 = ws.f[1], *V0 = ws.f[2], *V1 = ws.f[3], *Y = ws.f[4];
         // u_0 = x
-        st = copy_or_noise_t<T>(lat, sh, x, key, first, U0, stream);
+        st = copy_or_noise_t<T>(lat, sh, x, key, first, off, U0, stream);
         if (st != MPMC_OK) return st;
         void *ucur = U0, *unext = U1;
         const int n_in = poly.n_in, n_out = poly.n_out;
@@ -625,7 +629,7 @@ int poly_apply_t(const mpmc_lattice &lat, const mpmc_poly &poly, mpmc_shape sh, 
         }
         // final p_in(A) applied to y_out, dot against b
         const void *bv = noise ? nullptr : x;
-        st = newton_t<T>(lat, sh, n_in, poly.inv_roots_in, Y, false, bv, key, first, y, part, V0, V1, stream);
+        st = newton_t<T>(lat, sh, n_in, poly.inv_roots_in, Y, false, bv, key, first, off, y, part, V0, V1, stream);
         if (st != MPMC_OK) return st;
     }
     if (bhy) {
@@ -640,9 +644,9 @@ int poly_apply_t(const mpmc_lattice &lat, const mpmc_poly &poly, mpmc_shape sh, 
 template int wilson_apply_t<double>(const mpmc_lattice &, mpmc_shape, const void *, void *, void *);
 template int wilson_apply_t<float>(const mpmc_lattice &, mpmc_shape, const void *, void *, void *);
 template int residual_apply_t<double>(const mpmc_lattice &, mpmc_shape, const void *, const void *, uint64_t, uint64_t,
-                                      void *, void *);
+                                      const uint64_t *, void *, void *);
 template int residual_apply_t<float>(const mpmc_lattice &, mpmc_shape, const void *, const void *, uint64_t, uint64_t,
-                                     void *, void *);
+                                     const uint64_t *, void *, void *);
 template int poly_apply_t<double>(const mpmc_lattice &, const mpmc_poly &, mpmc_shape, const void *, const mpmc_noise *,
                                   void *, double *, const PolyWs &, void *);
 template int poly_apply_t<float>(const mpmc_lattice &, const mpmc_poly &, mpmc_shape, const void *, const mpmc_noise *,

@@ -28,12 +28,14 @@ template <typename T> int wilson_apply_t(const mpmc_lattice &, mpmc_shape, const
 // out = b - A x, b a field or (b == nullptr) the noise (key, first)
 template <typename T>
 int residual_apply_t(const mpmc_lattice &, mpmc_shape, const void *x, const void *b, uint64_t key, uint64_t first,
+                     const uint64_t *off,
                      void *out, void *stream);
 // t-sweep Newton steps (plane per workgroup); see sweep.hip
 bool sweep_fits(const mpmc_lattice &lat);
 template <typename T>
 int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, int n, const double *troots, const void *x, bool x_is_noise,
-                   const void *bvec, uint64_t key, uint64_t first, double2 *part, double2 *bhy, void *w0, void *w1,
+                   const void *bvec, uint64_t key, uint64_t first, const uint64_t *off, double2 *part, double2 *bhy,
+                   void *w0, void *w1,
                    void *stream);
 
 // process-wide options (mpmc_set_option)
@@ -45,12 +47,14 @@ int poly_apply_t(const mpmc_lattice &, const mpmc_poly &, mpmc_shape, const void
 
 // layout / noise kernels
 template <typename T>
-int copy_or_noise_t(const mpmc_lattice &lat, mpmc_shape sh, const void *x, uint64_t key, uint64_t first, void *out,
+int copy_or_noise_t(const mpmc_lattice &lat, mpmc_shape sh, const void *x, uint64_t key, uint64_t first,
+                    const uint64_t *off, void *out,
                     void *stream);
 int pack_gauge_impl(const int32_t dims[4], int32_t prec, const double *canon, void *gauge, void *stream);
 int pack_fields_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, const double *canon, void *field, void *stream);
 int unpack_fields_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, const void *field, double *canon,
                        void *stream);
+int counter_add_impl(uint64_t *counter, uint64_t inc, void *stream);
 int z4_fill_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, const mpmc_noise &nz, void *field, void *stream);
 
 // field utilities (Krylov set-up)

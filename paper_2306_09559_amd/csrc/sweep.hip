@@ -32,6 +32,7 @@ template <typename T> struct SweepArgs {
     int j;
     double kappa;
     uint64_t key, first;       // noise (input when IN_Z4; dot vector when bvec == nullptr)
+    const uint64_t *off;       // device sample counter added to first, or nullptr
     const cplx_t<T> *bvec;     // dot vector field (layout rb_b), or nullptr
     int rb_b;
     double2 *part;             // N partial sums, one per vector
@@ -283,7 +284,7 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
 
     const double2 tj = a.troots[a.j];
     const double2 beta = make_double2(a.kappa * tj.x, a.kappa * tj.y);   // kappa t_j
-    const uint64_t S = sample_state(a.key, a.first + (uint64_t)r);
+    const uint64_t S = sample_state(a.key, sample_base(a.first, a.off) + (uint64_t)r);
     const Plane<T> inp = plane_of<T>(a.in, r, a.V, a.rb_in);
     const Plane<T> outp = plane_of<T>(a.out, r, a.V, 1);
 
@@ -469,7 +470,7 @@ bool sweep_fits(const mpmc_lattice &lat) {
 
 template <typename T>
 int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, int n, const double *troots, const void *x, bool x_is_noise,
-                   const void *bvec, uint64_t key, uint64_t first, double2 *part, double2 *bhy, void *w0, void *w1,
+                   const void *bvec, uint64_t key, uint64_t first, const uint64_t *off, double2 *part, double2 *bhy, void *w0, void *w1,
                    void *stream) {
     SweepArgs<T> a{};
     for (int d = 0; d < 4; ++d) a.L[d] = lat.dims[d];
@@ -481,6 +482,7 @@ int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, int n, const double *
     a.kappa = lat.kappa;
     a.key = key;
     a.first = first;
+    a.off = off;
     a.bvec = (const cplx_t<T> *)bvec;
     a.rb_b = sh.rb;
     a.part = part;
@@ -522,8 +524,10 @@ int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, int n, const double *
 }
 
 template int sweep_newton_t<double>(const mpmc_lattice &, mpmc_shape, int, const double *, const void *, bool,
-                                    const void *, uint64_t, uint64_t, double2 *, double2 *, void *, void *, void *);
+                                    const void *, uint64_t, uint64_t, const uint64_t *, double2 *, double2 *, void *, void *,
+                                    void *);
 template int sweep_newton_t<float>(const mpmc_lattice &, mpmc_shape, int, const double *, const void *, bool,
-                                   const void *, uint64_t, uint64_t, double2 *, double2 *, void *, void *, void *);
+                                   const void *, uint64_t, uint64_t, const uint64_t *, double2 *, double2 *, void *, void *,
+                                    void *);
 
 }  // namespace mpmc

@@ -46,6 +46,8 @@ class LevelState:
     xl: Optional[torch.Tensor] = None       # x in the level precision
     last_solve: Optional[SolveStats] = None
     solve_tol: float = 1e-6
+    rb: int = 0                             # RHS block width of this level (0: the run's)
+    sweep: bool = True                      # allow the t-sweep kernel for this level
 
 
 @dataclass
@@ -62,10 +64,26 @@ class LatticeRun:
     composites: Dict[tuple, krylov.OuterRoots] = field(default_factory=dict)
 
     # -- sampling --------------------------------------------------------
+    def noise(self, level: int, sample_offset: Optional[torch.Tensor] = None) -> L.Noise:
+        lv = self.levels[level]
+        return L.Noise(self.cfg.seed_noise, self.cfg.lattice_id, lv.index, lv.drawn, sample_offset)
+
+    def level_rb(self, level: int) -> int:
+        return self.levels[level].rb or self.rb
+
+    def enqueue(self, level: int, nsamples: int, nz: L.Noise):
+        """Enqueue one batch of a polynomial level with an explicit noise
+        descriptor (used by graph capture, where the sample index comes from a
+        device counter)."""
+        lv = self.levels[level]
+        L.set_option(L.OPT_PLANE_SWEEP, int(lv.sweep))
+        L.mlmc_level_estimate(self.dl, lv.device, nsamples, self.level_rb(level), nz, lv.samples[:nsamples],
+                              lv.acc, lv.ws)
+
     def draw(self, level: int, nsamples: int):
         """Enqueue nsamples more samples of one level (one batch)."""
         lv = self.levels[level]
-        nz = L.Noise(self.cfg.seed_noise, self.cfg.lattice_id, lv.index, lv.drawn)
+        nz = self.noise(level)
         if lv.solver is not None:
             # x = A^{-1} b for this batch's noise, then b^H x - b^H P_lo b
             if nsamples != lv.solver.N:
@@ -74,7 +92,7 @@ class LatticeRun:
             lv.last_solve = lv.solver.solve(lv.b64, lv.x64, tol=lv.solve_tol)
             if lv.xl is not lv.x64:
                 L.field_axpby_mixed(self.cfg.dims, lv.solver.ones, lv.x64, None, lv.xl)
-        L.mlmc_level_estimate(self.dl, lv.device, nsamples, self.rb, nz, lv.samples[:nsamples], lv.acc, lv.ws)
+        self.enqueue(level, nsamples, nz)
         lv.drawn += nsamples
 
     def step(self, batch: Optional[Dict[int, int]] = None):
@@ -86,6 +104,18 @@ class LatticeRun:
         for lv in self.levels:
             lv.acc.zero_()
             lv.drawn = 0
+
+    def set_level_shape(self, level: int, rb: int, sweep: bool):
+        """Choose the RHS block width and kernel family of one level (the
+        autotuner's knobs); resizes the level's workspace."""
+        lv = self.levels[level]
+        if lv.solver is not None:
+            raise ValueError("the block width of a solve level is fixed by its solver")
+        N = self.cfg.levels[level].samples
+        if N % rb:
+            raise ValueError(f"rb={rb} does not divide {N}")
+        lv.rb, lv.sweep = int(rb), bool(sweep)
+        lv.ws = L.workspace(L.level_workspace_size(self.dl, lv.device, N, rb))
 
     def estimates(self):
         """Per-level (estimate, stderr, variance, n) on the host."""
