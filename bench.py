@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--rb", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-bulk (mixed) comparison run")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batched independent lattices and the top-level solve measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -144,6 +146,116 @@ def timed_steps(run, steps, stream):
     return wall, lvl_ms
 
 
+def kernel_launch_seconds(run, steps: int, stream) -> float:
+    """Average duration of one launch of the dominant kernel, from HIP events
+    on `stream`: scalar-mode applications of the top level's high-degree
+    polynomial (one t-sweep launch per operator application, plus one tiny
+    reduction) to the level's batch of Z4 vectors."""
+    import torch
+    from paper_2306_09559_amd import _lib as L
+    lv = run.levels[0]
+    poly = lv.device.poly_hi
+    L.set_option(L.OPT_PLANE_SWEEP, 1)
+    N = run.cfg.levels[0].samples
+    ws = L.workspace(L.poly_workspace_size(run.dl, poly, N, run.rb))
+    bhy = torch.empty(N, dtype=torch.complex128, device="cuda")
+    nz = L.Noise(run.cfg.seed_noise, run.cfg.lattice_id, 99, 0)
+    L.poly_apply(run.dl, poly, N, run.rb, None, nz, None, bhy, ws)      # warm-up
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        L.poly_apply(run.dl, poly, N, run.rb, None, nz, None, bhy, ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    launches = steps * (int(poly.inv_in.numel()) - 1)
+    return e0.elapsed_time(e1) * 1e-3 / launches
+
+
+def graph_level_seconds(run, reps: int):
+    """Per-sample seconds of each level when its batch is replayed as a HIP graph."""
+    import torch
+    from paper_2306_09559_amd.batch import GraphStep
+    out = []
+    for li in range(len(run.levels)):
+        gs = GraphStep([run], parallel=False, only=[(0, li)])
+        gs.replay()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        gs.replay(reps)
+        e1.record()
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1) * 1e-3 / (reps * run.cfg.levels[li].samples))
+    run.reset()
+    return out
+
+
+def batched_c5(steps: int):
+    """The mixed batch of independent lattices (8^4, 12^4, 16^4, 12^3x24; own
+    kappa, degree and sample count), FP32 bulk: serial eager steps against one
+    graph whose branches run the lattices concurrently."""
+    import time
+    import torch
+    from paper_2306_09559_amd import _lib as L
+    from paper_2306_09559_amd import driver
+    from paper_2306_09559_amd.batch import GraphStep
+    from synth.configs import C5
+    t0 = time.perf_counter()
+    runs = [driver.build(c, prec=L.F32, rb=8) for c in C5]
+    setup = time.perf_counter() - t0
+    for r in runs:
+        r.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for r in runs:
+            r.step()
+    torch.cuda.synchronize()
+    eager = (time.perf_counter() - t0) / steps
+    gs = GraphStep(runs, parallel=True)
+    gs.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gs.replay(steps)
+    torch.cuda.synchronize()
+    graph = (time.perf_counter() - t0) / steps
+    mvp = sum(r.mvp_rhs_per_step() for r in runs)
+    byts = sum(r.bytes_per_step() for r in runs)
+    return {"lattices": [f"{'x'.join(map(str, c.dims))} k={c.kappa} deg {c.levels[0].hi} N={c.levels[0].samples}"
+                         for c in C5],
+            "prec": "f32", "setup_s": round(setup, 2), "mvp_rhs_per_step": mvp,
+            "eager_serial_ms_per_step": round(eager * 1e3, 3), "graph_parallel_ms_per_step": round(graph * 1e3, 3),
+            "speedup": round(eager / graph, 3), "graph_GBps": round(byts / graph / 1e9, 1)}
+
+
+def top_level_c3():
+    """The top level Tr(A^{-1} - p_1) of the 16^3x32 workload: one batch of 64
+    Z4 vectors solved by deflated PP-GMRES (FP32 inner cycles, FP64 residual)
+    and sampled against the deflated composite p_1 (299 MVPs)."""
+    import time
+    import torch
+    from paper_2306_09559_amd import _lib as L
+    from paper_2306_09559_amd import driver
+    from synth.configs import C3
+    t0 = time.perf_counter()
+    run = driver.build(C3, prec=L.F32, rb=16)
+    setup = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run.draw(0, C3.levels[0].samples)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = run.levels[0].last_solve
+    e = run.estimates()[0]
+    return {"workload": "16^3x32 n=1572864, kappa=0.15, eps=0.5 links; Tr(A^-1 - Q), Q = deflated composite "
+                        "PP(20)x15 (deg 299), k=%d" % run.defl.device.k,
+            "setup_s": round(setup, 2), "batch": C3.levels[0].samples, "batch_s": round(dt, 3),
+            "solve": {"outer_fp64": st.outer, "inner_cycles": st.cycles, "arnoldi_steps": st.arnoldi_steps,
+                      "mvps_per_vector": st.mvps, "max_rel_residual": float(f"{st.rel_res.max():.3g}"),
+                      "rtolle": 1e-6},
+            "estimate": [round(e["estimate"].real, 4), round(e["estimate"].imag, 4)], "stderr": round(e["stderr"], 4),
+            "target_stderr": round(0.0005 * C3.volume / 3 ** 0.5, 3)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -154,6 +266,7 @@ def main():
     import torch
     from paper_2306_09559_amd import _lib as L
     from paper_2306_09559_amd import driver
+    from paper_2306_09559_amd.batch import GraphStep, autotune
     from synth.configs import C2
 
     torch.cuda.set_device(0)
@@ -170,12 +283,10 @@ def main():
     byts = run.bytes_per_step()
     value = byts * args.steps / wall / 1e9
 
-    # dominant kernel: every operator application of a level is one k_hop launch
-    # on `stream`; its average duration over the timed region from the level events
-    launches = sum(lv.mvps_per_sample for lv in run.levels) * args.steps
-    kernel_s = lvl_ms.sum() * 1e-3
+    # dominant kernel: the t-sweep launch (one per operator application)
+    launch_s = kernel_launch_seconds(run, args.steps, stream)
     per_launch_bytes = driver.launch_bytes(V, N, prec)
-    achieved = per_launch_bytes / (kernel_s / launches) / 1e9
+    achieved = per_launch_bytes / launch_s / 1e9
     traffic = measured_traffic(args.prec)
 
     est = run.estimates()
@@ -203,7 +314,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": KERNEL, "bytes_per_launch": per_launch_bytes,
-                     "avg_launch_us": round(kernel_s / launches * 1e6, 3)},
+                     "avg_launch_us": round(launch_s * 1e6, 3)},
         "time_to_eps_s": round(t_eps, 4),
         "eps": eps,
         "levels": [{"estimate": [round(e["estimate"].real, 6), round(e["estimate"].imag, 6)],
@@ -235,7 +346,29 @@ def main():
                      "(eps = 0.0005 V split over the levels), same noise",
             "bound_met": all(abs(a["estimate"] - b["estimate"]) <= 0.1 * t for a, b, t in zip(est32, est, targets)),
         }
-        out["time_to_eps_s"] = {"f64": out["time_to_eps_s"], "mixed": out["mixed"]["time_to_eps_s"]}
+        # mixed + batched: autotuned shapes, every level's batch replayed as a HIP graph
+        tune = autotune(run32, reps=2, use_cache=False)
+        gps = graph_level_seconds(run32, args.steps)
+        gs = GraphStep([run32], parallel=False)
+        gs.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gs.replay(args.steps)
+        torch.cuda.synchronize()
+        gstep = (time.perf_counter() - t0) / args.steps
+        t_mb = driver.time_to_error([e["variance"] for e in est32], gps, eps)
+        out["mixed_batched"] = {
+            "ms_per_step": round(gstep * 1e3, 3),
+            "value": round(run32.bytes_per_step() / gstep / 1e9, 2), "unit": "GB/s",
+            "time_to_eps_s": round(t_mb, 4),
+            "speedup_vs_f64": round(t_eps / t_mb, 3),
+            "shapes": {str(k): {"rb": v[0], "sweep": v[1]} for k, v in tune.choice.items()},
+        }
+        out["time_to_eps_s"] = {"f64": out["time_to_eps_s"], "mixed": out["mixed"]["time_to_eps_s"],
+                                "mixed_batched": round(t_mb, 4)}
+    if not args.no_extra:
+        out["batched_lattices"] = batched_c5(args.steps)
+        out["top_level"] = top_level_c3()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(C2, args.prec)
     if args.calibrate_copy:

@@ -43,14 +43,17 @@ class GraphStep:
     """One step of several lattice runs captured as one HIP graph."""
 
     def __init__(self, runs: Sequence[LatticeRun], batch: Optional[Dict[Tuple[int, int], int]] = None,
-                 parallel: bool = True, warmup: int = 1):
+                 parallel: bool = True, warmup: int = 1, only: Optional[Sequence[Tuple[int, int]]] = None):
+        """runs: the lattices; batch: samples per (run, level), default the
+        configured batch; only: restrict to these (run, level) pairs."""
         self.runs = list(runs)
         self.parallel = parallel
         self.items: List[List[_Item]] = []
+        sel = set(only) if only is not None else None
         for ri, run in enumerate(self.runs):
             row = []
             for li, lv in enumerate(run.levels):
-                if lv.solver is not None:
+                if lv.solver is not None or (sel is not None and (ri, li) not in sel):
                     continue
                 n = (batch or {}).get((ri, li), run.cfg.levels[li].samples)
                 row.append(_Item(run, li, n, torch.zeros(1, dtype=torch.int64, device="cuda")))
