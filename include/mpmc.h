@@ -89,6 +89,11 @@ typedef struct {
     int32_t prec;           /* MPMC_F64 or MPMC_F32: precision of gauge and fields */
     double kappa;           /* hopping parameter */
     const void *gauge;      /* device, library gauge layout, 36*V complex */
+    int32_t link_rows;      /* 3 (or 0): every entry of a link is read.  2: the links are special
+                               unitary (SU(3), as the gauge links of the paper's quenched
+                               ensembles) and the kernels read rows 0 and 1 only, rebuilding
+                               row 2 = conj(row 0 x row 1): a third less link traffic.  Exact for
+                               SU(3) links; check a gauge field with mpmc_gauge_unitarity. */
 } mpmc_lattice;
 
 typedef struct {
@@ -154,6 +159,12 @@ int mpmc_counter_add(uint64_t *counter, uint64_t increment, void *stream);
  * precision, library gauge layout).  Both device, caller-owned. */
 int mpmc_pack_gauge(const int32_t dims[4], int32_t prec, const double *canon, void *gauge,
                     void *stream);
+
+/* How far the packed links are from SU(3): out[0] = max over links of
+ * max_ab |(U U^H - I)_ab|, out[1] = max |det U - 1| (device, 2 FP64, computed
+ * by one workgroup in a fixed order).  Both are at the rounding level of the
+ * precision for links that may use link_rows = 2. */
+int mpmc_gauge_unitarity(const int32_t dims[4], int32_t prec, const void *gauge, double *out, void *stream);
 
 /* canon: device complex128 (N, V, 4, 3) <-> field (prec, field layout). */
 int mpmc_pack_fields(const int32_t dims[4], int32_t prec, mpmc_shape shape, const double *canon,

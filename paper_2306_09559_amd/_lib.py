@@ -36,7 +36,7 @@ c_i32, c_u64, c_f64, c_vp, c_size = ctypes.c_int32, ctypes.c_uint64, ctypes.c_do
 
 class mpmc_lattice(ctypes.Structure):
     _fields_ = [("dims", c_i32 * 4), ("antiperiodic_t", c_i32), ("prec", c_i32), ("kappa", c_f64),
-                ("gauge", c_vp)]
+                ("gauge", c_vp), ("link_rows", c_i32)]
 
 
 class mpmc_shape(ctypes.Structure):
@@ -67,6 +67,7 @@ _sig = {
     "mpmc_build_info": (ctypes.c_char_p, []),
     "mpmc_set_option": (ctypes.c_int, [c_i32, c_i32]),
     "mpmc_counter_add": (ctypes.c_int, [c_vp, c_u64, c_vp]),
+    "mpmc_gauge_unitarity": (ctypes.c_int, [P(c_i32), c_i32, c_vp, c_vp, c_vp]),
     "mpmc_pack_gauge": (ctypes.c_int, [P(c_i32), c_i32, c_vp, c_vp, c_vp]),
     "mpmc_pack_fields": (ctypes.c_int, [P(c_i32), c_i32, mpmc_shape, c_vp, c_vp, c_vp]),
     "mpmc_unpack_fields": (ctypes.c_int, [P(c_i32), c_i32, mpmc_shape, c_vp, c_vp, c_vp]),
@@ -164,6 +165,7 @@ class DeviceLattice:
     antiperiodic_t: bool
     prec: int
     gauge: torch.Tensor
+    link_rows: int = 3          # 2: SU(3) links, row 2 rebuilt in the kernels
 
     @property
     def V(self) -> int:
@@ -172,7 +174,7 @@ class DeviceLattice:
 
     def c(self) -> mpmc_lattice:
         return mpmc_lattice(_dims(self.dims), int(self.antiperiodic_t), int(self.prec), float(self.kappa),
-                            self.gauge.data_ptr())
+                            self.gauge.data_ptr(), int(self.link_rows))
 
 
 @dataclass
@@ -246,6 +248,14 @@ def counter_add(counter: torch.Tensor, increment: int):
     """counter[0] += increment on the device (int64 tensor; capturable)."""
     assert counter.dtype == torch.int64
     _check("mpmc_counter_add", _lib.mpmc_counter_add(_ptr(counter), int(increment), _stream()))
+
+
+def gauge_unitarity(dims, prec: int, gauge: torch.Tensor) -> tuple:
+    """(max |U U^H - I|, max |det U - 1|) over the packed links (synchronises)."""
+    out = torch.empty(2, dtype=torch.float64, device=gauge.device)
+    _check("mpmc_gauge_unitarity", _lib.mpmc_gauge_unitarity(_dims(dims), prec, _ptr(gauge), _ptr(out), _stream()))
+    o = out.cpu().numpy()
+    return float(o[0]), float(o[1])
 
 
 def pack_gauge(dims, prec: int, canon: torch.Tensor, gauge: torch.Tensor):

@@ -63,6 +63,7 @@ int check_lattice(const mpmc_lattice *lat) {
     if (!lat || !valid_dims(lat->dims) || !lat->gauge) return MPMC_EINVAL;
     if (!valid_prec(lat->prec)) return MPMC_EUNSUPPORTED;
     if (lat->antiperiodic_t != 0 && lat->antiperiodic_t != 1) return MPMC_EINVAL;
+    if (lat->link_rows != 0 && lat->link_rows != 2 && lat->link_rows != 3) return MPMC_EINVAL;
     return MPMC_OK;
 }
 
@@ -121,6 +122,12 @@ int mpmc_set_option(int32_t option, int32_t value) {
 int mpmc_counter_add(uint64_t *counter, uint64_t increment, void *stream) {
     if (!counter) return MPMC_EINVAL;
     return counter_add_impl(counter, increment, stream);
+}
+
+int mpmc_gauge_unitarity(const int32_t dims[4], int32_t prec, const void *gauge, double *out, void *stream) {
+    if (!valid_dims(dims) || !gauge || !out) return MPMC_EINVAL;
+    if (!valid_prec(prec)) return MPMC_EUNSUPPORTED;
+    return gauge_unitarity_impl(dims, prec, gauge, out, stream);
 }
 
 int mpmc_pack_gauge(const int32_t dims[4], int32_t prec, const double *canon, void *gauge, void *stream) {

@@ -61,6 +61,28 @@ template <typename T> __device__ __forceinline__ cplx_t<T> axpy_d(double2 a, cpl
 template <typename T> __device__ __forceinline__ cplx_t<T> mul_i(cplx_t<T> a) { return mk<T>(-a.y, a.x); }
 template <typename T> __device__ __forceinline__ cplx_t<T> mul_mi(cplx_t<T> a) { return mk<T>(a.y, -a.x); }
 
+// One link U (row-major, entry (a, b) at gl + (3a + b) * estride + off).
+// two_rows: U is special unitary and only rows 0 and 1 are read; row 2 is
+// rebuilt as the complex conjugate of row 0 x row 1 (for U in SU(3) the
+// rows are orthonormal and det U = 1, so row 2 = conj(r0 x r1) exactly).
+template <typename T>
+__device__ __forceinline__ void load_su3(const char *gl, size_t estride, uint32_t off, bool two_rows,
+                                         cplx_t<T> (&U)[9]) {
+#pragma unroll
+    for (int e = 0; e < 6; ++e) U[e] = *(const cplx_t<T> *)(gl + (size_t)e * estride + off);
+    if (two_rows) {
+        const cplx_t<T> c0 = csub<T>(cmul<T>(U[1], U[5]), cmul<T>(U[2], U[4]));
+        const cplx_t<T> c1 = csub<T>(cmul<T>(U[2], U[3]), cmul<T>(U[0], U[5]));
+        const cplx_t<T> c2 = csub<T>(cmul<T>(U[0], U[4]), cmul<T>(U[1], U[3]));
+        U[6] = mk<T>(c0.x, -c0.y);
+        U[7] = mk<T>(c1.x, -c1.y);
+        U[8] = mk<T>(c2.x, -c2.y);
+    } else {
+#pragma unroll
+        for (int e = 6; e < 9; ++e) U[e] = *(const cplx_t<T> *)(gl + (size_t)e * estride + off);
+    }
+}
+
 // ---------------------------------------------------------------- geometry
 struct Geo {
     int L[4];      // Lx, Ly, Lz, Lt

@@ -29,6 +29,7 @@ template <typename T> struct HopArgs {
     const cplx_t<T> *in;        // input field; unused when the input is noise
     cplx_t<T> *out;
     const cplx_t<T> *gauge;     // [mu][9][V]
+    int two_rows;               // links special unitary: row 2 rebuilt from rows 0, 1
     // step coefficients: t = troots[j] if troots, else (alpha, beta) given
     const double2 *troots;
     int j;
@@ -65,8 +66,11 @@ template <typename T> struct Blk {
     __device__ __forceinline__ cplx_t<T> ld(int c, uint32_t off) const {
         return *(const cplx_t<T> *)(base + (size_t)c * cstride + off);
     }
+    // outputs are read again only by the next launch: stream them past L2
     __device__ __forceinline__ void st(int c, uint32_t off, cplx_t<T> v) const {
-        *(cplx_t<T> *)(const_cast<char *>(base) + (size_t)c * cstride + off) = v;
+        T *p = (T *)(const_cast<char *>(base) + (size_t)c * cstride + off);
+        __builtin_nontemporal_store(v.x, p);
+        __builtin_nontemporal_store(v.y, p + 1);
     }
 };
 
@@ -153,11 +157,10 @@ __device__ __forceinline__ void reconstruct(const cplx_t<T> (&h)[2][3], cplx_t<T
 
 // h <- U h (FWD, U = U_mu(x)) or h <- U^H h (!FWD, U = U_mu(x - mu))
 template <typename T, bool FWD>
-__device__ __forceinline__ void su3_mul(const char *gl, size_t estride, int site, cplx_t<T> (&h)[2][3]) {
+__device__ __forceinline__ void su3_mul(const char *gl, size_t estride, int site, bool two_rows,
+                                        cplx_t<T> (&h)[2][3]) {
     cplx_t<T> U[9];
-    const uint32_t off = (uint32_t)site * (uint32_t)sizeof(cplx_t<T>);
-#pragma unroll
-    for (int e = 0; e < 9; ++e) U[e] = *(const cplx_t<T> *)(gl + (size_t)e * estride + off);
+    load_su3<T>(gl, estride, (uint32_t)site * (uint32_t)sizeof(cplx_t<T>), two_rows, U);
     cplx_t<T> o[2][3];
 #pragma unroll
     for (int sp = 0; sp < 2; ++sp)
@@ -192,7 +195,7 @@ __device__ __forceinline__ void hop_one(const HopArgs<T> &a, const Blk<T> &in, i
     Half<T> h;
     project<T, MU, FWD>(p, h.h);
     // forward: U_mu(x) h ; backward: U_mu(x - mu)^H h
-    su3_mul<T, FWD>(gl, estride, FWD ? s : nb, h.h);
+    su3_mul<T, FWD>(gl, estride, FWD ? s : nb, a.two_rows != 0, h.h);
     reconstruct<T, MU, FWD>(h.h, acc);
 }
 
@@ -468,6 +471,7 @@ template <typename T> static HopArgs<T> base_args(const mpmc_lattice &lat, mpmc_
     a.nblk = t.nblk;
     a.G = t.groups();
     a.gauge = (const cplx_t<T> *)lat.gauge;
+    a.two_rows = lat.link_rows == 2;
     a.kappa = lat.kappa;
     return a;
 }

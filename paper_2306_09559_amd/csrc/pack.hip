@@ -126,6 +126,68 @@ int unpack_fields_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, const
     return last_status();
 }
 
+// Deviation of the links from SU(3): one workgroup strides over all 4V
+// links, each thread keeps its maxima, and a fixed-order tree combines them.
+template <typename T>
+__global__ void __launch_bounds__(1024) k_unitarity(const cplx_t<T> *g, int V, double *out) {
+    __shared__ double red[2][1024];
+    double du = 0.0, dd = 0.0;
+    for (int l = (int)threadIdx.x; l < 4 * V; l += (int)blockDim.x) {
+        const int mu = l / V, s = l % V;
+        double ur[9], ui[9];
+        for (int e = 0; e < 9; ++e) {
+            const cplx_t<T> v = g[(size_t)(mu * 9 + e) * V + s];
+            ur[e] = (double)v.x;
+            ui[e] = (double)v.y;
+        }
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double re = 0.0, im = 0.0;          // (U U^H)_ab = sum_c U_ac conj(U_bc)
+                for (int c = 0; c < 3; ++c) {
+                    re += ur[3 * a + c] * ur[3 * b + c] + ui[3 * a + c] * ui[3 * b + c];
+                    im += ui[3 * a + c] * ur[3 * b + c] - ur[3 * a + c] * ui[3 * b + c];
+                }
+                if (a == b) re -= 1.0;
+                du = fmax(du, sqrt(re * re + im * im));
+            }
+        // det U by the first row's cofactors
+        double dr = 0.0, di = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+            const double mr = ur[3 + c1] * ur[6 + c2] - ui[3 + c1] * ui[6 + c2] - (ur[3 + c2] * ur[6 + c1] - ui[3 + c2] * ui[6 + c1]);
+            const double mi = ur[3 + c1] * ui[6 + c2] + ui[3 + c1] * ur[6 + c2] - (ur[3 + c2] * ui[6 + c1] + ui[3 + c2] * ur[6 + c1]);
+            dr += ur[c] * mr - ui[c] * mi;
+            di += ur[c] * mi + ui[c] * mr;
+        }
+        dd = fmax(dd, sqrt((dr - 1.0) * (dr - 1.0) + di * di));
+    }
+    red[0][threadIdx.x] = du;
+    red[1][threadIdx.x] = dd;
+    __syncthreads();
+    for (int st = (int)blockDim.x / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            red[0][threadIdx.x] = fmax(red[0][threadIdx.x], red[0][threadIdx.x + st]);
+            red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + st]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = red[0][0];
+        out[1] = red[1][0];
+    }
+}
+
+int gauge_unitarity_impl(const int32_t dims[4], int32_t prec, const void *gauge, double *out, void *stream) {
+    const int V = dims[0] * dims[1] * dims[2] * dims[3];
+    if (prec == MPMC_F64)
+        hipLaunchKernelGGL(k_unitarity<double>, dim3(1), dim3(1024), 0, (hipStream_t)stream, (const double2 *)gauge, V,
+                           out);
+    else
+        hipLaunchKernelGGL(k_unitarity<float>, dim3(1), dim3(1024), 0, (hipStream_t)stream, (const float2 *)gauge, V,
+                           out);
+    return last_status();
+}
+
 int counter_add_impl(uint64_t *counter, uint64_t inc, void *stream) {
     hipLaunchKernelGGL(k_counter_add, dim3(1), dim3(64), 0, (hipStream_t)stream, counter, inc);
     return last_status();

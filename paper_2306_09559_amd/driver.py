@@ -163,23 +163,34 @@ def _poly_value(roots: krylov.RootSet, comps: Dict[tuple, krylov.OuterRoots], p,
 
 def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optional[int] = None,
           arnoldi_m: int = 90, nev: int = 40, verbose: bool = False,
-          reuse: Optional["LatticeRun"] = None, gmres_m: int = 30, solve_tol: float = 1e-6) -> LatticeRun:
+          reuse: Optional["LatticeRun"] = None, gmres_m: int = 30, solve_tol: float = 1e-6,
+          two_row_links: bool = True) -> LatticeRun:
     """Set up a lattice workload: links, GMRES roots, PP-Arnoldi deflation,
     outer roots of composite polynomials (FP64 on the GPU, Sec. 5 setup
     step 2) and the level descriptors in precision `prec`.  With `reuse`,
     the roots and eigen-triplets of an earlier set-up of the same workload
     are taken over (the set-up is always FP64).  A top level with hi = SOLVE
     gets a deflated PP-GMRES(gmres_m) solver (FP32 inner cycles when prec is
-    FP32, FP64 residual) converging to solve_tol (rtolle)."""
+    FP32, FP64 residual) converging to solve_tol (rtolle).  Links that are
+    SU(3) to 1e-12 are read as two rows (two_row_links)."""
     t0 = time.perf_counter()
     U = synth.gauge_links(cfg.dims, cfg.eps, cfg.seed_links)
     canon = torch.from_numpy(U).cuda()
     V = cfg.volume
 
+    # SU(3) links need only two rows in the kernels (row 2 = conj(row 0 x row 1))
+    g64 = torch.empty(36 * V, dtype=torch.complex128, device="cuda")
+    L.pack_gauge(cfg.dims, L.F64, canon, g64)
+    du, dd = L.gauge_unitarity(cfg.dims, L.F64, g64)
+    link_rows = 2 if (two_row_links and max(du, dd) <= 1e-12) else 3
+
     def lattice(p):
-        g = torch.empty(36 * V, dtype=L.complex_dtype(p), device="cuda")
-        L.pack_gauge(cfg.dims, p, canon, g)
-        return L.DeviceLattice(tuple(cfg.dims), cfg.kappa, cfg.antiperiodic_t, p, g)
+        if p == L.F64:
+            g = g64
+        else:
+            g = torch.empty(36 * V, dtype=L.complex_dtype(p), device="cuda")
+            L.pack_gauge(cfg.dims, p, canon, g)
+        return L.DeviceLattice(tuple(cfg.dims), cfg.kappa, cfg.antiperiodic_t, p, g, link_rows)
 
     polys = [p for lv in cfg.levels for p in (lv.hi, lv.lo) if p is not None and p != SOLVE]
     comp_keys = sorted({p for p in polys if isinstance(p, tuple)})

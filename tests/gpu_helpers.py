@@ -12,14 +12,14 @@ def lib():
     return _lib
 
 
-def device_lattice(dims, kappa, eps, seed, antiperiodic=True, prec=0):
+def device_lattice(dims, kappa, eps, seed, antiperiodic=True, prec=0, link_rows=3):
     L = lib()
     U = synth.unit_links(dims) if eps == 0 else synth.gauge_links(dims, eps, seed)
     canon = torch.from_numpy(U).cuda()
     V = int(np.prod(dims))
     gauge = torch.empty(36 * V, dtype=L.complex_dtype(prec), device="cuda")
     L.pack_gauge(dims, prec, canon, gauge)
-    dl = L.DeviceLattice(tuple(dims), kappa, antiperiodic, prec, gauge)
+    dl = L.DeviceLattice(tuple(dims), kappa, antiperiodic, prec, gauge, link_rows)
     ol = oracle.Lattice(dims, kappa, U, antiperiodic)
     return dl, ol
 

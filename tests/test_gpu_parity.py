@@ -439,3 +439,72 @@ def test_sweep_matches_oracle_and_streaming(dims, ap, prec, nrhs, rb, z4):
     tol = 1e-12 if prec == 0 else 8 * deg * 50 * U32
     for opt in (1, 0):
         assert np.max(np.abs(out[opt] - ref) / np.abs(ref)) < tol, opt
+
+
+# ------------------------------------------------------------------ SU(3) links read as two rows
+@pytest.mark.parametrize("dims,ap", [((4, 4, 4, 4), True), ((8, 8, 8, 2), False)])
+def test_two_row_links_match_oracle(dims, ap):
+    """link_rows = 2 (row 2 rebuilt as conj(row 0 x row 1)) gives the full-link
+    operator to FP64 rounding for SU(3) links: A x, and scalar-mode
+    polynomials on both the t-sweep and the streaming kernel."""
+    L = lib()
+    dl, ol = device_lattice(dims, 0.14, 0.5, 77, ap, 0, link_rows=2)
+    V = dl.V
+    X = synth.random_fields(8, V, 3).reshape(8, 12 * V)
+    x = pack(dims, X, 4, 0)
+    y = L.empty_field(V, 8, 4, 0)
+    L.wilson_apply(dl, x, y)
+    Y = unpack(dims, y, 0)
+    R = ol.apply(X)
+    for r in range(8):
+        assert rel(Y[r], R[r]) < 1e-13
+    t = krylov.gmres_polys(ol.apply, synth.gaussian_start(ol.n, 5), [9]).inv_roots[9]
+    B = oracle.z4(5, 6, 7, 0, 16, V)
+    _, ref = ol.poly_apply(t, B)
+    for sweep in (1, 0):
+        L.set_option(L.OPT_PLANE_SWEEP, sweep)
+        poly = L.DevicePoly(dev_c128(t))
+        bhy = torch.empty(16, dtype=torch.complex128, device="cuda")
+        ws = L.workspace(L.poly_workspace_size(dl, poly, 16, 8))
+        L.poly_apply(dl, poly, 16, 8, None, L.Noise(5, 6, 7, 0), None, bhy, ws)
+        assert np.max(np.abs(bhy.cpu().numpy() - ref) / np.abs(ref)) < 1e-12
+    L.set_option(L.OPT_PLANE_SWEEP, 1)
+    # FP32 two-row links: the FP32 operator bound
+    dl32, _ = device_lattice(dims, 0.14, 0.5, 77, ap, 1, link_rows=2)
+    x32 = pack(dims, X, 4, 1)
+    y32 = L.empty_field(V, 8, 4, 1)
+    L.wilson_apply(dl32, x32, y32)
+    Y32 = unpack(dims, y32, 1)
+    for r in range(8):
+        assert rel(Y32[r], R[r]) < 1e-6
+
+
+def test_gauge_unitarity_check():
+    L = lib()
+    dims = (4, 4, 2, 4)
+    U = synth.gauge_links(dims, 0.5, 8)
+    V = int(np.prod(dims))
+    for scale, prec in ((1.0, 0), (1.01, 0), (1.0, 1)):
+        Us = U * scale
+        g = torch.empty(36 * V, dtype=L.complex_dtype(prec), device="cuda")
+        L.pack_gauge(dims, prec, torch.from_numpy(np.ascontiguousarray(Us)).cuda(), g)
+        du, dd = L.gauge_unitarity(dims, prec, g)
+        M = Us.reshape(-1, 3, 3)
+        if prec == 1:
+            M = M.astype(np.complex64).astype(np.complex128)
+        want_u = np.max(np.abs(M @ np.conj(np.swapaxes(M, 1, 2)) - np.eye(3)))
+        want_d = np.max(np.abs(np.linalg.det(M) - 1.0))
+        assert abs(du - want_u) <= 1e-12 + 1e-9 * want_u and abs(dd - want_d) <= 1e-12 + 1e-9 * want_d
+        if scale == 1.0:
+            assert max(du, dd) < (1e-13 if prec == 0 else 1e-6)
+        else:
+            assert abs(du - (1.01 ** 2 - 1)) < 1e-9 and abs(dd - (1.01 ** 3 - 1)) < 1e-9
+
+
+def test_link_rows_validated():
+    L = lib()
+    dl, _ = device_lattice((2, 2, 2, 4), 0.1, 0.5, 1, True, 0, link_rows=5)
+    x = L.empty_field(dl.V, 1, 1, 0)
+    y = L.empty_field(dl.V, 1, 1, 0)
+    with pytest.raises(L.MpmcError):
+        L.wilson_apply(dl, x, y)
