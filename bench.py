@@ -347,7 +347,7 @@ def main():
             "bound_met": all(abs(a["estimate"] - b["estimate"]) <= 0.1 * t for a, b, t in zip(est32, est, targets)),
         }
         # mixed + batched: autotuned shapes, every level's batch replayed as a HIP graph
-        tune = autotune(run32, reps=2, use_cache=False)
+        tune = autotune(run32, reps=4, use_cache=False)
         gps = graph_level_seconds(run32, args.steps)
         gs = GraphStep([run32], parallel=False)
         gs.replay()

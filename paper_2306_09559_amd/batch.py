@@ -160,9 +160,13 @@ class TuneResult:
     cached: Dict[int, bool] = field(default_factory=dict)
 
 
-def autotune(run: LatticeRun, reps: int = 3, use_cache: bool = True, cache_path: Optional[str] = None) -> TuneResult:
+def autotune(run: LatticeRun, reps: int = 3, use_cache: bool = True, cache_path: Optional[str] = None,
+             keep_within: float = 0.03) -> TuneResult:
     """Pick (rb, sweep) per polynomial level of `run` by timing; applies the
-    choice to the run and resets its accumulators."""
+    choice to the run and resets its accumulators.  The level's current shape
+    is kept unless another candidate is faster by more than keep_within (a
+    shape the kernel ignores, such as rb under the t-sweep, would otherwise
+    be chosen by timing noise)."""
     path = cache_path or _CACHE
     cache = {}
     if use_cache and os.path.exists(path):
@@ -183,12 +187,18 @@ def autotune(run: LatticeRun, reps: int = 3, use_cache: bool = True, cache_path:
             res.cached[li] = True
             continue
         best, times = None, {}
+        current = (run.level_rb(li), lv.sweep)
+        t_current = None
         for rb, sw in _candidates(run, li):
             run.set_level_shape(li, rb, sw)
             t = _time_level(run, li, reps)
             times[f"rb{rb}{'-sweep' if sw else ''}"] = t
+            if (rb, sw) == current:
+                t_current = t
             if best is None or t < best[0]:
                 best = (t, rb, sw)
+        if t_current is not None and t_current <= best[0] * (1.0 + keep_within):
+            best = (t_current,) + current
         _, rb, sw = best
         run.set_level_shape(li, rb, sw)
         res.choice[li] = (rb, sw)

@@ -266,8 +266,10 @@ __device__ __forceinline__ void dot_acc(const cplx_t<T> (&b)[12], const cplx_t<T
 }  // namespace
 
 // IN_Z4: the input is the noise itself; FIRST: also accumulate t_0 b^H w
-// (first Newton step); BFIELD: the dot vector b is a field, not the noise
-template <typename T, bool IN_Z4, bool DOT, bool FIRST, bool BFIELD>
+// (first Newton step); BFIELD: the dot vector b is a field, not the noise;
+// TWO: the links are read as two rows (SU(3), row 2 rebuilt) -- a template
+// parameter because a run-time flag cost 6% (FP64) and 14% (FP32) per launch
+template <typename T, bool IN_Z4, bool DOT, bool FIRST, bool BFIELD, bool TWO>
 __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
     using C = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -283,7 +285,7 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
     const int qyp = y + 1 == Ly ? q - y * Lx : q + Lx, qym = y == 0 ? q + (Ly - 1) * Lx : q - Lx;
     const int qzp = z + 1 == Lz ? q - z * Lx * Ly : q + Lx * Ly, qzm = z == 0 ? q + (Lz - 1) * Lx * Ly : q - Lx * Ly;
     const size_t estride = V * sizeof(C);
-    const bool two = a.two_rows != 0;
+    constexpr bool two = TWO;
     const char *g0 = (const char *)a.gauge;
     const char *gx = g0, *gy = g0 + 9 * estride, *gz = g0 + 18 * estride, *gt = g0 + 27 * estride;
 
@@ -493,24 +495,34 @@ int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, int n, const double *
     a.rb_b = sh.rb;
     a.part = part;
     const size_t lds = (size_t)a.P * 18 * sizeof(cplx_t<T>);
-    // kernels of this precision: (noise input, first), (field, first), (field, later),
-    // each with the dot vector as noise or as a field
-    const void *kern[2][3] = {
-        {(const void *)k_sweep<T, true, true, true, false>, (const void *)k_sweep<T, false, true, true, false>,
-         (const void *)k_sweep<T, false, true, false, false>},
-        {(const void *)k_sweep<T, true, true, true, true>, (const void *)k_sweep<T, false, true, true, true>,
-         (const void *)k_sweep<T, false, true, false, true>}};
+    // kernels of this precision: [link rows 3 | 2][dot vector noise | field]
+    // [(noise input, first), (field, first), (field, later)]
+    const void *kern[2][2][3] = {
+        {{(const void *)k_sweep<T, true, true, true, false, false>,
+          (const void *)k_sweep<T, false, true, true, false, false>,
+          (const void *)k_sweep<T, false, true, false, false, false>},
+         {(const void *)k_sweep<T, true, true, true, true, false>,
+          (const void *)k_sweep<T, false, true, true, true, false>,
+          (const void *)k_sweep<T, false, true, false, true, false>}},
+        {{(const void *)k_sweep<T, true, true, true, false, true>,
+          (const void *)k_sweep<T, false, true, true, false, true>,
+          (const void *)k_sweep<T, false, true, false, false, true>},
+         {(const void *)k_sweep<T, true, true, true, true, true>,
+          (const void *)k_sweep<T, false, true, true, true, true>,
+          (const void *)k_sweep<T, false, true, false, true, true>}}};
     static bool attr_set[2] = {false, false};
     const int pi = sizeof(T) == 8 ? 0 : 1;
     if (!attr_set[pi]) {
-        for (int bf = 0; bf < 2; ++bf)
-            for (int v = 0; v < 3; ++v)
-                if (hipFuncSetAttribute(kern[bf][v], hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) !=
-                    hipSuccess)
-                    return MPMC_EHIP;
+        for (int tw = 0; tw < 2; ++tw)
+            for (int bf = 0; bf < 2; ++bf)
+                for (int v = 0; v < 3; ++v)
+                    if (hipFuncSetAttribute(kern[tw][bf][v], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            160 * 1024) != hipSuccess)
+                        return MPMC_EHIP;
         attr_set[pi] = true;
     }
     const int bf = bvec != nullptr ? 1 : 0;
+    const int tw = lat.link_rows == 2 ? 1 : 0;
     const int d = n - 1;
     for (int j = 0; j < d; ++j) {
         a.j = j;
@@ -522,7 +534,7 @@ int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, int n, const double *
         a.bhy = (j == d - 1) ? bhy : nullptr;
         const int v = first_step ? (x_is_noise ? 0 : 1) : 2;
         void *args[] = {&a};
-        if (hipLaunchKernel(kern[bf][v], dim3(sh.nrhs), dim3(a.P), args, lds, (hipStream_t)stream) != hipSuccess)
+        if (hipLaunchKernel(kern[tw][bf][v], dim3(sh.nrhs), dim3(a.P), args, lds, (hipStream_t)stream) != hipSuccess)
             return MPMC_EHIP;
         if (hipGetLastError() != hipSuccess) return MPMC_EHIP;
     }
