@@ -366,6 +366,23 @@ def main():
         }
         out["time_to_eps_s"] = {"f64": out["time_to_eps_s"], "mixed": out["mixed"]["time_to_eps_s"],
                                 "mixed_batched": round(t_mb, 4)}
+        # the measured time to eps: the multilevel Monte Carlo of Sec. 5 step 3 run to
+        # completion (levels top first, each to its share of eps at its check points)
+        out["adaptive"] = {}
+        for name, r in (("f64", run), ("mixed", run32)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = driver.run_to_tolerance(r, eps)
+            torch.cuda.synchronize()
+            tot = time.perf_counter() - t0
+            err = float(np.sqrt(sum(x.stderr ** 2 for x in res)))
+            out["adaptive"][name] = {
+                "seconds": round(tot, 4), "stderr": round(err, 4), "eps": eps,
+                "trace_estimate": [round(sum(x.estimate for x in res).real, 3), round(sum(x.estimate for x in res).imag, 3)],
+                "levels": [{"n": x.n, "drawn": x.drawn, "stderr": round(x.stderr, 4), "target": round(x.target, 4),
+                            "seconds": round(x.seconds, 4)} for x in res]}
+        out["adaptive"]["speedup_mixed_vs_f64"] = round(out["adaptive"]["f64"]["seconds"] /
+                                                        out["adaptive"]["mixed"]["seconds"], 3)
     if not args.no_extra:
         out["batched_lattices"] = batched_c5(args.steps)
         out["top_level"] = top_level_c3()

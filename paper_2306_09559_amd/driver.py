@@ -299,3 +299,88 @@ def level_targets(eps: float, stderrs) -> List[float]:
         out.append(float(np.sqrt(max(eps * eps - e2, 0.0)) / np.sqrt(nl - l)))
         e2 += float(stderrs[l]) ** 2
     return out
+
+
+def check_points(level: int, nmax: int) -> List[int]:
+    """Sample counts at which a level's standard error is checked (Sec. 5
+    step 3): the first Monte Carlo from 2 noises after every noise, the second
+    at 3 and then every 3, every later one at 6 and then every 3."""
+    if level == 0:
+        return list(range(2, nmax + 1))
+    if level == 1:
+        return list(range(3, nmax + 1, 3))
+    return list(range(6, nmax + 1, 3))
+
+
+def stopping_index(s: np.ndarray, target: float, level: int, start: int = 0) -> Optional[int]:
+    """Smallest check point n > start (within len(s)) at which the standard
+    error of the first n complex samples, sqrt(sum |s - mean|^2 / (n-1) / n),
+    is at most target; None if there is none yet."""
+    s = np.asarray(s, dtype=np.complex128)
+    if len(s) == 0:
+        return None
+    s = s - s[0]           # the variance is shift-invariant; the shift keeps the running sums small
+    c1 = np.cumsum(s)
+    c2 = np.cumsum(np.abs(s) ** 2)
+    for n in check_points(level, len(s)):
+        if n <= start:
+            continue
+        mean = c1[n - 1] / n
+        m2 = max(c2[n - 1] - n * abs(mean) ** 2, 0.0)
+        if np.sqrt(m2 / (n - 1) / n) <= target:
+            return n
+    return None
+
+
+@dataclass
+class AdaptiveLevel:
+    n: int                 # samples the estimate uses (the stopping point)
+    drawn: int             # samples computed on the GPU (whole batches)
+    estimate: complex
+    stderr: float
+    target: float
+    seconds: float
+
+
+def run_to_tolerance(run: LatticeRun, eps: float, first_batch: int = 32,
+                     max_samples: int = 1 << 20) -> List[AdaptiveLevel]:
+    """The multilevel Monte Carlo of Sec. 5 step 3 on the GPU: levels top
+    first, each drawing batches of Z4 samples until its standard error falls
+    to its share of eps (level_targets, given the errors of the levels before
+    it) at one of its check points.  Batches start at first_batch and double
+    up to the level's configured batch (a solve level always draws its full
+    batch).  The estimate of a level uses exactly the samples up to its
+    stopping point, as a one-at-a-time draw would; the rest of the last batch
+    is discarded.  Returns one AdaptiveLevel per level."""
+    out: List[AdaptiveLevel] = []
+    errs: List[float] = []
+    nl = len(run.levels)
+    run.reset()
+    for li, lv in enumerate(run.levels):
+        target = level_targets(eps, errs + [0.0] * (nl - len(errs)))[li]
+        N = run.cfg.levels[li].samples
+        rb = run.level_rb(li)
+        batch = N if lv.solver is not None else max(rb, min(N, (first_batch // rb) * rb or rb))
+        chunks: List[np.ndarray] = []
+        have = 0
+        stop = None
+        t0 = time.perf_counter()
+        while stop is None and have < max_samples:
+            run.draw(li, batch)
+            S = lv.samples[:batch].cpu().numpy()
+            chunks.append(S[:, 0] + 1j * S[:, 1])
+            allv = np.concatenate(chunks)
+            stop = stopping_index(allv, target, li, start=0 if have == 0 else have)
+            have += batch
+            if lv.solver is None and batch < N:
+                batch = min(N, 2 * batch)
+        allv = np.concatenate(chunks)
+        n = stop if stop is not None else len(allv)
+        sv = allv[:n]
+        mean = complex(sv.mean())
+        var = float(np.sum(np.abs(sv - mean) ** 2) / (n - 1)) if n > 1 else float("inf")
+        corr = complex(np.sum(lv.c)) if lv.c is not None else 0.0
+        se = float(np.sqrt(var / n))
+        errs.append(se)
+        out.append(AdaptiveLevel(n, have, mean + corr, se, float(target), time.perf_counter() - t0))
+    return out

@@ -71,3 +71,21 @@ def test_level_targets_match_oracle(pk):
     # two levels: eps/sqrt(2), then what the first left
     assert np.allclose(driver.level_targets(1.0, [0.6, 0.1]), [1 / np.sqrt(2), 0.8])
     assert driver.level_targets(1.0, [1.5, 0.1])[1] == 0.0
+
+
+def test_stopping_rule_matches_oracle(pk):
+    """The driver's check cadence and stopping point agree with the oracle's
+    check_points and level_estimate (Sec. 5 step 3)."""
+    from paper_2306_09559_amd import driver
+    from oracle import estimator
+    rng = np.random.default_rng(3)
+    for level in (0, 1, 2, 3):
+        assert driver.check_points(level, 40) == estimator.check_points(min(level, 2) + 1, 40)
+        s = 5.0 + rng.standard_normal(300) + 1j * rng.standard_normal(300)
+        for target in (0.5, 0.2, 0.09):
+            n = driver.stopping_index(s, target, level)
+            ok = [m for m in estimator.check_points(min(level, 2) + 1, len(s))
+                  if estimator.level_estimate(s[:m]).stderr <= target]
+            assert n == (ok[0] if ok else None)
+            if n is not None and n > 2:
+                assert estimator.level_estimate(s[:n]).stderr <= target
