@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-bulk (mixed) comparison run")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched independent lattices and the top-level solve measurements")
+    ap.add_argument("--c4", action="store_true",
+                    help="also run one step of the 24^3x48 four-level workload (set-up ~50 s, ~190 GiB)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -138,7 +140,8 @@ def timed_steps(run, steps, stream):
     for k in range(steps):
         for i in range(nl):
             ev[k][i][0].record(stream)
-            run.draw(i, run.cfg.levels[i].samples)
+            for _ in range(run.batches(i)):
+                run.draw(i, run.levels[i].batch)
             ev[k][i][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -254,6 +257,39 @@ def top_level_c3():
                       "rtolle": 1e-6},
             "estimate": [round(e["estimate"].real, 4), round(e["estimate"].imag, 4)], "stderr": round(e["stderr"], 4),
             "target_stderr": round(0.0005 * C3.volume / 3 ** 0.5, 3)}
+
+
+def c4_step():
+    """One step of the 24^3x48 workload (n = 7.96M, FP32 bulk): levels
+    Tr(p_1 - p_60), Tr(p_60 - p_15), Tr(p_15 - p_4) deflated and Tr(p_4), with
+    32 / 128 / 512 / 2048 samples drawn in batches of at most 256 vectors, the
+    whole step replayed as one HIP graph."""
+    import time
+    import torch
+    from paper_2306_09559_amd import _lib as L
+    from paper_2306_09559_amd import driver
+    from paper_2306_09559_amd.batch import GraphStep
+    from synth.configs import C4
+    t0 = time.perf_counter()
+    run = driver.build(C4, prec=L.F32, rb=16, max_batch=256, arnoldi_m=200, nev=160)
+    setup = time.perf_counter() - t0
+    gs = GraphStep([run], parallel=False)
+    gs.replay()
+    torch.cuda.synchronize()
+    gs.reset()
+    t0 = time.perf_counter()
+    gs.replay()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    est = run.estimates()
+    return {"workload": "24^3x48 n=7962624, kappa=0.15, eps=0.5 links; levels (20x15 composite)-p60, p60-p15, "
+                        "p15-p4 deflated (k=%d accepted of 160 candidates), p4; 32/128/512/2048 samples"
+                        % run.defl.device.k,
+            "prec": "f32", "setup_s": round(setup, 1), "graph_step_s": round(dt, 3),
+            "mvp_rhs_per_step": run.mvp_rhs_per_step(), "GBps": round(run.bytes_per_step() / dt / 1e9, 1),
+            "levels": [{"estimate": [round(e["estimate"].real, 2), round(e["estimate"].imag, 2)],
+                        "stderr": round(e["stderr"], 3), "n": e["n"]} for e in est],
+            "eps": 0.0005 * C4.volume}
 
 
 def main():
@@ -386,6 +422,8 @@ def main():
     if not args.no_extra:
         out["batched_lattices"] = batched_c5(args.steps)
         out["top_level"] = top_level_c3()
+    if args.c4:
+        out["c4"] = c4_step()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(C2, args.prec)
     if args.calibrate_copy:

@@ -148,6 +148,14 @@ const char *mpmc_build_info(void);
 enum { MPMC_OPT_PLANE_SWEEP = 1 };
 int mpmc_set_option(int32_t option, int32_t value);
 
+/* Which t-sweep a scalar-mode polynomial on this lattice and batch would
+ * use (host only, enqueues nothing).  out (host, 8 int32): [0] 1 if a sweep
+ * applies, [1] 1 if the xyz-plane is cut into blocks with a halo in LDS (FP32
+ * lattices whose plane exceeds one workgroup), [2..4] block extents in x, y,
+ * z, [5] sites per block (= workgroup size), [6] halo sites, [7] blocks per
+ * plane. */
+int mpmc_sweep_plan(const mpmc_lattice *lat, mpmc_shape shape, int32_t *out);
+
 /* *counter += increment, enqueued on `stream` as a one-thread kernel (plain
  * vector store; capturable in a HIP graph, unlike a memset or memcpy node).
  * counter: device, caller-owned. */

@@ -67,6 +67,7 @@ _sig = {
     "mpmc_build_info": (ctypes.c_char_p, []),
     "mpmc_set_option": (ctypes.c_int, [c_i32, c_i32]),
     "mpmc_counter_add": (ctypes.c_int, [c_vp, c_u64, c_vp]),
+    "mpmc_sweep_plan": (ctypes.c_int, [P(mpmc_lattice), mpmc_shape, P(c_i32)]),
     "mpmc_gauge_unitarity": (ctypes.c_int, [P(c_i32), c_i32, c_vp, c_vp, c_vp]),
     "mpmc_pack_gauge": (ctypes.c_int, [P(c_i32), c_i32, c_vp, c_vp, c_vp]),
     "mpmc_pack_fields": (ctypes.c_int, [P(c_i32), c_i32, mpmc_shape, c_vp, c_vp, c_vp]),
@@ -244,6 +245,15 @@ def workspace(nbytes: int, device="cuda") -> torch.Tensor:
 
 
 # ------------------------------------------------------------------ entry points
+def sweep_plan(lat: "DeviceLattice", nrhs: int, rb: int) -> dict:
+    """The t-sweep a scalar-mode polynomial would use on this lattice and batch."""
+    out = (c_i32 * 8)()
+    L = lat.c()
+    _check("mpmc_sweep_plan", _lib.mpmc_sweep_plan(ctypes.byref(L), mpmc_shape(nrhs, rb), out))
+    v = list(out)
+    return dict(ok=bool(v[0]), halo=bool(v[1]), block=tuple(v[2:5]), sites=v[5], halo_sites=v[6], blocks=v[7])
+
+
 def counter_add(counter: torch.Tensor, increment: int):
     """counter[0] += increment on the device (int64 tensor; capturable)."""
     assert counter.dtype == torch.int64

@@ -35,7 +35,8 @@ from .driver import LatticeRun
 class _Item:
     run: LatticeRun
     level: int
-    nsamples: int
+    nsamples: int          # vectors per batch
+    repeats: int           # batches per replay
     counter: torch.Tensor
 
 
@@ -55,8 +56,11 @@ class GraphStep:
             for li, lv in enumerate(run.levels):
                 if lv.solver is not None or (sel is not None and (ri, li) not in sel):
                     continue
-                n = (batch or {}).get((ri, li), run.cfg.levels[li].samples)
-                row.append(_Item(run, li, n, torch.zeros(1, dtype=torch.int64, device="cuda")))
+                if batch is not None and (ri, li) in batch:
+                    n, reps = batch[(ri, li)], 1
+                else:
+                    n, reps = lv.batch, run.batches(li)
+                row.append(_Item(run, li, n, reps, torch.zeros(1, dtype=torch.int64, device="cuda")))
             self.items.append(row)
         self.replays = 0
         self._side = [torch.cuda.Stream() for _ in self.runs] if parallel else []
@@ -77,8 +81,9 @@ class GraphStep:
             # the sample index is the counter alone: replay k draws samples k*N .. k*N+N-1
             nz = L.Noise(it.run.cfg.seed_noise, it.run.cfg.lattice_id, it.run.levels[it.level].index, 0,
                          it.counter)
-            it.run.enqueue(it.level, it.nsamples, nz)
-            L.counter_add(it.counter, it.nsamples)
+            for _ in range(it.repeats):
+                it.run.enqueue(it.level, it.nsamples, nz)
+                L.counter_add(it.counter, it.nsamples)
 
     def _enqueue_all(self, main: torch.cuda.Stream):
         if not self.parallel:
@@ -108,7 +113,8 @@ class GraphStep:
         self.replays += times
 
     def samples_drawn(self) -> Dict[Tuple[int, int], int]:
-        return {(ri, it.level): it.nsamples * self.replays for ri, row in enumerate(self.items) for it in row}
+        return {(ri, it.level): it.nsamples * it.repeats * self.replays
+                for ri, row in enumerate(self.items) for it in row}
 
 
 # ------------------------------------------------------------------ autotuner
@@ -129,7 +135,7 @@ def _key(run: LatticeRun, level: int) -> str:
 
 
 def _candidates(run: LatticeRun, level: int) -> List[Tuple[int, bool]]:
-    N = run.cfg.levels[level].samples
+    N = run.levels[level].batch
     rbs = [rb for rb in (1, 2, 4, 8, 16, 32) if N % rb == 0]
     P = run.cfg.dims[0] * run.cfg.dims[1] * run.cfg.dims[2]
     csz = 16 if run.prec == L.F64 else 8
@@ -141,7 +147,7 @@ def _candidates(run: LatticeRun, level: int) -> List[Tuple[int, bool]]:
 
 
 def _time_level(run: LatticeRun, level: int, reps: int) -> float:
-    N = run.cfg.levels[level].samples
+    N = run.levels[level].batch
     s = torch.cuda.current_stream()
     run.draw(level, N)                 # warm-up
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

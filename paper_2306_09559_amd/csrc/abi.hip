@@ -130,6 +130,15 @@ int mpmc_gauge_unitarity(const int32_t dims[4], int32_t prec, const void *gauge,
     return gauge_unitarity_impl(dims, prec, gauge, out, stream);
 }
 
+int mpmc_sweep_plan(const mpmc_lattice *lat, mpmc_shape shape, int32_t *out) {
+    MPMC_TRY(check_lattice(lat));
+    if (!valid_shape(shape) || !out) return MPMC_EINVAL;
+    const SweepPlan p = sweep_plan(*lat, shape);
+    const int32_t v[8] = {p.ok ? 1 : 0, p.halo ? 1 : 0, p.B[0], p.B[1], p.B[2], p.Pb, p.Hb, p.nbp};
+    for (int i = 0; i < 8; ++i) out[i] = v[i];
+    return MPMC_OK;
+}
+
 int mpmc_pack_gauge(const int32_t dims[4], int32_t prec, const double *canon, void *gauge, void *stream) {
     if (!valid_dims(dims) || !canon || !gauge) return MPMC_EINVAL;
     if (!valid_prec(prec)) return MPMC_EUNSUPPORTED;

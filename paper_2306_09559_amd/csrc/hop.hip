@@ -578,10 +578,12 @@ int poly_apply_t(const mpmc_lattice &lat, const mpmc_poly &poly, mpmc_shape sh, 
     double2 *part = bhy ? (double2 *)ws.part : nullptr;
     const FieldTiling t = make_tiling(lat.dims[0] * lat.dims[1] * lat.dims[2] * lat.dims[3], sh.nrhs, sh.rb);
     int st;
-    if (poly.n_out == 0 && y == nullptr && bhy != nullptr && poly.n_in >= 2 && g_opt_sweep && sweep_fits(lat)) {
-        // scalar mode on a lattice whose xyz-plane fits one workgroup: t-sweep
-        return sweep_newton_t<T>(lat, sh, poly.n_in, poly.inv_roots_in, x, x_noise, bvec, key, first, off, part,
-                                 (double2 *)bhy, ws.f[0], ws.f[1], stream);
+    if (poly.n_out == 0 && y == nullptr && bhy != nullptr && poly.n_in >= 2 && g_opt_sweep) {
+        // scalar mode: t-sweep over xyz-blocks when the lattice admits one
+        const SweepPlan plan = sweep_plan(lat, sh);
+        if (plan.ok)
+            return sweep_newton_t<T>(lat, sh, plan, poly.n_in, poly.inv_roots_in, x, x_noise, bvec, key, first, off,
+                                     part, (double2 *)bhy, ws.f[0], ws.f[1], stream);
     }
     if (poly.n_out == 0) {
         st = newton_t<T>(lat, sh, poly.n_in, poly.inv_roots_in, x, x_noise, bvec, key, first, off, y, part, ws.f[0],

@@ -30,13 +30,20 @@ template <typename T>
 int residual_apply_t(const mpmc_lattice &, mpmc_shape, const void *x, const void *b, uint64_t key, uint64_t first,
                      const uint64_t *off,
                      void *out, void *stream);
-// t-sweep Newton steps (plane per workgroup); see sweep.hip
-bool sweep_fits(const mpmc_lattice &lat);
+// t-sweep Newton steps (an xyz-block per workgroup); see sweep.hip
+struct SweepPlan {
+    bool ok = false;       // the sweep applies to this lattice and batch
+    bool halo = false;     // blocks smaller than the plane, with a halo in LDS (FP32)
+    int B[3] = {0, 0, 0};  // block extents in x, y, z
+    int Pb = 0, Hb = 0;    // block sites (= workgroup size) and halo sites
+    int nbp = 1;           // blocks per plane
+    size_t lds = 0;        // dynamic LDS bytes
+};
+SweepPlan sweep_plan(const mpmc_lattice &lat, mpmc_shape sh);
 template <typename T>
-int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, int n, const double *troots, const void *x, bool x_is_noise,
-                   const void *bvec, uint64_t key, uint64_t first, const uint64_t *off, double2 *part, double2 *bhy,
-                   void *w0, void *w1,
-                   void *stream);
+int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, const SweepPlan &plan, int n, const double *troots,
+                   const void *x, bool x_is_noise, const void *bvec, uint64_t key, uint64_t first, const uint64_t *off,
+                   double2 *part, double2 *bhy, void *w0, void *w1, void *stream);
 
 // process-wide options (mpmc_set_option)
 extern int g_opt_sweep;

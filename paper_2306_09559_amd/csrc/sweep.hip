@@ -37,8 +37,11 @@ template <typename T> struct SweepArgs {
     const cplx_t<T> *bvec;     // dot vector field (layout rb_b), or nullptr
     int rb_b;
     double2 *part;             // N partial sums, one per vector
-    double2 *bhy;              // final sums (last step), or nullptr
+    double2 *bhy;              // final sums (last step, whole-plane blocks only), or nullptr
     int dot_first;
+    // xyz-blocks (HALO): block extents, sites, halo sites, blocks per plane
+    int B[3];
+    int Pb, Hb, nbp;
 };
 
 namespace {
@@ -268,22 +271,91 @@ __device__ __forceinline__ void dot_acc(const cplx_t<T> (&b)[12], const cplx_t<T
 // IN_Z4: the input is the noise itself; FIRST: also accumulate t_0 b^H w
 // (first Newton step); BFIELD: the dot vector b is a field, not the noise;
 // TWO: the links are read as two rows (SU(3), row 2 rebuilt) -- a template
-// parameter because a run-time flag cost 6% (FP64) and 14% (FP32) per launch
-template <typename T, bool IN_Z4, bool DOT, bool FIRST, bool BFIELD, bool TWO>
+// parameter because a run-time flag cost 6% (FP64) and 14% (FP32) per launch;
+// HALO: a workgroup owns an xyz-block of the plane (the plane is too large
+// for one workgroup's LDS) and stages a one-site halo of the neighbouring
+// blocks next to it; without HALO the block is the whole plane and the x, y,
+// z neighbours wrap inside it.
+template <typename T, bool IN_Z4, bool DOT, bool FIRST, bool BFIELD, bool TWO, bool HALO>
 __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
     using C = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     C *lds = reinterpret_cast<C *>(smem);
-    const int r = (int)blockIdx.x;
-    const int q = (int)threadIdx.x;               // site within the plane
     const int P = a.P, Lt = a.L[3];
-    const size_t V = (size_t)a.V;
-    const int x = q % a.L[0], y = (q / a.L[0]) % a.L[1], z = q / (a.L[0] * a.L[1]);
     const int Lx = a.L[0], Ly = a.L[1], Lz = a.L[2];
-    // in-plane neighbours (periodic)
-    const int qxp = x + 1 == Lx ? q - x : q + 1, qxm = x == 0 ? q + Lx - 1 : q - 1;
-    const int qyp = y + 1 == Ly ? q - y * Lx : q + Lx, qym = y == 0 ? q + (Ly - 1) * Lx : q - Lx;
-    const int qzp = z + 1 == Lz ? q - z * Lx * Ly : q + Lx * Ly, qzm = z == 0 ? q + (Lz - 1) * Lx * Ly : q - Lx * Ly;
+    const int q = (int)threadIdx.x;               // site within the block
+    int r, blk = 0;
+    int x, y, z, bx, by, bz, Pb, Hb;
+    if (HALO) {
+        // blocks of one vector are consecutive logical ids: one XCD, shared halos in its L2
+        const unsigned lg = xcd_remap(blockIdx.x, gridDim.x);
+        r = (int)(lg / (unsigned)a.nbp);
+        blk = (int)(lg % (unsigned)a.nbp);
+        bx = a.B[0];
+        by = a.B[1];
+        bz = a.B[2];
+        Pb = a.Pb;
+        Hb = a.Hb;
+        const int nbx = Lx / bx, nby = Ly / by;
+        x = (blk % nbx) * bx + q % bx;
+        y = ((blk / nbx) % nby) * by + (q / bx) % by;
+        z = (blk / (nbx * nby)) * bz + q / (bx * by);
+    } else {
+        r = (int)blockIdx.x;
+        bx = Lx;
+        by = Ly;
+        bz = Lz;
+        Pb = P;
+        Hb = 0;
+        x = q % Lx;
+        y = (q / Lx) % Ly;
+        z = q / (Lx * Ly);
+    }
+    const int Sl = Pb + Hb;                       // LDS sites: block, then halo
+    const int lx = q % bx, ly = (q / bx) % by, lz = q / (bx * by);
+    const int gq = x + Lx * (y + Ly * z);         // plane index of this site
+    // plane indices of the backward neighbours (periodic), for their links
+    const int gxm = x == 0 ? gq + Lx - 1 : gq - 1;
+    const int gym = y == 0 ? gq + (Ly - 1) * Lx : gq - Lx;
+    const int gzm = z == 0 ? gq + (Lz - 1) * Lx * Ly : gq - Lx * Ly;
+    // LDS slots of the six neighbours: inside the block, wrapped inside it
+    // when the block spans the dimension, else on the halo face
+    const bool hx = bx < Lx, hy = by < Ly, hz = bz < Lz;
+    const int Fx = by * bz, Fy = bx * bz, Fz = bx * by;
+    const int o_xm = 0, o_xp = hx ? Fx : 0, o_ym = hx ? 2 * Fx : 0;
+    const int o_yp = o_ym + (hy ? Fy : 0), o_zm = o_ym + (hy ? 2 * Fy : 0), o_zp = o_zm + (hz ? Fz : 0);
+    const int sxp = lx + 1 < bx ? q + 1 : (!hx ? q - lx : Pb + o_xp + ly + by * lz);
+    const int sxm = lx > 0 ? q - 1 : (!hx ? q + bx - 1 : Pb + o_xm + ly + by * lz);
+    const int syp = ly + 1 < by ? q + bx : (!hy ? q - ly * bx : Pb + o_yp + lx + bx * lz);
+    const int sym = ly > 0 ? q - bx : (!hy ? q + (by - 1) * bx : Pb + o_ym + lx + bx * lz);
+    const int szp = lz + 1 < bz ? q + bx * by : (!hz ? q - lz * bx * by : Pb + o_zp + lx + bx * ly);
+    const int szm = lz > 0 ? q - bx * by : (!hz ? q + (bz - 1) * bx * by : Pb + o_zm + lx + bx * ly);
+    // the halo site this thread stages (threads q < Hb), as a plane index
+    int ghq = 0;
+    if (HALO && q < Hb) {
+        const int x0 = x - lx, y0 = y - ly, z0 = z - lz;
+        int hx_, hy_, hz_, f;
+        if (q < o_ym) {                           // x faces
+            f = q < o_xp ? q : q - o_xp;
+            hx_ = q < o_xp ? (x0 == 0 ? Lx - 1 : x0 - 1) : (x0 + bx == Lx ? 0 : x0 + bx);
+            hy_ = y0 + f % by;
+            hz_ = z0 + f / by;
+        } else if (q < o_zm) {                    // y faces
+            const bool minus = q < o_yp;
+            f = minus ? q - o_ym : q - o_yp;
+            hx_ = x0 + f % bx;
+            hy_ = minus ? (y0 == 0 ? Ly - 1 : y0 - 1) : (y0 + by == Ly ? 0 : y0 + by);
+            hz_ = z0 + f / bx;
+        } else {                                  // z faces
+            const bool minus = q < o_zp;
+            f = minus ? q - o_zm : q - o_zp;
+            hx_ = x0 + f % bx;
+            hy_ = y0 + f / bx;
+            hz_ = minus ? (z0 == 0 ? Lz - 1 : z0 - 1) : (z0 + bz == Lz ? 0 : z0 + bz);
+        }
+        ghq = hx_ + Lx * (hy_ + Ly * hz_);
+    }
+    const size_t V = (size_t)a.V;
     const size_t estride = V * sizeof(C);
     constexpr bool two = TWO;
     const char *g0 = (const char *)a.gauge;
@@ -298,24 +370,28 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
     // The -t term of the next plane is carried in LDS behind the plane (as the
     // colour-rotated half spinor (1 + g_t) U_t^H psi, sign included), which
     // keeps it out of the registers during the hops.
-    C *stl = lds + 12 * P;
-    // prologue: -t term of plane 0 from plane Lt-1; cur = plane 0
+    C *stl = lds + 12 * Sl;
+    // prologue: -t term of plane 0 from plane Lt-1; cur (and halo) = plane 0
     C stash[2][3];
     {
         C p[12];
-        load_plane_site<T>(inp, IN_Z4, S, q + (Lt - 1) * P, p);
+        load_plane_site<T>(inp, IN_Z4, S, gq + (Lt - 1) * P, p);
         proj<T, 3, false>(p, stash);
         C U[9];
-        load_link<T>(gt, estride, q + (Lt - 1) * P, two, U);
+        load_link<T>(gt, estride, gq + (Lt - 1) * P, two, U);
         mul_link<T, true>(U, stash);
         const T sg = a.apbc ? T(-1) : T(1);
 #pragma unroll
         for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
-            for (int aa = 0; aa < 3; ++aa) stl[(sp * 3 + aa) * P + q] = mk<T>(sg * stash[sp][aa].x, sg * stash[sp][aa].y);
+            for (int aa = 0; aa < 3; ++aa) stl[(sp * 3 + aa) * Pb + q] = mk<T>(sg * stash[sp][aa].x, sg * stash[sp][aa].y);
     }
     C cur[12];
-    load_plane_site<T>(inp, IN_Z4, S, q, cur);
+    load_plane_site<T>(inp, IN_Z4, S, gq, cur);
+    C hcur[12];
+    if constexpr (HALO) {
+        if (q < Hb) load_plane_site<T>(inp, IN_Z4, S, ghq, hcur);
+    }
 
     // out = alpha w + beta D w is formed as beta * ((alpha/beta) w + D w): the
     // current spinor then enters the accumulator at the start of the step and
@@ -331,10 +407,16 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
 
     double dre = 0.0, dim = 0.0, d0re = 0.0, d0im = 0.0;
     for (int t = 0; t < Lt; ++t) {
-        const int s = q + t * P;
+        const int s = gq + t * P;
         const T sg = (t + 1 == Lt && a.apbc) ? T(-1) : T(1);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) lds[c * P + q] = cur[c];
+        for (int c = 0; c < 12; ++c) lds[c * Sl + q] = cur[c];
+        if constexpr (HALO) {
+            if (q < Hb) {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) lds[c * Sl + Pb + q] = hcur[c];
+            }
+        }
         // accumulator: (alpha/beta) w + the -t term carried from plane t-1
         C acc[12];
 #pragma unroll
@@ -344,7 +426,7 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
 #pragma unroll
             for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
-                for (int aa = 0; aa < 3; ++aa) st[sp][aa] = stl[(sp * 3 + aa) * P + q];
+                for (int aa = 0; aa < 3; ++aa) st[sp][aa] = stl[(sp * 3 + aa) * Pb + q];
             recon<T, 3, false>(st, acc);
         }
         // the -t term of (x, t+1): (1 + g_t) U_t(x, t)^H w(x, t)
@@ -357,7 +439,7 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
 #pragma unroll
             for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
-                for (int aa = 0; aa < 3; ++aa) stl[(sp * 3 + aa) * P + q] = mk<T>(sg * st[sp][aa].x, sg * st[sp][aa].y);
+                for (int aa = 0; aa < 3; ++aa) stl[(sp * 3 + aa) * Pb + q] = mk<T>(sg * st[sp][aa].x, sg * st[sp][aa].y);
         }
         if (DOT && FIRST) {
             C b[12];
@@ -372,10 +454,14 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
             }
             dot_acc<T>(b, cur, d0re, d0im);
         }
-        // prefetch the +t plane (plane 0 again after the last one)
+        // prefetch the +t plane (plane 0 again after the last one) and its halo
         const int tn = t + 1 == Lt ? 0 : t + 1;
         C nxt[12];
-        load_plane_site<T>(inp, IN_Z4, S, q + tn * P, nxt);
+        load_plane_site<T>(inp, IN_Z4, S, gq + tn * P, nxt);
+        C hnx[12];
+        if constexpr (HALO) {
+            if (q < Hb) load_plane_site<T>(inp, IN_Z4, S, ghq + tn * P, hnx);
+        }
         __syncthreads();
 
         // The six spatial hops run as a rolled loop with opaque copies of the
@@ -383,17 +469,17 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
         // hops nor hoist their addresses, which bounds the live registers.
 #pragma nounroll
         for (int k = 0; k < 6; ++k) {
-            int qn = k == 0 ? qxp : k == 1 ? qxm : k == 2 ? qyp : k == 3 ? qym : k == 4 ? qzp : qzm;
-            int gs = (k & 1) ? qn + t * P : s;
+            int qn = k == 0 ? sxp : k == 1 ? sxm : k == 2 ? syp : k == 3 ? sym : k == 4 ? szp : szm;
+            int gs = k == 1 ? gxm + t * P : k == 3 ? gym + t * P : k == 5 ? gzm + t * P : s;
             const char *gg = k < 2 ? gx : k < 4 ? gy : gz;
             asm volatile("" : "+v"(qn), "+v"(gs), "+s"(gg));
             switch (k) {
-            case 0: plane_hop<T, 0, true>(lds, P, qn, gg, estride, gs, two, acc); break;
-            case 1: plane_hop<T, 0, false>(lds, P, qn, gg, estride, gs, two, acc); break;
-            case 2: plane_hop<T, 1, true>(lds, P, qn, gg, estride, gs, two, acc); break;
-            case 3: plane_hop<T, 1, false>(lds, P, qn, gg, estride, gs, two, acc); break;
-            case 4: plane_hop<T, 2, true>(lds, P, qn, gg, estride, gs, two, acc); break;
-            default: plane_hop<T, 2, false>(lds, P, qn, gg, estride, gs, two, acc); break;
+            case 0: plane_hop<T, 0, true>(lds, Sl, qn, gg, estride, gs, two, acc); break;
+            case 1: plane_hop<T, 0, false>(lds, Sl, qn, gg, estride, gs, two, acc); break;
+            case 2: plane_hop<T, 1, true>(lds, Sl, qn, gg, estride, gs, two, acc); break;
+            case 3: plane_hop<T, 1, false>(lds, Sl, qn, gg, estride, gs, two, acc); break;
+            case 4: plane_hop<T, 2, true>(lds, Sl, qn, gg, estride, gs, two, acc); break;
+            default: plane_hop<T, 2, false>(lds, Sl, qn, gg, estride, gs, two, acc); break;
             }
         }
         // +t hop: (1 - g_t) U_t(x, t) w(x, t+1)
@@ -432,10 +518,16 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
         __syncthreads();
 #pragma unroll
         for (int c = 0; c < 12; ++c) cur[c] = nxt[c];
+        if constexpr (HALO) {
+            if (q < Hb) {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) hcur[c] = hnx[c];
+            }
+        }
     }
 
     if (DOT) {
-        // fixed-order tree over the plane's threads (LDS plane buffer reused)
+        // fixed-order tree over the block's threads (LDS plane buffer reused)
         double2 *red = reinterpret_cast<double2 *>(smem);
         double2 v = zmul2(a.troots[a.j + 1], make_double2(dre, dim));
         if (FIRST) {
@@ -445,7 +537,7 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
         }
         red[q] = v;
         __syncthreads();
-        int n = P;
+        int n = Pb;
         while (n > 1) {
             const int h = (n + 1) >> 1;
             if (q < n - h) {
@@ -456,29 +548,99 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
             n = h;
         }
         if (q == 0) {
+            // one partial per (vector, block); whole-plane blocks also write b^H y at the end
+            const size_t pi = HALO ? (size_t)r * (size_t)a.nbp + (size_t)blk : (size_t)r;
             double2 tot = red[0];
             if (!FIRST) {
-                tot.x += a.part[r].x;
-                tot.y += a.part[r].y;
+                tot.x += a.part[pi].x;
+                tot.y += a.part[pi].y;
             }
-            a.part[r] = tot;
-            if (a.bhy) a.bhy[r] = tot;
+            a.part[pi] = tot;
+            if (!HALO && a.bhy) a.bhy[r] = tot;
         }
     }
 }
 
+// b^H y of a blocked sweep: the blocks' partials of each vector in a fixed order
+__global__ void k_sweep_sum(const double2 *part, int nbp, int nrhs, double2 *bhy) {
+    const int r = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (r >= nrhs) return;
+    double re = 0.0, im = 0.0;
+    for (int b = 0; b < nbp; ++b) {
+        re += part[(size_t)r * nbp + b].x;
+        im += part[(size_t)r * nbp + b].y;
+    }
+    bhy[r] = make_double2(re, im);
+}
+
 // ------------------------------------------------------------------ host side
 
-bool sweep_fits(const mpmc_lattice &lat) {
-    const int P = lat.dims[0] * lat.dims[1] * lat.dims[2];
-    const size_t lds = (size_t)P * 18 * (lat.prec == MPMC_F64 ? 16 : 8);   // plane + carried half spinors
-    return P >= 64 && P <= 512 && P % 64 == 0 && lds <= 160 * 1024;
+SweepPlan sweep_plan(const mpmc_lattice &lat, mpmc_shape sh) {
+    SweepPlan p;
+    const int Lx = lat.dims[0], Ly = lat.dims[1], Lz = lat.dims[2], Lt = lat.dims[3];
+    const int P = Lx * Ly * Lz;
+    const size_t csz = lat.prec == MPMC_F64 ? 16 : 8;
+    const size_t V = (size_t)P * (size_t)Lt;
+    if (36 * V * csz >= ((size_t)1 << 32)) return p;          // 32-bit link offsets
+    const size_t kLds = 160 * 1024;
+    if (P >= 64 && P <= 512 && P % 64 == 0 && 18 * (size_t)P * csz <= kLds) {
+        // the whole xyz-plane in one workgroup (neighbours wrap inside it)
+        p.ok = true;
+        p.B[0] = Lx;
+        p.B[1] = Ly;
+        p.B[2] = Lz;
+        p.Pb = P;
+        p.lds = 18 * (size_t)P * csz;
+        return p;
+    }
+    if (lat.prec != MPMC_F32) return p;                        // FP64 blocks + halo exceed the registers
+    // A blocked sweep walks all Lt planes inside each workgroup: it pays only
+    // when the launch still gives every CU a full workgroup's worth of
+    // threads; small batches on large planes stay on the streaming kernel.
+    static int cus[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return p;
+    if (!cus[dev] && hipDeviceGetAttribute(&cus[dev], hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return p;
+    const size_t min_threads = (size_t)cus[dev] * 512;
+    if ((size_t)sh.nrhs * (size_t)P < min_threads) return p;
+    // partial sums: one per (vector, block) in the polynomial workspace
+    const size_t spw = 256 / (size_t)sh.rb;
+    const size_t avail = ((V + spw - 1) / spw) * (size_t)sh.nrhs;
+    for (int bx = 1; bx <= Lx; ++bx) {
+        if (Lx % bx) continue;
+        for (int by = 1; by <= Ly; ++by) {
+            if (Ly % by) continue;
+            for (int bz = 1; bz <= Lz; ++bz) {
+                if (Lz % bz) continue;
+                const int Pb = bx * by * bz;
+                if (Pb < 64 || Pb > 512 || Pb % 64) continue;
+                const int Hb = 2 * ((bx < Lx ? by * bz : 0) + (by < Ly ? bx * bz : 0) + (bz < Lz ? bx * by : 0));
+                if (Hb > Pb) continue;                          // one halo site per thread at most
+                const size_t lds = (12 * (size_t)(Pb + Hb) + 6 * (size_t)Pb) * csz;
+                if (lds > kLds) continue;
+                if ((size_t)sh.nrhs * (size_t)(P / Pb) > avail) continue;
+                if (!p.ok || Pb > p.Pb || (Pb == p.Pb && Hb < p.Hb)) {
+                    p.ok = true;
+                    p.halo = true;
+                    p.B[0] = bx;
+                    p.B[1] = by;
+                    p.B[2] = bz;
+                    p.Pb = Pb;
+                    p.Hb = Hb;
+                    p.nbp = P / Pb;
+                    p.lds = lds;
+                }
+            }
+        }
+    }
+    return p;
 }
 
 template <typename T>
-int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, int n, const double *troots, const void *x, bool x_is_noise,
-                   const void *bvec, uint64_t key, uint64_t first, const uint64_t *off, double2 *part, double2 *bhy, void *w0, void *w1,
-                   void *stream) {
+int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, const SweepPlan &plan, int n, const double *troots,
+                   const void *x, bool x_is_noise, const void *bvec, uint64_t key, uint64_t first, const uint64_t *off,
+                   double2 *part, double2 *bhy, void *w0, void *w1, void *stream) {
     SweepArgs<T> a{};
     for (int d = 0; d < 4; ++d) a.L[d] = lat.dims[d];
     a.P = lat.dims[0] * lat.dims[1] * lat.dims[2];
@@ -494,36 +656,47 @@ int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, int n, const double *
     a.bvec = (const cplx_t<T> *)bvec;
     a.rb_b = sh.rb;
     a.part = part;
-    const size_t lds = (size_t)a.P * 18 * sizeof(cplx_t<T>);
-    // kernels of this precision: [link rows 3 | 2][dot vector noise | field]
-    // [(noise input, first), (field, first), (field, later)]
-    const void *kern[2][2][3] = {
-        {{(const void *)k_sweep<T, true, true, true, false, false>,
-          (const void *)k_sweep<T, false, true, true, false, false>,
-          (const void *)k_sweep<T, false, true, false, false, false>},
-         {(const void *)k_sweep<T, true, true, true, true, false>,
-          (const void *)k_sweep<T, false, true, true, true, false>,
-          (const void *)k_sweep<T, false, true, false, true, false>}},
-        {{(const void *)k_sweep<T, true, true, true, false, true>,
-          (const void *)k_sweep<T, false, true, true, false, true>,
-          (const void *)k_sweep<T, false, true, false, false, true>},
-         {(const void *)k_sweep<T, true, true, true, true, true>,
-          (const void *)k_sweep<T, false, true, true, true, true>,
-          (const void *)k_sweep<T, false, true, false, true, true>}}};
+    for (int d = 0; d < 3; ++d) a.B[d] = plan.B[d];
+    a.Pb = plan.Pb;
+    a.Hb = plan.Hb;
+    a.nbp = plan.nbp;
+    // kernels of this precision: [halo][link rows 3 | 2][dot vector noise | field]
+    // [(noise input, first), (field, first), (field, later)]; blocks with a halo are FP32 only
+#define MPMC_SWEEP_ROW(H, TW, BF)                                                                   \
+    {(const void *)k_sweep<T, true, true, true, BF, TW, H>, (const void *)k_sweep<T, false, true, true, BF, TW, H>, \
+     (const void *)k_sweep<T, false, true, false, BF, TW, H>}
+    const void *kern[2][2][2][3] = {
+        {{MPMC_SWEEP_ROW(false, false, false), MPMC_SWEEP_ROW(false, false, true)},
+         {MPMC_SWEEP_ROW(false, true, false), MPMC_SWEEP_ROW(false, true, true)}},
+        {{{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}},
+         {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}}}};
+    if constexpr (sizeof(T) == 4) {
+        const void *kh[2][2][3] = {{MPMC_SWEEP_ROW(true, false, false), MPMC_SWEEP_ROW(true, false, true)},
+                                   {MPMC_SWEEP_ROW(true, true, false), MPMC_SWEEP_ROW(true, true, true)}};
+        for (int tw = 0; tw < 2; ++tw)
+            for (int bf = 0; bf < 2; ++bf)
+                for (int v = 0; v < 3; ++v) kern[1][tw][bf][v] = kh[tw][bf][v];
+    }
+#undef MPMC_SWEEP_ROW
     static bool attr_set[2] = {false, false};
     const int pi = sizeof(T) == 8 ? 0 : 1;
     if (!attr_set[pi]) {
-        for (int tw = 0; tw < 2; ++tw)
-            for (int bf = 0; bf < 2; ++bf)
-                for (int v = 0; v < 3; ++v)
-                    if (hipFuncSetAttribute(kern[tw][bf][v], hipFuncAttributeMaxDynamicSharedMemorySize,
-                                            160 * 1024) != hipSuccess)
-                        return MPMC_EHIP;
+        for (int h = 0; h < 2; ++h)
+            for (int tw = 0; tw < 2; ++tw)
+                for (int bf = 0; bf < 2; ++bf)
+                    for (int v = 0; v < 3; ++v)
+                        if (kern[h][tw][bf][v] &&
+                            hipFuncSetAttribute(kern[h][tw][bf][v], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                160 * 1024) != hipSuccess)
+                            return MPMC_EHIP;
         attr_set[pi] = true;
     }
+    const int h = plan.halo ? 1 : 0;
     const int bf = bvec != nullptr ? 1 : 0;
     const int tw = lat.link_rows == 2 ? 1 : 0;
+    if (!kern[h][tw][bf][0]) return MPMC_EUNSUPPORTED;
     const int d = n - 1;
+    const dim3 grid((unsigned)(sh.nrhs * plan.nbp)), block((unsigned)plan.Pb);
     for (int j = 0; j < d; ++j) {
         a.j = j;
         const bool first_step = (j == 0);
@@ -531,21 +704,26 @@ int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, int n, const double *
         a.rb_in = first_step ? sh.rb : 1;
         a.out = (cplx_t<T> *)(j % 2 == 0 ? w0 : w1);
         a.dot_first = first_step;
-        a.bhy = (j == d - 1) ? bhy : nullptr;
+        a.bhy = (j == d - 1 && !plan.halo) ? bhy : nullptr;
         const int v = first_step ? (x_is_noise ? 0 : 1) : 2;
         void *args[] = {&a};
-        if (hipLaunchKernel(kern[tw][bf][v], dim3(sh.nrhs), dim3(a.P), args, lds, (hipStream_t)stream) != hipSuccess)
+        if (hipLaunchKernel(kern[h][tw][bf][v], grid, block, args, plan.lds, (hipStream_t)stream) != hipSuccess)
             return MPMC_EHIP;
+        if (hipGetLastError() != hipSuccess) return MPMC_EHIP;
+    }
+    if (plan.halo && bhy) {
+        hipLaunchKernelGGL(k_sweep_sum, dim3((sh.nrhs + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                           (const double2 *)part, plan.nbp, sh.nrhs, bhy);
         if (hipGetLastError() != hipSuccess) return MPMC_EHIP;
     }
     return MPMC_OK;
 }
 
-template int sweep_newton_t<double>(const mpmc_lattice &, mpmc_shape, int, const double *, const void *, bool,
-                                    const void *, uint64_t, uint64_t, const uint64_t *, double2 *, double2 *, void *, void *,
-                                    void *);
-template int sweep_newton_t<float>(const mpmc_lattice &, mpmc_shape, int, const double *, const void *, bool,
-                                   const void *, uint64_t, uint64_t, const uint64_t *, double2 *, double2 *, void *, void *,
-                                    void *);
+template int sweep_newton_t<double>(const mpmc_lattice &, mpmc_shape, const SweepPlan &, int, const double *,
+                                    const void *, bool, const void *, uint64_t, uint64_t, const uint64_t *, double2 *,
+                                    double2 *, void *, void *, void *);
+template int sweep_newton_t<float>(const mpmc_lattice &, mpmc_shape, const SweepPlan &, int, const double *,
+                                   const void *, bool, const void *, uint64_t, uint64_t, const uint64_t *, double2 *,
+                                   double2 *, void *, void *, void *);
 
 }  // namespace mpmc

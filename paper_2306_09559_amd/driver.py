@@ -47,6 +47,7 @@ class LevelState:
     last_solve: Optional[SolveStats] = None
     solve_tol: float = 1e-6
     rb: int = 0                             # RHS block width of this level (0: the run's)
+    batch: int = 0                          # vectors per batch (device buffers); samples per step / batch draws
     sweep: bool = True                      # allow the t-sweep kernel for this level
 
 
@@ -95,10 +96,19 @@ class LatticeRun:
         self.enqueue(level, nsamples, nz)
         lv.drawn += nsamples
 
+    def batches(self, level: int) -> int:
+        """Batches per step of a level: its configured samples / its batch size."""
+        return self.cfg.levels[level].samples // self.levels[level].batch
+
     def step(self, batch: Optional[Dict[int, int]] = None):
-        """One pass of the hot path: every level draws its configured batch."""
+        """One pass of the hot path: every level draws its configured samples
+        (in batches of its buffer size), or `batch[level]` samples."""
         for i, lv in enumerate(self.levels):
-            self.draw(i, (batch or {}).get(i, self.cfg.levels[i].samples))
+            if batch is not None and i in batch:
+                self.draw(i, batch[i])
+                continue
+            for _ in range(self.batches(i)):
+                self.draw(i, lv.batch)
 
     def reset(self):
         for lv in self.levels:
@@ -111,7 +121,7 @@ class LatticeRun:
         lv = self.levels[level]
         if lv.solver is not None:
             raise ValueError("the block width of a solve level is fixed by its solver")
-        N = self.cfg.levels[level].samples
+        N = lv.batch
         if N % rb:
             raise ValueError(f"rb={rb} does not divide {N}")
         lv.rb, lv.sweep = int(rb), bool(sweep)
@@ -149,6 +159,17 @@ def launch_bytes(V: int, nrhs: int, prec: int) -> int:
     return V * nrhs * 24 * c + V * 36 * c
 
 
+def _batch_size(samples: int, rb: int, max_batch: int) -> int:
+    """Largest multiple of rb that divides samples and is at most max_batch."""
+    if samples % rb:
+        raise ValueError(f"rb={rb} does not divide the level's {samples} samples")
+    best = rb
+    for b in range(rb, min(samples, max_batch) + 1, rb):
+        if samples % b == 0:
+            best = b
+    return best
+
+
 def _device_poly(roots: krylov.RootSet, comps: Dict[tuple, krylov.OuterRoots], p) -> L.DevicePoly:
     if isinstance(p, tuple):
         return comps[p].device
@@ -164,7 +185,7 @@ def _poly_value(roots: krylov.RootSet, comps: Dict[tuple, krylov.OuterRoots], p,
 def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optional[int] = None,
           arnoldi_m: int = 90, nev: int = 40, verbose: bool = False,
           reuse: Optional["LatticeRun"] = None, gmres_m: int = 30, solve_tol: float = 1e-6,
-          two_row_links: bool = True) -> LatticeRun:
+          two_row_links: bool = True, max_batch: int = 1 << 30) -> LatticeRun:
     """Set up a lattice workload: links, GMRES roots, PP-Arnoldi deflation,
     outer roots of composite polynomials (FP64 on the GPU, Sec. 5 setup
     step 2) and the level descriptors in precision `prec`.  With `reuse`,
@@ -172,7 +193,9 @@ def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optio
     are taken over (the set-up is always FP64).  A top level with hi = SOLVE
     gets a deflated PP-GMRES(gmres_m) solver (FP32 inner cycles when prec is
     FP32, FP64 residual) converging to solve_tol (rtolle).  Links that are
-    SU(3) to 1e-12 are read as two rows (two_row_links)."""
+    SU(3) to 1e-12 are read as two rows (two_row_links).  A level's device
+    buffers hold at most max_batch vectors; a step draws its samples in
+    samples / batch batches."""
     t0 = time.perf_counter()
     U = synth.gauge_links(cfg.dims, cfg.eps, cfg.seed_links)
     canon = torch.from_numpy(U).cuda()
@@ -236,7 +259,7 @@ def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optio
     run.defl64_V = defl64_V
     run.composites = comps
     for i, lv in enumerate(cfg.levels):
-        N = lv.samples
+        N = _batch_size(lv.samples, rb, max_batch)
         if lv.hi == SOLVE:
             # Tr(A^{-1} - Q) with Q the deflated p_1 (Sec. 4.3): the deflation is in Q,
             # so the samples carry no Monte Carlo deflation term
@@ -254,7 +277,7 @@ def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optio
             ws = L.workspace(L.level_workspace_size(dl, dlev, N, rb))
             st = LevelState(i, dlev, poly_mvps(lv.lo), None, torch.zeros(8, dtype=torch.float64, device="cuda"),
                             torch.empty((N, 6), dtype=torch.float64, device="cuda"), ws, solver=solver,
-                            b64=L.empty_field(V, N, rb, L.F64), x64=x64, xl=xl, solve_tol=solve_tol)
+                            b64=L.empty_field(V, N, rb, L.F64), x64=x64, xl=xl, solve_tol=solve_tol, batch=N)
             run.levels.append(st)
             continue
         hi = _device_poly(roots, comps, lv.hi)
@@ -270,7 +293,7 @@ def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optio
         ws = L.workspace(L.level_workspace_size(dl, dlev, N, rb))
         run.levels.append(LevelState(i, dlev, poly_mvps(lv.hi) + poly_mvps(lv.lo), c,
                                      torch.zeros(8, dtype=torch.float64, device="cuda"),
-                                     torch.empty((N, 6), dtype=torch.float64, device="cuda"), ws))
+                                     torch.empty((N, 6), dtype=torch.float64, device="cuda"), ws, batch=N))
     torch.cuda.synchronize()
     run.setup_seconds = time.perf_counter() - t0
     if verbose:
@@ -358,7 +381,7 @@ def run_to_tolerance(run: LatticeRun, eps: float, first_batch: int = 32,
     run.reset()
     for li, lv in enumerate(run.levels):
         target = level_targets(eps, errs + [0.0] * (nl - len(errs)))[li]
-        N = run.cfg.levels[li].samples
+        N = lv.batch
         rb = run.level_rb(li)
         batch = N if lv.solver is not None else max(rb, min(N, (first_batch // rb) * rb or rb))
         chunks: List[np.ndarray] = []

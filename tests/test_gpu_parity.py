@@ -412,10 +412,19 @@ def test_level_accumulates_batches_and_is_deterministic():
     ((8, 4, 2, 3), True, 0, 4, 2, True),       # odd Lt
     ((4, 4, 4, 1), True, 0, 4, 4, True),       # Lt = 1: the t-neighbours are the site itself
     ((8, 8, 8, 4), True, 1, 16, 16, True),     # FP32
+    # planes larger than one workgroup: xyz-blocks with a halo (FP32), with
+    # enough vectors for a workgroup's worth of threads per CU (256 CUs)
+    ((8, 8, 16, 4), True, 1, 128, 4, True),    # two blocks, cut in z
+    ((16, 8, 8, 3), True, 1, 128, 2, False),   # cut in x, field input, odd Lt
+    ((12, 12, 12, 2), True, 1, 80, 8, True),   # 4 x 4 x 12 blocks, cut in x and y
+    ((16, 16, 16, 2), False, 1, 32, 4, True),  # eight blocks of a 16^3 plane
 ])
 def test_sweep_matches_oracle_and_streaming(dims, ap, prec, nrhs, rb, z4):
     L = lib()
     dl, ol = device_lattice(dims, 0.14, 0.4, 33, ap, prec=prec)
+    plan = L.sweep_plan(dl, nrhs, rb)
+    P = dims[0] * dims[1] * dims[2]
+    assert plan["ok"] and plan["halo"] == (P > 512), plan
     deg = 9
     t = krylov.gmres_polys(ol.apply, synth.gaussian_start(ol.n, 1), [deg]).inv_roots[deg]
     poly = L.DevicePoly(dev_c128(t))
@@ -508,3 +517,19 @@ def test_link_rows_validated():
     y = L.empty_field(dl.V, 1, 1, 0)
     with pytest.raises(L.MpmcError):
         L.wilson_apply(dl, x, y)
+
+
+def test_blocked_sweep_two_row_links():
+    """xyz-blocks with a halo and two-row SU(3) links against the oracle."""
+    L = lib()
+    dims = (16, 16, 16, 2)
+    dl, ol = device_lattice(dims, 0.14, 0.4, 35, True, prec=1, link_rows=2)
+    N = 32
+    assert L.sweep_plan(dl, N, 8)["halo"]
+    t = krylov.gmres_polys(ol.apply, synth.gaussian_start(ol.n, 2), [6]).inv_roots[6]
+    poly = L.DevicePoly(dev_c128(t))
+    ws = L.workspace(L.poly_workspace_size(dl, poly, N, 8))
+    bhy = torch.empty(N, dtype=torch.complex128, device="cuda")
+    L.poly_apply(dl, poly, N, 8, None, L.Noise(6, 6, 6, 0), None, bhy, ws)
+    _, ref = ol.poly_apply(t, oracle.z4(6, 6, 6, 0, N, dl.V))
+    assert np.max(np.abs(bhy.cpu().numpy() - ref) / np.abs(ref)) < 8 * 6 * 50 * U32
