@@ -419,6 +419,24 @@ def main():
                             "seconds": round(x.seconds, 4)} for x in res]}
         out["adaptive"]["speedup_mixed_vs_f64"] = round(out["adaptive"]["f64"]["seconds"] /
                                                         out["adaptive"]["mixed"]["seconds"], 3)
+        # the paper's lowest level exact by probing (Sec. 5 step 3d), eps over the Monte Carlo levels;
+        # the colouring is set-up (once per lattice and degree) and timed apart
+        from paper_2306_09559_amd import probing
+        t0 = time.perf_counter()
+        col = probing.colouring(C2.dims, int(C2.levels[-1].hi))
+        out["adaptive"]["colouring"] = {"distance": int(C2.levels[-1].hi), "colours": int(col.max()) + 1,
+                                        "setup_s": round(time.perf_counter() - t0, 3)}
+        for name, r in (("f64_probing", run), ("mixed_probing", run32)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = driver.run_to_tolerance(r, eps, probe_last=True)
+            torch.cuda.synchronize()
+            tot = time.perf_counter() - t0
+            out["adaptive"][name] = {
+                "seconds": round(tot, 4), "stderr": round(float(np.sqrt(sum(x.stderr ** 2 for x in res))), 4),
+                "trace_estimate": [round(sum(x.estimate for x in res).real, 3),
+                                   round(sum(x.estimate for x in res).imag, 3)],
+                "levels": [{"n": x.n, "stderr": round(x.stderr, 4), "seconds": round(x.seconds, 4)} for x in res]}
     if not args.no_extra:
         out["batched_lattices"] = batched_c5(args.steps)
         out["top_level"] = top_level_c3()

@@ -174,6 +174,17 @@ int mpmc_pack_gauge(const int32_t dims[4], int32_t prec, const double *canon, vo
  * precision for links that may use link_rows = 2. */
 int mpmc_gauge_unitarity(const int32_t dims[4], int32_t prec, const void *gauge, double *out, void *stream);
 
+/* Probe vectors for an exact trace by probing (Sec. 3.1, Sec. 5 step 3d):
+ * vector r of the batch is probe p = first_probe + r, i.e. colour c = p / 12
+ * and unknown k = p % 12 (k = 3 spin + colour index): entry (k, s) is 1 where
+ * colour[s] == c, every other entry 0.  With a colouring in which sites of one
+ * colour are further apart than the degree of p, the sum over all probes of
+ * b^H p(A) b is Tr p(A).
+ *   colour  device, V int32 (colour of each site, 0 .. ncolours-1)
+ *   field   device field of `shape` (written) */
+int mpmc_probe_fill(const int32_t dims[4], int32_t prec, mpmc_shape shape, const int32_t *colour,
+                    int64_t first_probe, void *field, void *stream);
+
 /* canon: device complex128 (N, V, 4, 3) <-> field (prec, field layout). */
 int mpmc_pack_fields(const int32_t dims[4], int32_t prec, mpmc_shape shape, const double *canon,
                      void *field, void *stream);

@@ -18,6 +18,7 @@ Contents
   dense.py       dense matrices and free-field closed forms for tiny lattices
   solve.py       the top level Tr(A^{-1} - p_1(A)): dense solves, residuals,
                  top-level samples
+  probing.py     exact Tr p(A) by probing with a brute-force distance colouring
 """
 from __future__ import annotations
 

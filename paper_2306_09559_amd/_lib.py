@@ -67,6 +67,7 @@ _sig = {
     "mpmc_build_info": (ctypes.c_char_p, []),
     "mpmc_set_option": (ctypes.c_int, [c_i32, c_i32]),
     "mpmc_counter_add": (ctypes.c_int, [c_vp, c_u64, c_vp]),
+    "mpmc_probe_fill": (ctypes.c_int, [P(c_i32), c_i32, mpmc_shape, c_vp, ctypes.c_int64, c_vp, c_vp]),
     "mpmc_sweep_plan": (ctypes.c_int, [P(mpmc_lattice), mpmc_shape, P(c_i32)]),
     "mpmc_gauge_unitarity": (ctypes.c_int, [P(c_i32), c_i32, c_vp, c_vp, c_vp]),
     "mpmc_pack_gauge": (ctypes.c_int, [P(c_i32), c_i32, c_vp, c_vp, c_vp]),
@@ -252,6 +253,13 @@ def sweep_plan(lat: "DeviceLattice", nrhs: int, rb: int) -> dict:
     _check("mpmc_sweep_plan", _lib.mpmc_sweep_plan(ctypes.byref(L), mpmc_shape(nrhs, rb), out))
     v = list(out)
     return dict(ok=bool(v[0]), halo=bool(v[1]), block=tuple(v[2:5]), sites=v[5], halo_sites=v[6], blocks=v[7])
+
+
+def probe_fill(dims, prec: int, colour: torch.Tensor, first_probe: int, field: torch.Tensor):
+    """Probe vectors first_probe .. + N-1 (colour c = p // 12, unknown p % 12)."""
+    assert colour.dtype == torch.int32 and colour.is_contiguous()
+    _check("mpmc_probe_fill", _lib.mpmc_probe_fill(_dims(dims), prec, field_shape(field), _ptr(colour),
+                                                   int(first_probe), _ptr(field), _stream()))
 
 
 def counter_add(counter: torch.Tensor, increment: int):

@@ -139,6 +139,13 @@ int mpmc_sweep_plan(const mpmc_lattice *lat, mpmc_shape shape, int32_t *out) {
     return MPMC_OK;
 }
 
+int mpmc_probe_fill(const int32_t dims[4], int32_t prec, mpmc_shape shape, const int32_t *colour,
+                    int64_t first_probe, void *field, void *stream) {
+    if (!valid_dims(dims) || !valid_shape(shape) || !colour || !field || first_probe < 0) return MPMC_EINVAL;
+    if (!valid_prec(prec)) return MPMC_EUNSUPPORTED;
+    return probe_fill_impl(dims, prec, shape, colour, first_probe, field, stream);
+}
+
 int mpmc_pack_gauge(const int32_t dims[4], int32_t prec, const double *canon, void *gauge, void *stream) {
     if (!valid_dims(dims) || !canon || !gauge) return MPMC_EINVAL;
     if (!valid_prec(prec)) return MPMC_EUNSUPPORTED;

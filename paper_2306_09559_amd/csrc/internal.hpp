@@ -62,6 +62,8 @@ int pack_fields_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, const d
 int unpack_fields_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, const void *field, double *canon,
                        void *stream);
 int counter_add_impl(uint64_t *counter, uint64_t inc, void *stream);
+int probe_fill_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, const int32_t *colour, int64_t first,
+                    void *field, void *stream);
 int gauge_unitarity_impl(const int32_t dims[4], int32_t prec, const void *gauge, double *out, void *stream);
 int z4_fill_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, const mpmc_noise &nz, void *field, void *stream);
 

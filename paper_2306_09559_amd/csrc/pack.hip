@@ -57,6 +57,22 @@ __global__ void k_pack_gauge(const double2 *canon, cplx_t<T> *gauge, int V) {
     gauge[e] = mk<T>((T)v.x, (T)v.y);
 }
 
+template <typename T>
+__global__ void k_probe_fill(cplx_t<T> *field, const int32_t *colour, int V, int rb, int nrhs, int64_t first) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t total = (size_t)nrhs * 12 * (size_t)V;
+    if (e >= total) return;
+    const int j = (int)(e % (size_t)rb);
+    size_t q = e / (size_t)rb;
+    const int s = (int)(q % (size_t)V);
+    q /= (size_t)V;
+    const int c = (int)(q % 12);
+    const int nbk = (int)(q / 12);
+    const int64_t p = first + (int64_t)(nbk * rb + j);
+    const bool on = (c == (int)(p % 12)) && ((int64_t)colour[s] == p / 12);
+    field[e] = mk<T>(on ? T(1) : T(0), T(0));
+}
+
 __global__ void k_counter_add(uint64_t *c, uint64_t inc) {
     if (threadIdx.x == 0 && blockIdx.x == 0) c[0] = c[0] + inc;
 }
@@ -185,6 +201,19 @@ int gauge_unitarity_impl(const int32_t dims[4], int32_t prec, const void *gauge,
     else
         hipLaunchKernelGGL(k_unitarity<float>, dim3(1), dim3(1024), 0, (hipStream_t)stream, (const float2 *)gauge, V,
                            out);
+    return last_status();
+}
+
+int probe_fill_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, const int32_t *colour, int64_t first,
+                    void *field, void *stream) {
+    const int V = dims[0] * dims[1] * dims[2] * dims[3];
+    const size_t total = (size_t)sh.nrhs * 12 * V;
+    if (prec == MPMC_F64)
+        hipLaunchKernelGGL(k_probe_fill<double>, dim3(nblocks(total, 256)), dim3(256), 0, (hipStream_t)stream,
+                           (double2 *)field, colour, V, sh.rb, sh.nrhs, first);
+    else
+        hipLaunchKernelGGL(k_probe_fill<float>, dim3(nblocks(total, 256)), dim3(256), 0, (hipStream_t)stream,
+                           (float2 *)field, colour, V, sh.rb, sh.nrhs, first);
     return last_status();
 }
 

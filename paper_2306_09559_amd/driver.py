@@ -366,7 +366,7 @@ class AdaptiveLevel:
 
 
 def run_to_tolerance(run: LatticeRun, eps: float, first_batch: int = 32,
-                     max_samples: int = 1 << 20) -> List[AdaptiveLevel]:
+                     max_samples: int = 1 << 20, probe_last: bool = False) -> List[AdaptiveLevel]:
     """The multilevel Monte Carlo of Sec. 5 step 3 on the GPU: levels top
     first, each drawing batches of Z4 samples until its standard error falls
     to its share of eps (level_targets, given the errors of the levels before
@@ -374,13 +374,27 @@ def run_to_tolerance(run: LatticeRun, eps: float, first_batch: int = 32,
     up to the level's configured batch (a solve level always draws its full
     batch).  The estimate of a level uses exactly the samples up to its
     stopping point, as a one-at-a-time draw would; the rest of the last batch
-    is discarded.  Returns one AdaptiveLevel per level."""
+    is discarded.  With probe_last, the last level Tr p_d(A) is computed
+    exactly by probing with a distance-d colouring (Sec. 5 step 3d; its
+    standard error is 0) and eps is split over the Monte Carlo levels only.
+    Returns one AdaptiveLevel per level."""
+    from . import probing
     out: List[AdaptiveLevel] = []
     errs: List[float] = []
     nl = len(run.levels)
+    last = run.cfg.levels[-1]
+    if probe_last and not (last.lo is None and isinstance(last.hi, int)):
+        raise ValueError("probing needs a last level Tr p_d(A) of a single polynomial")
+    nmc = nl - 1 if probe_last else nl
     run.reset()
     for li, lv in enumerate(run.levels):
-        target = level_targets(eps, errs + [0.0] * (nl - len(errs)))[li]
+        if li == nmc:
+            t0 = time.perf_counter()
+            col = probing.colouring(run.cfg.dims, int(last.hi))
+            pr = probing.probe_trace(run.dl, lv.device.poly_hi, col, nrhs=lv.batch)
+            out.append(AdaptiveLevel(pr.probes, pr.probes, pr.trace, 0.0, 0.0, time.perf_counter() - t0))
+            break
+        target = level_targets(eps, errs + [0.0] * (nmc - len(errs)))[li]
         N = lv.batch
         rb = run.level_rb(li)
         batch = N if lv.solver is not None else max(rb, min(N, (first_batch // rb) * rb or rb))
