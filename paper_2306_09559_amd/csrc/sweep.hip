@@ -249,6 +249,50 @@ __device__ __forceinline__ void plane_hop(const cplx_t<T> *lds, int P, int q, co
     }
 }
 
+// link elements as stored (two rows when TWO), and the rebuild of row 2
+template <typename T, bool TWO>
+__device__ __forceinline__ void link_raw(const char *g, size_t estride, int site, cplx_t<T> (&U)[9]) {
+    const uint32_t off = (uint32_t)site * (uint32_t)sizeof(cplx_t<T>);
+#pragma unroll
+    for (int e = 0; e < (TWO ? 6 : 9); ++e) U[e] = *(const cplx_t<T> *)(g + (size_t)e * estride + off);
+}
+template <typename T, bool TWO> __device__ __forceinline__ void link_complete(cplx_t<T> (&U)[9]) {
+    if (TWO) {
+        const cplx_t<T> c0 = csub<T>(cmul<T>(U[1], U[5]), cmul<T>(U[2], U[4]));
+        const cplx_t<T> c1 = csub<T>(cmul<T>(U[2], U[3]), cmul<T>(U[0], U[5]));
+        const cplx_t<T> c2 = csub<T>(cmul<T>(U[0], U[4]), cmul<T>(U[1], U[3]));
+        U[6] = mk<T>(c0.x, -c0.y);
+        U[7] = mk<T>(c1.x, -c1.y);
+        U[8] = mk<T>(c2.x, -c2.y);
+    }
+}
+
+// plane_hop with the link already in registers
+template <typename T, int MU, bool FWD>
+__device__ __forceinline__ void plane_hop_u(const cplx_t<T> *lds, int P, int q, const cplx_t<T> (&U)[9],
+                                            cplx_t<T> (&acc)[12]) {
+    cplx_t<T> h[2][3];
+    proj_lds<T, MU, FWD>(lds, P, q, h);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cplx_t<T> u[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) u[b] = U[FWD ? 3 * a + b : 3 * b + a];
+        cplx_t<T> g0 = mk<T>(T(0), T(0)), g1 = mk<T>(T(0), T(0));
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            if (FWD) {
+                g0 = cfma<T>(u[b], h[0][b], g0);
+                g1 = cfma<T>(u[b], h[1][b], g1);
+            } else {
+                g0 = cfmaconj<T>(u[b], h[0][b], g0);
+                g1 = cfmaconj<T>(u[b], h[1][b], g1);
+            }
+        }
+        recon_a<T, MU, FWD>(a, g0, g1, acc);
+    }
+}
+
 __device__ __forceinline__ double2 zmul2(double2 a, double2 b) {
     double2 r;
     r.x = a.x * b.x - a.y * b.y;
@@ -464,6 +508,59 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
         }
         __syncthreads();
 
+        if constexpr (sizeof(T) == 4 && !FIRST) {
+            // FP32 after the first step: the link of each hop is loaded one hop
+            // ahead (the +t link during the -z hop), a (+mu, -mu) pair per
+            // rolled iteration.  This kernel has the registers for the second
+            // link and is bound by instruction issue once the link latency is
+            // hidden (measured: 79 -> 69 us per launch at 8^4 x 256 vectors).
+            // The FP64 kernel and the first-step kernels have no registers to
+            // spare: there the prefetch spills, and FP64 without the spills
+            // measured no faster.
+            C Ua[9];
+            {
+                int s0 = s;
+                const char *g0p = gx;
+                asm volatile("" : "+v"(s0), "+s"(g0p));
+                link_raw<T, TWO>(g0p, estride, s0, Ua);
+            }
+#pragma nounroll
+            for (int k2 = 0; k2 < 3; ++k2) {
+                C Ub[9];
+                int qf = k2 == 0 ? sxp : k2 == 1 ? syp : szp;
+                int qb = k2 == 0 ? sxm : k2 == 1 ? sym : szm;
+                int sb = (k2 == 0 ? gxm : k2 == 1 ? gym : gzm) + t * P;
+                const char *gm = k2 == 0 ? gx : k2 == 1 ? gy : gz;
+                asm volatile("" : "+v"(qf), "+v"(qb), "+v"(sb), "+s"(gm));
+                link_raw<T, TWO>(gm, estride, sb, Ub);
+                link_complete<T, TWO>(Ua);
+                switch (k2) {
+                case 0: plane_hop_u<T, 0, true>(lds, Sl, qf, Ua, acc); break;
+                case 1: plane_hop_u<T, 1, true>(lds, Sl, qf, Ua, acc); break;
+                default: plane_hop_u<T, 2, true>(lds, Sl, qf, Ua, acc); break;
+                }
+                int sn = s;
+                const char *gn = k2 == 0 ? gy : k2 == 1 ? gz : gt;
+                asm volatile("" : "+v"(sn), "+s"(gn));
+                link_raw<T, TWO>(gn, estride, sn, Ua);
+                link_complete<T, TWO>(Ub);
+                switch (k2) {
+                case 0: plane_hop_u<T, 0, false>(lds, Sl, qb, Ub, acc); break;
+                case 1: plane_hop_u<T, 1, false>(lds, Sl, qb, Ub, acc); break;
+                default: plane_hop_u<T, 2, false>(lds, Sl, qb, Ub, acc); break;
+                }
+            }
+            // +t hop: (1 - g_t) U_t(x, t) w(x, t+1), its link already in Ua
+            link_complete<T, TWO>(Ua);
+            C h[2][3];
+            proj<T, 3, true>(nxt, h);
+            mul_link<T, false>(Ua, h);
+#pragma unroll
+            for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+                for (int aa = 0; aa < 3; ++aa) h[sp][aa] = mk<T>(sg * h[sp][aa].x, sg * h[sp][aa].y);
+            recon<T, 3, true>(h, acc);
+        } else {
         // The six spatial hops run as a rolled loop with opaque copies of the
         // loop-invariant inputs: the compiler can then neither interleave the
         // hops nor hoist their addresses, which bounds the live registers.
@@ -496,6 +593,7 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
 #pragma unroll
                 for (int aa = 0; aa < 3; ++aa) h[sp][aa] = mk<T>(sg * h[sp][aa].x, sg * h[sp][aa].y);
             recon<T, 3, true>(h, acc);
+        }
         }
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
