@@ -230,33 +230,51 @@ def batched_c5(steps: int):
             "speedup": round(eager / graph, 3), "graph_GBps": round(byts / graph / 1e9, 1)}
 
 
-def top_level_c3():
+def top_level_c3(cfg=None):
     """The top level Tr(A^{-1} - p_1) of the 16^3x32 workload: one batch of 64
     Z4 vectors solved by deflated PP-GMRES (FP32 inner cycles, FP64 residual)
-    and sampled against the deflated composite p_1 (299 MVPs)."""
+    and sampled against the deflated double polynomial p_1.  cfg: the regular
+    set-up (default, PP(20)x15 = degree 299) or the extra-deflation one."""
     import time
     import torch
     from paper_2306_09559_amd import _lib as L
     from paper_2306_09559_amd import driver
     from synth.configs import C3
+    cfg = cfg or C3
     t0 = time.perf_counter()
-    run = driver.build(C3, prec=L.F32, rb=16)
+    run = driver.build(cfg, prec=L.F32, rb=16)
     setup = time.perf_counter() - t0
     torch.cuda.synchronize()
+    N = cfg.levels[0].samples
     t0 = time.perf_counter()
-    run.draw(0, C3.levels[0].samples)
+    run.draw(0, N)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     st = run.levels[0].last_solve
     e = run.estimates()[0]
-    return {"workload": "16^3x32 n=1572864, kappa=0.15, eps=0.5 links; Tr(A^-1 - Q), Q = deflated composite "
-                        "PP(20)x15 (deg 299), k=%d" % run.defl.device.k,
-            "setup_s": round(setup, 2), "batch": C3.levels[0].samples, "batch_s": round(dt, 3),
+    key = cfg.levels[0].lo
+    comp = run.composites[key]
+    prm = run.setup_params
+    var = e["stderr"] ** 2 * N
+    target = 0.0005 * cfg.volume / 3 ** 0.5
+    links = ("links of the 8^4 workload tiled" if cfg.extra.get("tile_from") else "eps=%g links" % cfg.eps)
+    return {"workload": "%s %s n=%d, kappa=%.6g, %s; Tr(A^-1 - Q), Q = deflated double polynomial PP(%d)x%d "
+                        "(deg %d), k=%d" % (cfg.name, "x".join(map(str, cfg.dims)), cfg.n, cfg.kappa, links, key[0],
+                                            comp.n_out, key[0] * comp.n_out - 1, run.defl.device.k),
+            "setup": {"seconds": round(setup, 2), "pin_degree": key[0] - 1, "arnoldi_steps": run.defl.arnoldi_steps,
+                      "arnoldi_gmres_residual": float(f"{run.defl.arnoldi_residual:.3g}"),
+                      "ritz_tested": run.defl.candidates, "accepted": run.defl.device.k,
+                      "accepted_abs_lambda": [float(f"{abs(l):.3g}") for l in sorted(run.defl.lam, key=abs)],
+                      "p1_outer_roots": comp.n_out, "p1_residual": float(f"{comp.residual:.3g}"),
+                      "gmres_m": prm["gmres_m"]},
+            "batch": N, "batch_s": round(dt, 3),
             "solve": {"outer_fp64": st.outer, "inner_cycles": st.cycles, "arnoldi_steps": st.arnoldi_steps,
                       "mvps_per_vector": st.mvps, "max_rel_residual": float(f"{st.rel_res.max():.3g}"),
-                      "rtolle": 1e-6},
+                      "rtolle": prm["solve_tol"]},
             "estimate": [round(e["estimate"].real, 4), round(e["estimate"].imag, 4)], "stderr": round(e["stderr"], 4),
-            "target_stderr": round(0.0005 * C3.volume / 3 ** 0.5, 3)}
+            "sample_variance": round(var, 2), "target_stderr": round(target, 3),
+            # time for this level alone to reach its share eps/sqrt(3) of eps = 0.0005 V
+            "seconds_to_target": round(var / target ** 2 * dt / N, 3)}
 
 
 def c4_step():
@@ -271,7 +289,7 @@ def c4_step():
     from paper_2306_09559_amd.batch import GraphStep
     from synth.configs import C4
     t0 = time.perf_counter()
-    run = driver.build(C4, prec=L.F32, rb=16, max_batch=256, arnoldi_m=200, nev=160)
+    run = driver.build(C4, prec=L.F32, rb=16, max_batch=256)
     setup = time.perf_counter() - t0
     gs = GraphStep([run], parallel=False)
     gs.replay()
@@ -440,6 +458,9 @@ def main():
     if not args.no_extra:
         out["batched_lattices"] = batched_c5(args.steps)
         out["top_level"] = top_level_c3()
+        # a near-critical 16^3x32 top level with the regular and the extra-deflation set-up (Sec. 6.1)
+        from synth.configs import C3R, C3X
+        out["deflation_setups"] = {"regular": top_level_c3(C3R), "extra": top_level_c3(C3X)}
     if args.c4:
         out["c4"] = c4_step()
     if not args.no_cpu_baseline:

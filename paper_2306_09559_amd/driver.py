@@ -182,10 +182,24 @@ def _poly_value(roots: krylov.RootSet, comps: Dict[tuple, krylov.OuterRoots], p,
     return krylov.newton_value(roots.inv_roots[p], lam)
 
 
+# set-up parameters (Sec. 5 step 2) and their defaults; a configuration may
+# set any of them in its `extra` dict, an argument of build() overrides both
+SETUP_DEFAULTS = {
+    "pin_degree": None,    # degree of p_in for PP-Arnoldi (dp_in); default: the composite's, else a middle degree
+    "arnoldi_m": 90,       # PP-Arnoldi steps at most
+    "rtolev": None,        # stop PP-Arnoldi at this PP-GMRES relative residual (None: run arnoldi_m steps)
+    "nev": 40,             # Ritz pairs nearest the origin tested for deflation (nevch)
+    "rtolpoly1": None,     # stop the outer PP-GMRES of a double polynomial here (None: the configured n_out)
+    "gmres_m": 30,         # restart length of the top-level PP-GMRES
+    "solve_tol": 1e-6,     # rtolle
+}
+
+
 def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optional[int] = None,
-          arnoldi_m: int = 90, nev: int = 40, verbose: bool = False,
-          reuse: Optional["LatticeRun"] = None, gmres_m: int = 30, solve_tol: float = 1e-6,
-          two_row_links: bool = True, max_batch: int = 1 << 30) -> LatticeRun:
+          arnoldi_m: Optional[int] = None, nev: Optional[int] = None, verbose: bool = False,
+          reuse: Optional["LatticeRun"] = None, gmres_m: Optional[int] = None, solve_tol: Optional[float] = None,
+          two_row_links: bool = True, max_batch: int = 1 << 30, rtolev: Optional[float] = None,
+          rtolpoly1: Optional[float] = None) -> LatticeRun:
     """Set up a lattice workload: links, GMRES roots, PP-Arnoldi deflation,
     outer roots of composite polynomials (FP64 on the GPU, Sec. 5 setup
     step 2) and the level descriptors in precision `prec`.  With `reuse`,
@@ -195,9 +209,15 @@ def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optio
     FP32, FP64 residual) converging to solve_tol (rtolle).  Links that are
     SU(3) to 1e-12 are read as two rows (two_row_links).  A level's device
     buffers hold at most max_batch vectors; a step draws its samples in
-    samples / batch batches."""
+    samples / batch batches.  Set-up parameters not given here come from
+    cfg.extra, else SETUP_DEFAULTS."""
     t0 = time.perf_counter()
-    U = synth.gauge_links(cfg.dims, cfg.eps, cfg.seed_links)
+    given = dict(pin_degree=pin_degree, arnoldi_m=arnoldi_m, rtolev=rtolev, nev=nev, rtolpoly1=rtolpoly1,
+                 gmres_m=gmres_m, solve_tol=solve_tol)
+    prm = {k: (given[k] if given[k] is not None else cfg.extra.get(k, d)) for k, d in SETUP_DEFAULTS.items()}
+    pin_degree, arnoldi_m, rtolev, nev = prm["pin_degree"], prm["arnoldi_m"], prm["rtolev"], prm["nev"]
+    rtolpoly1, gmres_m, solve_tol = prm["rtolpoly1"], prm["gmres_m"], prm["solve_tol"]
+    U = synth.config_links(cfg)
     canon = torch.from_numpy(U).cuda()
     V = cfg.volume
 
@@ -228,7 +248,7 @@ def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optio
             d0 = reuse.defl
             defl = krylov.Deflation(L.DeviceDefl(d0.device.k, reuse.defl64_V, d0.device.pair, d0.device.scale,
                                                  d0.device.hinv), d0.lam, d0.pair, d0.res_right, d0.res_left,
-                                    d0.candidates)
+                                    d0.candidates, d0.arnoldi_steps, d0.arnoldi_residual)
         comps = reuse.composites
         dl64 = None
     else:
@@ -241,11 +261,13 @@ def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optio
             if pd not in roots.device:
                 extra = krylov.gmres_roots(dl64, [pd], start)
                 roots.inv_roots[pd], roots.device[pd] = extra.inv_roots[pd], extra.device[pd]
-            defl = krylov.pp_arnoldi_deflation(dl64, roots.device[pd], start, arnoldi_m, nev, cfg.k_defl)
+            defl = krylov.pp_arnoldi_deflation(dl64, roots.device[pd], start, arnoldi_m, nev, cfg.k_defl,
+                                               rtolev=rtolev)
         for key in comp_keys:
             n_in, n_out = key
             comps[key] = krylov.pp_outer_roots(dl64, roots.device[n_in - 1], roots.inv_roots[n_in - 1], defl,
-                                               n_out, L.Noise(cfg.seed_noise, cfg.lattice_id, 1000, 0))
+                                               n_out, L.Noise(cfg.seed_noise, cfg.lattice_id, 1000, 0),
+                                               rtol=rtolpoly1)
     defl64_V = defl.device.V if defl is not None else None
     dl = dl64 if (prec == L.F64 and dl64 is not None) else lattice(prec)
     if defl is not None and prec != L.F64:
@@ -258,6 +280,13 @@ def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optio
     run = LatticeRun(cfg, prec, rb, dl, roots, defl)
     run.defl64_V = defl64_V
     run.composites = comps
+    run.setup_params = prm
+
+    def mvps(p) -> int:
+        # a double polynomial stopped by rtolpoly1 has fewer outer roots than configured
+        if isinstance(p, tuple):
+            return p[0] * comps[p].n_out - 1
+        return poly_mvps(p)
     for i, lv in enumerate(cfg.levels):
         N = _batch_size(lv.samples, rb, max_batch)
         if lv.hi == SOLVE:
@@ -275,7 +304,7 @@ def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optio
             solver = MixedPPGMRES(l64, dl, roots.device[n_in - 1], defl.device if defl is not None else None,
                                   gmres_m, N, rb)
             ws = L.workspace(L.level_workspace_size(dl, dlev, N, rb))
-            st = LevelState(i, dlev, poly_mvps(lv.lo), None, torch.zeros(8, dtype=torch.float64, device="cuda"),
+            st = LevelState(i, dlev, mvps(lv.lo), None, torch.zeros(8, dtype=torch.float64, device="cuda"),
                             torch.empty((N, 6), dtype=torch.float64, device="cuda"), ws, solver=solver,
                             b64=L.empty_field(V, N, rb, L.F64), x64=x64, xl=xl, solve_tol=solve_tol, batch=N)
             run.levels.append(st)
@@ -291,7 +320,7 @@ def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optio
                              defl.device if c is not None else None, c is not None,
                              krylov._c(c) if c is not None else None)
         ws = L.workspace(L.level_workspace_size(dl, dlev, N, rb))
-        run.levels.append(LevelState(i, dlev, poly_mvps(lv.hi) + poly_mvps(lv.lo), c,
+        run.levels.append(LevelState(i, dlev, mvps(lv.hi) + mvps(lv.lo), c,
                                      torch.zeros(8, dtype=torch.float64, device="cuda"),
                                      torch.empty((N, 6), dtype=torch.float64, device="cuda"), ws, batch=N))
     torch.cuda.synchronize()

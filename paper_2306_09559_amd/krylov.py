@@ -229,16 +229,27 @@ class Deflation:
     res_right: np.ndarray
     res_left: np.ndarray
     candidates: int
+    arnoldi_steps: int = 0       # PP-Arnoldi steps taken
+    arnoldi_residual: float = float("nan")   # PP-GMRES relative residual on that basis
 
 
 def pp_arnoldi_deflation(dl: L.DeviceLattice, pin: L.DevicePoly, start: np.ndarray, m: int, nev: int,
-                         kmax: int, imaglim: float = 2e-4, evectol: float = 1e-3) -> Deflation:
-    """Setup step 2(b): PP-Arnoldi, Ritz pairs nearest the origin, selection."""
+                         kmax: int, imaglim: float = 2e-4, evectol: float = 1e-3,
+                         rtolev: Optional[float] = None) -> Deflation:
+    """Setup step 2(b): PP-Arnoldi, Ritz pairs nearest the origin, selection.
+    The Arnoldi run takes m steps, or stops earlier once the relative residual
+    of the PP-GMRES solution of B y = start on the same basis is at most
+    rtolev (the paper's stopping rule; a fixed step count is its "extra
+    deflation" set-up, Sec. 6.1)."""
     dims, V = dl.dims, dl.V
     ops = Operators(dl)
     ops.set_pin(pin)
     arn = DeviceArnoldi(dl, m)
-    H, beta, mm, _ = arn.run(ops.B, start)
+    stop = None
+    if rtolev is not None:
+        def stop(j, Hb, b):
+            return gmres_residual(Hb, b, j + 1) <= rtolev * b
+    H, beta, mm, _ = arn.run(ops.B, start, stop)
     mu, G = np.linalg.eig(H[:mm, :mm])
     idx = np.argsort(np.abs(mu))[:nev]
     kp = _pad16(nev)
@@ -312,6 +323,7 @@ def pp_arnoldi_deflation(dl: L.DeviceLattice, pin: L.DevicePoly, start: np.ndarr
             i += 1
     if not acc:
         raise RuntimeError("no eigenvalue passed the deflation selection")
+    arnoldi_steps = mm
     ka = len(acc)
     kpa = _pad16(ka)
     pos = {a: q for q, a in enumerate(acc)}
@@ -338,26 +350,34 @@ def pp_arnoldi_deflation(dl: L.DeviceLattice, pin: L.DevicePoly, start: np.ndarr
     Hm = UAV.cpu().numpy()[:, :ka]
     defl.hinv = _c(np.linalg.inv(Hm))
     torch.cuda.synchronize()
-    return Deflation(defl, lam, pr, np.array(rrs), np.array(rls), k)
+    return Deflation(defl, lam, pr, np.array(rrs), np.array(rls), k, arnoldi_steps,
+                     gmres_residual(H, beta, mm) / beta)
 
 
 @dataclass
 class OuterRoots:
     inv_roots: np.ndarray        # Leja-ordered 1/phi (host)
     device: L.DevicePoly         # composite p_in(A) p_out(A p_in(A))
-    residual: float              # PP-GMRES relative residual after n_out steps
+    residual: float              # PP-GMRES relative residual after the steps taken
+
+    @property
+    def n_out(self) -> int:
+        return len(self.inv_roots)
 
 
 def pp_outer_roots(dl: L.DeviceLattice, pin: L.DevicePoly, inv_in: np.ndarray, defl: Optional[Deflation],
-                   n_out: int, noise: L.Noise) -> OuterRoots:
+                   n_out: int, noise: L.Noise, rtol: Optional[float] = None) -> OuterRoots:
     """Setup step 2(c): the deflated double polynomial.  A Z4 start vector is
     deflated with one Left-right Projection (Sec. 2.1) when triplets are
-    given, then n_out steps of PP-GMRES on B = A p_in(A) from it; the
-    harmonic Ritz values of that step are the roots phi_j of the outer
+    given, then n_out steps of PP-GMRES on B = A p_in(A) from it -- or fewer:
+    with rtol (the paper's rtolpoly1) the run stops at the first step whose
+    GMRES residual is at most rtol times the norm of the Z4 vector.  The
+    harmonic Ritz values of the last step are the roots phi_j of the outer
     residual polynomial pi_out(beta), beta = a p_in(a) (Sec. 3.2, Sec. 4.3)."""
     dims, V = dl.dims, dl.V
     b = L.empty_field(V, 1, 1, F64)
     L.z4_fill(dims, F64, noise, b)
+    ref = float(np.sqrt(12.0 * V))               # || Z4 vector ||: every entry has modulus 1
     if defl is not None:
         r = L.empty_field(V, 1, 1, F64)
         d = torch.empty((defl.device.k, 1), dtype=torch.complex128, device="cuda")
@@ -370,7 +390,11 @@ def pp_outer_roots(dl: L.DeviceLattice, pin: L.DevicePoly, inv_in: np.ndarray, d
     ops = Operators(dl)
     ops.set_pin(pin)
     arn = DeviceArnoldi(dl, n_out)
-    H, beta, m, _ = arn.run(ops.B, start)
+    stop = None
+    if rtol is not None:
+        def stop(j, Hb, bt):
+            return gmres_residual(Hb, bt, j + 1) <= rtol * ref
+    H, beta, m, _ = arn.run(ops.B, start, stop)
     phi = leja(harmonic_ritz_values(H, m))
     inv = 1.0 / phi
-    return OuterRoots(inv, L.DevicePoly(_c(inv_in), _c(inv)), gmres_residual(H, beta, m) / beta)
+    return OuterRoots(inv, L.DevicePoly(_c(inv_in), _c(inv)), gmres_residual(H, beta, m) / ref)

@@ -46,6 +46,33 @@ def gauge_links(dims, eps: float, seed: int) -> np.ndarray:
     return np.ascontiguousarray(U.astype(np.complex128))
 
 
+def tiled_links(dims, base_dims, eps: float, seed: int) -> np.ndarray:
+    """gauge_links(base_dims, eps, seed) repeated periodically over `dims`
+    (every extent a multiple of the base's): the link at (x, y, z, t) is the
+    base link at (x mod bx, y mod by, z mod bz, t mod bt).  With periodic
+    boundaries in every direction each eigenpair of the base operator gives
+    one of the tiled operator (the eigenvector repeated), so the tiled
+    lattice keeps the base's spectral edge at any size."""
+    if any(d % b for d, b in zip(dims, base_dims)):
+        raise ValueError(f"{dims} is not a multiple of {base_dims}")
+    base = gauge_links(base_dims, eps, seed)
+    lx, ly, lz, lt = dims
+    bx, by, bz, bt = base_dims
+    s = np.arange(volume(dims))
+    x, y, z, t = s % lx, (s // lx) % ly, (s // (lx * ly)) % lz, s // (lx * ly * lz)
+    bs = (x % bx) + bx * ((y % by) + by * ((z % bz) + bz * (t % bt)))
+    return np.ascontiguousarray(base[:, bs])
+
+
+def config_links(cfg) -> np.ndarray:
+    """The links of a workload configuration: tiled from a smaller lattice
+    when its `extra` names one ("tile_from"), else gauge_links."""
+    tile = cfg.extra.get("tile_from") if cfg.extra else None
+    if tile is not None:
+        return tiled_links(cfg.dims, tuple(tile), cfg.eps, cfg.seed_links)
+    return gauge_links(cfg.dims, cfg.eps, cfg.seed_links)
+
+
 def unit_links(dims) -> np.ndarray:
     """The free field: every link is the 3x3 identity."""
     V = volume(dims)

@@ -93,12 +93,37 @@ C3 = LatticeConfig(
     description="16^3x32, n=1.57M, composite poly 20x15 (deg 299), 64 RHS, FP32 bulk / FP64 sums",
 )
 
+# Near-critical 16^3x32 top level (n = 1.57M): the links of the 8^4 workload
+# tiled 2x2x2x4 with its periodic time and kappa, so the eigenvalue of A
+# nearest the origin keeps modulus 1e-3 (every eigenpair of the 8^4 operator
+# is one of the tiled one).  Two set-ups of the deflation, after Example 3 and
+# Sec. 6.1: "regular" runs PP(50)-Arnoldi until its PP-GMRES residual is
+# 1e-12 (rtolev, Example 2); "extra" runs PP(70)-Arnoldi for a fixed 150
+# steps.  Both test the 60 Ritz pairs nearest the origin, grow the outer
+# polynomial of the deflated p_1 = p_in(A) p_out(A p_in(A)) until its PP-GMRES
+# residual is 1e-5 (rtolpoly1, at most 50 roots) and solve with
+# PP(dp_in+1)-GMRES(50) to 1e-6 (rtolle).
+_C3N = dict(dims=(16, 16, 16, 32), eps=0.3, kappa=0.13241373193166625, antiperiodic_t=False, k_defl=60,
+            seed_links=201, seed_start=302, seed_noise=303, lattice_id=6)
+C3R = LatticeConfig(
+    name="C3R", levels=(Level(SOLVE, (50, 50), 64, deflated=True),), **_C3N,
+    description="near-critical 16^3x32 (8^4 links tiled), top level, regular deflation: PP(50)-Arnoldi to 1e-12",
+    extra={"tile_from": (8, 8, 8, 8), "arnoldi_m": 250, "rtolev": 1e-12, "nev": 60, "rtolpoly1": 1e-5,
+           "gmres_m": 50},
+)
+C3X = LatticeConfig(
+    name="C3X", levels=(Level(SOLVE, (70, 50), 64, deflated=True),), **_C3N,
+    description="near-critical 16^3x32 (8^4 links tiled), top level, extra deflation: PP(70)-Arnoldi(150)",
+    extra={"tile_from": (8, 8, 8, 8), "arnoldi_m": 150, "nev": 60, "rtolpoly1": 1e-5, "gmres_m": 50},
+)
+
 C4 = LatticeConfig(
     name="C4", dims=(24, 24, 24, 48), eps=0.5, kappa=0.150,
     levels=(Level((20, 15), 60, 32, deflated=True), Level(60, 15, 128, deflated=True),
             Level(15, 4, 512, deflated=True), Level(4, None, 2048)),
     k_defl=128, seed_links=401, seed_start=402, seed_noise=403, lattice_id=4,
     description="24^3x48, n=7.96M complex64, 4 levels 299/60/15/4, 128 eigvecs, 32/128/512/2048 samples",
+    extra={"arnoldi_m": 200, "nev": 160},
 )
 
 C5 = tuple(
@@ -113,4 +138,4 @@ C5 = tuple(
     ])
 )
 
-CONFIGS = {"C1": C1, "C2": C2, "C3": C3, "C4": C4}
+CONFIGS = {"C1": C1, "C2": C2, "C3": C3, "C3R": C3R, "C3X": C3X, "C4": C4}

@@ -70,3 +70,71 @@ def test_pp_arnoldi_deflation_small():
     H = np.linalg.inv(df.device.hinv.cpu().numpy())
     assert np.allclose(np.diag(H), df.lam, atol=1e-6)
     assert np.max(np.abs(H - np.diag(np.diag(H)))) < 1e-5
+
+
+def test_outer_roots_rtolpoly1_matches_oracle():
+    """The outer PP-GMRES stopped by rtolpoly1 (relative to the Z4 start
+    vector, R16) takes the oracle's number of steps and gives its roots."""
+    from paper_2306_09559_amd import krylov
+    L = lib()
+    dims = (4, 4, 4, 4)
+    dl, ol = device_lattice(dims, 0.15, 0.5, 101, True)
+    start = synth.gaussian_start(ol.n, 5)
+    rs = krylov.gmres_roots(dl, [5], start)
+    t_in = rs.inv_roots[5]
+    out = krylov.pp_outer_roots(dl, rs.device[5], t_in, None, 60, L.Noise(31, 3, 1000, 0), rtol=1e-7)
+    r0 = oracle.z4(31, 3, 1000, 0, 1, dl.V)[0]
+    opB = okr.pp_operator(ol.apply, t_in, lambda t, v: ol.poly_apply(t, v)[0])
+    t_out, arn = okr.pp_gmres_roots(opB, r0, n_out=60, rtol=1e-7, rnorm_ref=np.linalg.norm(r0))
+    assert out.n_out == arn.m < 60
+    assert _matched(1.0 / out.inv_roots, 1.0 / t_out) < 1e-8 * np.max(np.abs(1.0 / t_out))
+    assert out.residual <= 1e-7
+
+
+def test_pp_arnoldi_rtolev_matches_oracle():
+    """PP-Arnoldi stopped by rtolev takes the oracle's number of steps; the
+    accepted eigenvalues are eigenvalues of the dense matrix."""
+    from paper_2306_09559_amd import krylov
+    dims = (2, 2, 2, 4)
+    dl, ol = device_lattice(dims, 0.16, 0.5, 21, True)
+    start = synth.gaussian_start(ol.n, 3)
+    rs = krylov.gmres_roots(dl, [6], start)
+    df = krylov.pp_arnoldi_deflation(dl, rs.device[6], start, 120, 16, 8, rtolev=1e-10)
+    opB = okr.pp_operator(ol.apply, rs.inv_roots[6], lambda t, v: ol.poly_apply(t, v)[0])
+    _, _, _, arn = okr.pp_arnoldi_ritz(opB, ol.apply, start, 120, 16, rtol=1e-10)
+    assert df.arnoldi_steps == arn.m < 120
+    assert df.arnoldi_residual <= 1e-10
+    ev = np.linalg.eigvals(dense.dense_matrix(ol))
+    # z^H A z of a unit right vector z is within ||A z - lambda z|| / |u^H z| of
+    # the eigenvalue (u the unit left vector, |u^H z| = 1 / |scale|), to first order
+    scale = np.abs(df.device.scale.cpu().numpy()[: df.device.k])
+    for l, rr, sc in zip(df.lam, df.res_right, scale):
+        err = np.min(np.abs(ev - l))
+        print(f"lambda {l:.6f}: error {err:.2e}, residual {rr:.2e}, 1/|u^H z| {sc:.3g}")
+        assert err <= max(1e-9, 2.0 * rr * sc)
+
+
+def test_extra_deflation_setup_small():
+    """The extra-deflation set-up (Sec. 6.1) end to end on a 4^4 lattice: a
+    fixed-length PP-Arnoldi, the selection, the deflated double polynomial
+    grown to rtolpoly1, and deflated PP-GMRES(m) top-level solves."""
+    import dataclasses
+    from paper_2306_09559_amd import driver
+    from synth.configs import C1, Level, SOLVE
+    L = lib()
+    cfg = dataclasses.replace(C1, name="C1X", levels=(Level(SOLVE, (8, 30), 16, deflated=True),), k_defl=20,
+                              extra={"arnoldi_m": 40, "nev": 24, "rtolpoly1": 1e-5, "gmres_m": 20})
+    run = driver.build(cfg, prec=L.F32, rb=16)
+    df = run.defl
+    assert df.arnoldi_steps == 40 and df.candidates == 24
+    assert 0 < df.device.k <= 20
+    assert np.all(df.res_right < 1e-3) and np.all(df.res_left < 1e-3)
+    comp = run.composites[(8, 30)]
+    assert comp.n_out == 30 or comp.residual <= 1e-5
+    assert run.levels[0].mvps_per_sample == 8 * comp.n_out - 1
+    assert run.levels[0].solver.m == 20
+    run.draw(0, 16)
+    torch.cuda.synchronize()
+    assert np.max(run.levels[0].last_solve.rel_res) <= 1e-6
+    e = run.estimates()[0]
+    assert e["n"] == 16 and np.isfinite(e["estimate"])

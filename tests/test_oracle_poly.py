@@ -143,3 +143,44 @@ def test_degree_arithmetic():
     assert poly_mvps((50, 33)) == 1649
     assert poly_mvps((20, 15)) == 299
     assert 615 ** 2 == 378225 and 30 ** 2 + 31 ** 2 == 1861
+
+
+@pytest.mark.parametrize("rtol", [1e-3, 1e-6])
+def test_pp_gmres_rtol_stops_at_first_crossing(rtol):
+    """rtolpoly1 (Sec. 5 step 2c): the outer PP-GMRES stops at the first step
+    whose residual r0 - B x_j, formed explicitly from the Krylov basis and B,
+    is at most rtol ||ref||; the step before it is still above."""
+    lat = _lat((2, 2, 2, 2), kappa=0.16)
+    r0 = synth.gaussian_start(lat.n, 12)
+    ps = krylov.gmres_polys(lat.apply, r0, [3])
+    t_in = ps.inv_roots[3]
+    opB = krylov.pp_operator(lat.apply, t_in, lambda t, v: lat.poly_apply(t, v)[0])
+    ref = 2.0 * np.linalg.norm(r0)
+    _, arn = krylov.pp_gmres_roots(opB, r0, rtol=rtol, rnorm_ref=ref)
+    m = arn.m
+
+    def explicit(j):
+        y, _ = krylov.gmres_ls(arn.Hbar, arn.beta, j)
+        return np.linalg.norm(r0 - opB(arn.Vb[:j].T @ y))
+
+    assert explicit(m) <= rtol * ref * (1 + 1e-9)
+    assert m == 1 or explicit(m - 1) > rtol * ref
+
+
+def test_pp_arnoldi_rtolev_stops_at_first_crossing():
+    """rtolev (Sec. 5 step 2b): PP-Arnoldi stops at the first step where the
+    PP-GMRES solution of B y = r0 on its basis has relative residual <= rtolev."""
+    lat = _lat((2, 2, 2, 2), kappa=0.16)
+    r0 = synth.gaussian_start(lat.n, 13)
+    ps = krylov.gmres_polys(lat.apply, r0, [3])
+    opB = krylov.pp_operator(lat.apply, ps.inv_roots[3], lambda t, v: lat.poly_apply(t, v)[0])
+    lam, Z, AZ, arn = krylov.pp_arnoldi_ritz(opB, lat.apply, r0, 200, 8, rtol=1e-8)
+    m = arn.m
+
+    def explicit(j):
+        y, _ = krylov.gmres_ls(arn.Hbar, arn.beta, j)
+        return np.linalg.norm(r0 - opB(arn.Vb[:j].T @ y)) / np.linalg.norm(r0)
+
+    assert m < 200
+    assert explicit(m) <= 1e-8 * (1 + 1e-6)
+    assert explicit(m - 1) > 1e-8
