@@ -456,6 +456,14 @@ def main():
                                    round(sum(x.estimate for x in res).imag, 3)],
                 "levels": [{"n": x.n, "stderr": round(x.stderr, 4), "seconds": round(x.seconds, 4)} for x in res]}
     if not args.no_extra:
+        # variance of the deflated levels against the number of deflated eigenvectors (Sec. 4.1)
+        from paper_2306_09559_amd import diagnostics
+        prof = {}
+        for li in (0, 1):
+            p = diagnostics.level_variance_profile(run, li, run.levels[li].batch)
+            prof[f"level{li}"] = {"variance_vs_k": [float(f"{v:.4g}") for v in p.variance],
+                                  "reproduction_error": float(f"{p.reproduction_error:.2g}")}
+        out["deflation_profile"] = prof
         out["batched_lattices"] = batched_c5(args.steps)
         out["top_level"] = top_level_c3()
         # a near-critical 16^3x32 top level with the regular and the extra-deflation set-up (Sec. 6.1)
