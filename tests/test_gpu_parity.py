@@ -414,10 +414,11 @@ def test_level_accumulates_batches_and_is_deterministic():
     ((8, 8, 8, 4), True, 1, 16, 16, True),     # FP32
     # planes larger than one workgroup: xyz-blocks with a halo (FP32), with
     # enough vectors for a workgroup's worth of threads per CU (256 CUs)
-    ((8, 8, 16, 4), True, 1, 128, 4, True),    # two blocks, cut in z
-    ((16, 8, 8, 3), True, 1, 128, 2, False),   # cut in x, field input, odd Lt
-    ((12, 12, 12, 2), True, 1, 80, 8, True),   # 4 x 4 x 12 blocks, cut in x and y
-    ((16, 16, 16, 2), False, 1, 32, 4, True),  # eight blocks of a 16^3 plane
+    ((8, 8, 16, 4), True, 1, 128, 4, True),    # 8 x 8 x 8 blocks, cut in z
+    ((16, 8, 8, 3), True, 1, 128, 2, False),   # 16 x 4 x 8 blocks, field input, odd Lt
+    ((12, 12, 12, 2), True, 1, 80, 8, True),   # 12 x 4 x 4 blocks, cut in y and z
+    ((16, 16, 16, 2), False, 1, 32, 4, True),  # eight 16 x 4 x 8 blocks of a 16^3 plane
+    ((32, 8, 8, 2), True, 1, 64, 16, True),    # 16 x 4 x 8 blocks, cut in x and y
 ])
 def test_sweep_matches_oracle_and_streaming(dims, ap, prec, nrhs, rb, z4):
     L = lib()
@@ -425,6 +426,7 @@ def test_sweep_matches_oracle_and_streaming(dims, ap, prec, nrhs, rb, z4):
     plan = L.sweep_plan(dl, nrhs, rb)
     P = dims[0] * dims[1] * dims[2]
     assert plan["ok"] and plan["halo"] == (P > 512), plan
+    print(dims, "block", plan["block"], "halo sites", plan["halo_sites"])
     deg = 9
     t = krylov.gmres_polys(ol.apply, synth.gaussian_start(ol.n, 1), [deg]).inv_roots[deg]
     poly = L.DevicePoly(dev_c128(t))
