@@ -82,6 +82,20 @@ __global__ void k_copy_vector(const cplx_t<T> *src, int src_rb, int src_r, cplx_
     dst[fidx(dst_r, c, s, V, dst_rb)] = src[fidx(src_r, c, s, V, src_rb)];
 }
 
+// a whole batch from block width src_rb to dst_rb, one thread per destination element
+template <typename T>
+__global__ void k_relayout(const cplx_t<T> *src, int src_rb, cplx_t<T> *dst, int dst_rb, int V, int nrhs) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (size_t)nrhs * 12 * (size_t)V) return;
+    const int j = (int)(e % (size_t)dst_rb);
+    size_t rest = e / (size_t)dst_rb;
+    const int s = (int)(rest % (size_t)V);
+    rest /= (size_t)V;
+    const int c = (int)(rest % 12);
+    const int r = (int)(rest / 12) * dst_rb + j;
+    dst[e] = src[fidx(r, c, s, V, src_rb)];
+}
+
 // y = alpha x + beta y across precisions, coefficients applied in FP64
 template <typename TX, typename TY>
 __global__ void k_axpby_mixed(const double2 *alpha, const cplx_t<TX> *x, const double2 *beta, cplx_t<TY> *y, int V,
@@ -310,6 +324,19 @@ int field_block_axpy_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, in
     else
         hipLaunchKernelGGL(k_block_axpy<float>, dim3(g), dim3(256), 0, s, (const float2 *)basis, F, k,
                            (const double2 *)coeff, accumulate, (float2 *)y, V, sh.rb, sh.nrhs);
+    return st();
+}
+
+int field_relayout_impl(const int32_t dims[4], int32_t prec, int32_t nrhs, const void *src, int32_t src_rb, void *dst,
+                        int32_t dst_rb, void *stream) {
+    const int V = dims[0] * dims[1] * dims[2] * dims[3];
+    const unsigned g = (unsigned)(((size_t)nrhs * 12 * (size_t)V + 255) / 256);
+    if (prec == MPMC_F64)
+        hipLaunchKernelGGL(k_relayout<double>, dim3(g), dim3(256), 0, (hipStream_t)stream, (const double2 *)src, src_rb,
+                           (double2 *)dst, dst_rb, V, nrhs);
+    else
+        hipLaunchKernelGGL(k_relayout<float>, dim3(g), dim3(256), 0, (hipStream_t)stream, (const float2 *)src, src_rb,
+                           (float2 *)dst, dst_rb, V, nrhs);
     return st();
 }
 

@@ -566,6 +566,49 @@ static int newton_t(const mpmc_lattice &lat, mpmc_shape sh, int n, const double 
     return MPMC_OK;
 }
 
+// b^H p_in(A) p_out(A p_in(A)) b for the noise b, the input (x, or b when x
+// is null) moved to block width 1 first; see poly_apply_t
+template <typename T>
+static int composite_sweep_t(const mpmc_lattice &lat, const mpmc_poly &poly, mpmc_shape sh, mpmc_shape sh1,
+                             const SweepPlan &plan, const void *x, uint64_t key, uint64_t first, const uint64_t *off,
+                             double *bhy, const PolyWs &ws, void *stream) {
+    void *U0 = ws.f[0], *U1 = ws.f[1], *V0 = ws.f[2], *V1 = ws.f[3], *Y = ws.f[4];
+    const int32_t prec = sizeof(T) == 8 ? MPMC_F64 : MPMC_F32;
+    int st;
+    if (x != nullptr)
+        st = field_relayout_impl(lat.dims, prec, sh.nrhs, x, sh.rb, U0, 1, stream);
+    else
+        st = copy_or_noise_t<T>(lat, sh1, nullptr, key, first, off, U0, stream);
+    if (st != MPMC_OK) return st;
+    HopArgs<T> a = base_args<T>(lat, sh1);
+    a.troots = (const double2 *)poly.inv_roots_in;
+    a.phi = (const double2 *)poly.inv_roots_out;
+    void *ucur = U0, *unext = U1;
+    const int n_in = poly.n_in, n_out = poly.n_out;
+    for (int jo = 0; jo + 1 < n_out; ++jo) {
+        const void *vin = nullptr;
+        st = sweep_chain_t<T>(lat, sh1, plan, n_in - 1, poly.inv_roots_in, ucur, 1, V0, V1, &vin, stream);
+        if (st != MPMC_OK) return st;
+        // last inner step with the outer update: u_next, y (the chain left V0 or V1 free)
+        a.j = n_in - 1;
+        a.in = (const cplx_t<T> *)vin;
+        a.u = (const cplx_t<T> *)ucur;
+        a.u_next = (cplx_t<T> *)unext;
+        a.y = (cplx_t<T> *)Y;
+        a.jo = jo;
+        a.y_first = (jo == 0);
+        a.jo_last = (jo + 2 == n_out);
+        launch_hop<T>(a, false, false, false, true, false, stream);
+        if (hipGetLastError() != hipSuccess) return MPMC_EHIP;
+        void *tmp = ucur;
+        ucur = unext;
+        unext = tmp;
+    }
+    // final p_in(A) applied to y_out, dot against the noise
+    return sweep_newton_t<T>(lat, sh1, plan, n_in, poly.inv_roots_in, Y, false, nullptr, key, first, off,
+                             (double2 *)ws.part, (double2 *)bhy, V0, V1, stream);
+}
+
 template <typename T>
 int poly_apply_t(const mpmc_lattice &lat, const mpmc_poly &poly, mpmc_shape sh, const void *x, const mpmc_noise *noise,
                  void *y, double *bhy, const PolyWs &ws, void *stream) {
@@ -584,6 +627,14 @@ int poly_apply_t(const mpmc_lattice &lat, const mpmc_poly &poly, mpmc_shape sh, 
         if (plan.ok)
             return sweep_newton_t<T>(lat, sh, plan, poly.n_in, poly.inv_roots_in, x, x_noise, bvec, key, first, off,
                                      part, (double2 *)bhy, ws.f[0], ws.f[1], stream);
+    }
+    if (poly.n_out >= 2 && poly.n_in >= 2 && y == nullptr && bhy != nullptr && noise != nullptr && g_opt_sweep) {
+        // scalar-mode double polynomial against the noise: the n_in - 1 plain
+        // steps of every inner chain and the final p_in run as t-sweeps, the
+        // fused outer update on the streaming kernel, all at block width 1
+        const mpmc_shape sh1{sh.nrhs, 1};
+        const SweepPlan plan = sweep_plan(lat, sh1);
+        if (plan.ok) return composite_sweep_t<T>(lat, poly, sh, sh1, plan, x, key, first, off, bhy, ws, stream);
     }
     if (poly.n_out == 0) {
         st = newton_t<T>(lat, sh, poly.n_in, poly.inv_roots_in, x, x_noise, bvec, key, first, off, y, part, ws.f[0],

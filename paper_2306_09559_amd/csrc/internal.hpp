@@ -45,6 +45,13 @@ int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, const SweepPlan &plan
                    const void *x, bool x_is_noise, const void *bvec, uint64_t key, uint64_t first, const uint64_t *off,
                    double2 *part, double2 *bhy, void *w0, void *w1, void *stream);
 
+// count plain Newton steps w <- w - t_j A w (j = 0 .. count-1, no dot) of
+// nrhs vectors from `in` (block width rb_in); outputs alternate w0, w1 at
+// block width 1.  *out is the last output (in itself when count is 0).
+template <typename T>
+int sweep_chain_t(const mpmc_lattice &lat, mpmc_shape sh, const SweepPlan &plan, int count, const double *troots,
+                  const void *in, int rb_in, void *w0, void *w1, const void **out, void *stream);
+
 // process-wide options (mpmc_set_option)
 extern int g_opt_sweep;
 
@@ -73,6 +80,8 @@ int field_axpby_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, const d
 size_t field_dot_ws_bytes(const int32_t dims[4], mpmc_shape sh);
 int field_dot_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, const void *x, const void *y, double *out,
                    void *ws, void *stream);
+int field_relayout_impl(const int32_t dims[4], int32_t prec, int32_t nrhs, const void *src, int32_t src_rb, void *dst,
+                        int32_t dst_rb, void *stream);
 int field_copy_vector_impl(const int32_t dims[4], int32_t prec, mpmc_shape ssh, const void *src, int32_t si,
                            mpmc_shape dsh, void *dst, int32_t di, void *stream);
 int field_axpby_mixed_impl(const int32_t dims[4], mpmc_shape sh, int32_t xp, const double *alpha, const void *x,

@@ -832,6 +832,66 @@ int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, const SweepPlan &plan
     return MPMC_OK;
 }
 
+template <typename T>
+int sweep_chain_t(const mpmc_lattice &lat, mpmc_shape sh, const SweepPlan &plan, int count, const double *troots,
+                  const void *in, int rb_in, void *w0, void *w1, const void **out, void *stream) {
+    *out = in;
+    if (count <= 0) return MPMC_OK;
+    SweepArgs<T> a{};
+    for (int d = 0; d < 4; ++d) a.L[d] = lat.dims[d];
+    a.P = lat.dims[0] * lat.dims[1] * lat.dims[2];
+    a.V = a.P * lat.dims[3];
+    a.apbc = lat.antiperiodic_t;
+    a.gauge = (const cplx_t<T> *)lat.gauge;
+    a.two_rows = lat.link_rows == 2;
+    a.troots = (const double2 *)troots;
+    a.kappa = lat.kappa;
+    for (int d = 0; d < 3; ++d) a.B[d] = plan.B[d];
+    a.Pb = plan.Pb;
+    a.Hb = plan.Hb;
+    a.nbp = plan.nbp;
+    // [halo][link rows 3 | 2]; blocks with a halo are FP32 only
+    const void *kern[2][2] = {{(const void *)k_sweep<T, false, false, false, false, false, false>,
+                               (const void *)k_sweep<T, false, false, false, false, true, false>},
+                              {nullptr, nullptr}};
+    if constexpr (sizeof(T) == 4) {
+        kern[1][0] = (const void *)k_sweep<T, false, false, false, false, false, true>;
+        kern[1][1] = (const void *)k_sweep<T, false, false, false, false, true, true>;
+    }
+    static bool attr_set[2] = {false, false};
+    const int pi = sizeof(T) == 8 ? 0 : 1;
+    if (!attr_set[pi]) {
+        for (int h = 0; h < 2; ++h)
+            for (int tw = 0; tw < 2; ++tw)
+                if (kern[h][tw] && hipFuncSetAttribute(kern[h][tw], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       160 * 1024) != hipSuccess)
+                    return MPMC_EHIP;
+        attr_set[pi] = true;
+    }
+    const void *k = kern[plan.halo ? 1 : 0][lat.link_rows == 2 ? 1 : 0];
+    if (!k) return MPMC_EUNSUPPORTED;
+    const dim3 grid((unsigned)(sh.nrhs * plan.nbp)), block((unsigned)plan.Pb);
+    const void *cur = in;
+    for (int j = 0; j < count; ++j) {
+        a.j = j;
+        a.in = (const cplx_t<T> *)cur;
+        a.rb_in = j == 0 ? rb_in : 1;
+        void *o = (j % 2 == 0) ? w0 : w1;
+        a.out = (cplx_t<T> *)o;
+        void *args[] = {&a};
+        if (hipLaunchKernel(k, grid, block, args, plan.lds, (hipStream_t)stream) != hipSuccess) return MPMC_EHIP;
+        if (hipGetLastError() != hipSuccess) return MPMC_EHIP;
+        cur = o;
+    }
+    *out = cur;
+    return MPMC_OK;
+}
+
+template int sweep_chain_t<double>(const mpmc_lattice &, mpmc_shape, const SweepPlan &, int, const double *,
+                                   const void *, int, void *, void *, const void **, void *);
+template int sweep_chain_t<float>(const mpmc_lattice &, mpmc_shape, const SweepPlan &, int, const double *,
+                                  const void *, int, void *, void *, const void **, void *);
+
 template int sweep_newton_t<double>(const mpmc_lattice &, mpmc_shape, const SweepPlan &, int, const double *,
                                     const void *, bool, const void *, uint64_t, uint64_t, const uint64_t *, double2 *,
                                     double2 *, void *, void *, void *);
