@@ -606,7 +606,7 @@ static int composite_sweep_t(const mpmc_lattice &lat, const mpmc_poly &poly, mpm
     }
     // final p_in(A) applied to y_out, dot against the noise
     return sweep_newton_t<T>(lat, sh1, plan, n_in, poly.inv_roots_in, Y, false, nullptr, key, first, off,
-                             (double2 *)ws.part, (double2 *)bhy, V0, V1, stream);
+                             (double2 *)ws.part, (double2 *)bhy, V0, V1, nullptr, stream);
 }
 
 template <typename T>
@@ -626,7 +626,18 @@ int poly_apply_t(const mpmc_lattice &lat, const mpmc_poly &poly, mpmc_shape sh, 
         const SweepPlan plan = sweep_plan(lat, sh);
         if (plan.ok)
             return sweep_newton_t<T>(lat, sh, plan, poly.n_in, poly.inv_roots_in, x, x_noise, bvec, key, first, off,
-                                     part, (double2 *)bhy, ws.f[0], ws.f[1], stream);
+                                     part, (double2 *)bhy, ws.f[0], ws.f[1], nullptr, stream);
+    }
+    if (poly.n_out == 0 && poly.n_in >= 2 && y != nullptr && sh.rb == 1 && (noise != nullptr || bhy == nullptr) &&
+        g_opt_sweep) {
+        // vector mode on the t-sweep: y (block width 1, like the sweep's own
+        // outputs) accumulates t_j w_j in the same launches; only when the
+        // batch fills the GPU (the sweep walks all planes per workgroup)
+        const SweepPlan plan = sweep_plan(lat, sh);
+        if (plan.ok && plan.fills)
+            return sweep_newton_t<T>(lat, sh, plan, poly.n_in, poly.inv_roots_in, x, x_noise, bhy ? bvec : nullptr,
+                                     key, first, off, bhy ? part : nullptr, (double2 *)bhy, ws.f[0], ws.f[1], y,
+                                     stream);
     }
     if (poly.n_out >= 2 && poly.n_in >= 2 && y == nullptr && bhy != nullptr && noise != nullptr && g_opt_sweep) {
         // scalar-mode double polynomial against the noise: the n_in - 1 plain

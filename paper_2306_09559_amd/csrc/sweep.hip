@@ -43,6 +43,9 @@ template <typename T> struct SweepArgs {
     // xyz-blocks (HALO): block extents, sites, halo sites, blocks per plane
     int B[3];
     int Pb, Hb, nbp;
+    // vector mode (YACC): y (block width 1) accumulates t_j w_j, zeroed first, + t_{j+1} w_{j+1} last
+    cplx_t<T> *y;
+    int y_first, y_last;
 };
 
 namespace {
@@ -321,7 +324,7 @@ __device__ __forceinline__ void dot_acc(const cplx_t<T> (&b)[12], const cplx_t<T
 // for one workgroup's LDS) and stages a one-site halo of the neighbouring
 // blocks next to it; without HALO the block is the whole plane and the x, y,
 // z neighbours wrap inside it.
-template <typename T, bool IN_Z4, bool DOT, bool FIRST, bool BFIELD, bool TWO, bool HALO>
+template <typename T, bool IN_Z4, bool DOT, bool FIRST, bool BFIELD, bool TWO, bool HALO, bool YACC = false>
 __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
     using C = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -614,6 +617,19 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
             }
             dot_acc<T>(b, acc, dre, dim);
         }
+        if constexpr (YACC) {
+            // y += t_j w_j (+ t_{j+1} w_{j+1} after the last step); w_j is still
+            // this site's entry of the LDS plane, so it costs no registers
+            const Plane<T> yp = plane_of<T>(a.y, r, a.V, 1);
+            const double2 tn = a.y_last ? a.troots[a.j + 1] : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                C yv = a.y_first ? mk<T>(T(0), T(0)) : yp.ld(c, s);
+                yv = axpy_d<T>(tj, lds[c * Sl + q], yv);
+                if (a.y_last) yv = axpy_d<T>(tn, acc[c], yv);
+                yp.st(c, s, yv);
+            }
+        }
         __syncthreads();
 #pragma unroll
         for (int c = 0; c < 12; ++c) cur[c] = nxt[c];
@@ -682,6 +698,13 @@ SweepPlan sweep_plan(const mpmc_lattice &lat, mpmc_shape sh) {
     const size_t V = (size_t)P * (size_t)Lt;
     if (36 * V * csz >= ((size_t)1 << 32)) return p;          // 32-bit link offsets
     const size_t kLds = 160 * 1024;
+    static int cus[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return p;
+    if (!cus[dev] && hipDeviceGetAttribute(&cus[dev], hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return p;
+    const size_t min_threads = (size_t)cus[dev] * 512;
+    p.fills = (size_t)sh.nrhs * (size_t)P >= min_threads;
     if (P >= 64 && P <= 512 && P % 64 == 0 && 18 * (size_t)P * csz <= kLds) {
         // the whole xyz-plane in one workgroup (neighbours wrap inside it)
         p.ok = true;
@@ -696,13 +719,7 @@ SweepPlan sweep_plan(const mpmc_lattice &lat, mpmc_shape sh) {
     // A blocked sweep walks all Lt planes inside each workgroup: it pays only
     // when the launch still gives every CU a full workgroup's worth of
     // threads; small batches on large planes stay on the streaming kernel.
-    static int cus[64] = {};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return p;
-    if (!cus[dev] && hipDeviceGetAttribute(&cus[dev], hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        return p;
-    const size_t min_threads = (size_t)cus[dev] * 512;
-    if ((size_t)sh.nrhs * (size_t)P < min_threads) return p;
+    if (!p.fills) return p;
     // partial sums: one per (vector, block) in the polynomial workspace
     const size_t spw = 256 / (size_t)sh.rb;
     const size_t avail = ((V + spw - 1) / spw) * (size_t)sh.nrhs;
@@ -750,10 +767,45 @@ SweepPlan sweep_plan(const mpmc_lattice &lat, mpmc_shape sh) {
     return p;
 }
 
+// kernel of one launch: v = 0 noise input (first step), 1 field input (first
+// step), 2 a later step; dot: accumulate b^H w partials (b the noise, or the
+// field bvec when bf); yacc: vector mode.  Blocks with a halo are FP32 only;
+// vector mode has no field dot vector.
+template <typename T, bool Y, bool D, bool BF, bool TW, bool H> static const void *sweep_kernel_v(int v) {
+    if (v == 0) return (const void *)k_sweep<T, true, D, true, BF, TW, H, Y>;
+    if (v == 1) return (const void *)k_sweep<T, false, D, true, BF, TW, H, Y>;
+    return (const void *)k_sweep<T, false, D, false, BF, TW, H, Y>;
+}
+template <typename T, bool Y, bool D, bool BF> static const void *sweep_kernel_h(bool tw, bool h, int v) {
+    if (h) {
+        if constexpr (sizeof(T) == 4)
+            return tw ? sweep_kernel_v<T, Y, D, BF, true, true>(v) : sweep_kernel_v<T, Y, D, BF, false, true>(v);
+        return nullptr;
+    }
+    return tw ? sweep_kernel_v<T, Y, D, BF, true, false>(v) : sweep_kernel_v<T, Y, D, BF, false, false>(v);
+}
+template <typename T> static const void *sweep_kernel(bool yacc, bool dot, bool bf, bool tw, bool h, int v) {
+    if (!dot && !yacc && v < 2) return nullptr;   // the plain chain has no first-step variants
+    if (yacc) {
+        if (bf) return nullptr;
+        return dot ? sweep_kernel_h<T, true, true, false>(tw, h, v) : sweep_kernel_h<T, true, false, false>(tw, h, v);
+    }
+    if (!dot) return bf ? nullptr : sweep_kernel_h<T, false, false, false>(tw, h, v);
+    return bf ? sweep_kernel_h<T, false, true, true>(tw, h, v) : sweep_kernel_h<T, false, true, false>(tw, h, v);
+}
+// the kernels use up to 160 KB of dynamic LDS: allowed once per kernel
+static int ensure_lds_attr(const void *k) {
+    static const void *done[128];
+    static int ndone = 0;
+    for (int i = 0; i < ndone; ++i)
+        if (done[i] == k) return MPMC_OK;
+    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess) return MPMC_EHIP;
+    if (ndone < 128) done[ndone++] = k;
+    return MPMC_OK;
+}
+
 template <typename T>
-int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, const SweepPlan &plan, int n, const double *troots,
-                   const void *x, bool x_is_noise, const void *bvec, uint64_t key, uint64_t first, const uint64_t *off,
-                   double2 *part, double2 *bhy, void *w0, void *w1, void *stream) {
+static SweepArgs<T> sweep_args(const mpmc_lattice &lat, const SweepPlan &plan, const double *troots) {
     SweepArgs<T> a{};
     for (int d = 0; d < 4; ++d) a.L[d] = lat.dims[d];
     a.P = lat.dims[0] * lat.dims[1] * lat.dims[2];
@@ -763,51 +815,28 @@ int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, const SweepPlan &plan
     a.two_rows = lat.link_rows == 2;
     a.troots = (const double2 *)troots;
     a.kappa = lat.kappa;
+    for (int d = 0; d < 3; ++d) a.B[d] = plan.B[d];
+    a.Pb = plan.Pb;
+    a.Hb = plan.Hb;
+    a.nbp = plan.nbp;
+    return a;
+}
+
+template <typename T>
+int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, const SweepPlan &plan, int n, const double *troots,
+                   const void *x, bool x_is_noise, const void *bvec, uint64_t key, uint64_t first, const uint64_t *off,
+                   double2 *part, double2 *bhy, void *w0, void *w1, void *yacc, void *stream) {
+    SweepArgs<T> a = sweep_args<T>(lat, plan, troots);
     a.key = key;
     a.first = first;
     a.off = off;
     a.bvec = (const cplx_t<T> *)bvec;
     a.rb_b = sh.rb;
     a.part = part;
-    for (int d = 0; d < 3; ++d) a.B[d] = plan.B[d];
-    a.Pb = plan.Pb;
-    a.Hb = plan.Hb;
-    a.nbp = plan.nbp;
-    // kernels of this precision: [halo][link rows 3 | 2][dot vector noise | field]
-    // [(noise input, first), (field, first), (field, later)]; blocks with a halo are FP32 only
-#define MPMC_SWEEP_ROW(H, TW, BF)                                                                   \
-    {(const void *)k_sweep<T, true, true, true, BF, TW, H>, (const void *)k_sweep<T, false, true, true, BF, TW, H>, \
-     (const void *)k_sweep<T, false, true, false, BF, TW, H>}
-    const void *kern[2][2][2][3] = {
-        {{MPMC_SWEEP_ROW(false, false, false), MPMC_SWEEP_ROW(false, false, true)},
-         {MPMC_SWEEP_ROW(false, true, false), MPMC_SWEEP_ROW(false, true, true)}},
-        {{{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}},
-         {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}}}};
-    if constexpr (sizeof(T) == 4) {
-        const void *kh[2][2][3] = {{MPMC_SWEEP_ROW(true, false, false), MPMC_SWEEP_ROW(true, false, true)},
-                                   {MPMC_SWEEP_ROW(true, true, false), MPMC_SWEEP_ROW(true, true, true)}};
-        for (int tw = 0; tw < 2; ++tw)
-            for (int bf = 0; bf < 2; ++bf)
-                for (int v = 0; v < 3; ++v) kern[1][tw][bf][v] = kh[tw][bf][v];
-    }
-#undef MPMC_SWEEP_ROW
-    static bool attr_set[2] = {false, false};
-    const int pi = sizeof(T) == 8 ? 0 : 1;
-    if (!attr_set[pi]) {
-        for (int h = 0; h < 2; ++h)
-            for (int tw = 0; tw < 2; ++tw)
-                for (int bf = 0; bf < 2; ++bf)
-                    for (int v = 0; v < 3; ++v)
-                        if (kern[h][tw][bf][v] &&
-                            hipFuncSetAttribute(kern[h][tw][bf][v], hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                160 * 1024) != hipSuccess)
-                            return MPMC_EHIP;
-        attr_set[pi] = true;
-    }
-    const int h = plan.halo ? 1 : 0;
-    const int bf = bvec != nullptr ? 1 : 0;
-    const int tw = lat.link_rows == 2 ? 1 : 0;
-    if (!kern[h][tw][bf][0]) return MPMC_EUNSUPPORTED;
+    a.y = (cplx_t<T> *)yacc;
+    const bool h = plan.halo, tw = lat.link_rows == 2, bf = bvec != nullptr, dot = bhy != nullptr;
+    const bool y = yacc != nullptr;
+    if (!dot && !y) return MPMC_EINVAL;
     const int d = n - 1;
     const dim3 grid((unsigned)(sh.nrhs * plan.nbp)), block((unsigned)plan.Pb);
     for (int j = 0; j < d; ++j) {
@@ -818,10 +847,14 @@ int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, const SweepPlan &plan
         a.out = (cplx_t<T> *)(j % 2 == 0 ? w0 : w1);
         a.dot_first = first_step;
         a.bhy = (j == d - 1 && !plan.halo) ? bhy : nullptr;
+        a.y_first = first_step;
+        a.y_last = (j == d - 1);
         const int v = first_step ? (x_is_noise ? 0 : 1) : 2;
+        const void *k = sweep_kernel<T>(y, dot, bf, tw, h, v);
+        if (!k) return MPMC_EUNSUPPORTED;
+        if (ensure_lds_attr(k) != MPMC_OK) return MPMC_EHIP;
         void *args[] = {&a};
-        if (hipLaunchKernel(kern[h][tw][bf][v], grid, block, args, plan.lds, (hipStream_t)stream) != hipSuccess)
-            return MPMC_EHIP;
+        if (hipLaunchKernel(k, grid, block, args, plan.lds, (hipStream_t)stream) != hipSuccess) return MPMC_EHIP;
         if (hipGetLastError() != hipSuccess) return MPMC_EHIP;
     }
     if (plan.halo && bhy) {
@@ -837,39 +870,10 @@ int sweep_chain_t(const mpmc_lattice &lat, mpmc_shape sh, const SweepPlan &plan,
                   const void *in, int rb_in, void *w0, void *w1, const void **out, void *stream) {
     *out = in;
     if (count <= 0) return MPMC_OK;
-    SweepArgs<T> a{};
-    for (int d = 0; d < 4; ++d) a.L[d] = lat.dims[d];
-    a.P = lat.dims[0] * lat.dims[1] * lat.dims[2];
-    a.V = a.P * lat.dims[3];
-    a.apbc = lat.antiperiodic_t;
-    a.gauge = (const cplx_t<T> *)lat.gauge;
-    a.two_rows = lat.link_rows == 2;
-    a.troots = (const double2 *)troots;
-    a.kappa = lat.kappa;
-    for (int d = 0; d < 3; ++d) a.B[d] = plan.B[d];
-    a.Pb = plan.Pb;
-    a.Hb = plan.Hb;
-    a.nbp = plan.nbp;
-    // [halo][link rows 3 | 2]; blocks with a halo are FP32 only
-    const void *kern[2][2] = {{(const void *)k_sweep<T, false, false, false, false, false, false>,
-                               (const void *)k_sweep<T, false, false, false, false, true, false>},
-                              {nullptr, nullptr}};
-    if constexpr (sizeof(T) == 4) {
-        kern[1][0] = (const void *)k_sweep<T, false, false, false, false, false, true>;
-        kern[1][1] = (const void *)k_sweep<T, false, false, false, false, true, true>;
-    }
-    static bool attr_set[2] = {false, false};
-    const int pi = sizeof(T) == 8 ? 0 : 1;
-    if (!attr_set[pi]) {
-        for (int h = 0; h < 2; ++h)
-            for (int tw = 0; tw < 2; ++tw)
-                if (kern[h][tw] && hipFuncSetAttribute(kern[h][tw], hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                       160 * 1024) != hipSuccess)
-                    return MPMC_EHIP;
-        attr_set[pi] = true;
-    }
-    const void *k = kern[plan.halo ? 1 : 0][lat.link_rows == 2 ? 1 : 0];
+    SweepArgs<T> a = sweep_args<T>(lat, plan, troots);
+    const void *k = sweep_kernel<T>(false, false, false, lat.link_rows == 2, plan.halo, 2);
     if (!k) return MPMC_EUNSUPPORTED;
+    if (ensure_lds_attr(k) != MPMC_OK) return MPMC_EHIP;
     const dim3 grid((unsigned)(sh.nrhs * plan.nbp)), block((unsigned)plan.Pb);
     const void *cur = in;
     for (int j = 0; j < count; ++j) {
@@ -894,9 +898,9 @@ template int sweep_chain_t<float>(const mpmc_lattice &, mpmc_shape, const SweepP
 
 template int sweep_newton_t<double>(const mpmc_lattice &, mpmc_shape, const SweepPlan &, int, const double *,
                                     const void *, bool, const void *, uint64_t, uint64_t, const uint64_t *, double2 *,
-                                    double2 *, void *, void *, void *);
+                                    double2 *, void *, void *, void *, void *);
 template int sweep_newton_t<float>(const mpmc_lattice &, mpmc_shape, const SweepPlan &, int, const double *,
                                    const void *, bool, const void *, uint64_t, uint64_t, const uint64_t *, double2 *,
-                                   double2 *, void *, void *, void *);
+                                   double2 *, void *, void *, void *, void *);
 
 }  // namespace mpmc

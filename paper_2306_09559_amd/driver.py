@@ -192,6 +192,7 @@ SETUP_DEFAULTS = {
     "rtolpoly1": None,     # stop the outer PP-GMRES of a double polynomial here (None: the configured n_out)
     "gmres_m": 30,         # restart length of the top-level PP-GMRES
     "solve_tol": 1e-6,     # rtolle
+    "solve_rb": 1,         # block width of a top level's fields (1: its polynomials run on the t-sweep)
 }
 
 
@@ -213,7 +214,7 @@ def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optio
     cfg.extra, else SETUP_DEFAULTS."""
     t0 = time.perf_counter()
     given = dict(pin_degree=pin_degree, arnoldi_m=arnoldi_m, rtolev=rtolev, nev=nev, rtolpoly1=rtolpoly1,
-                 gmres_m=gmres_m, solve_tol=solve_tol)
+                 gmres_m=gmres_m, solve_tol=solve_tol, solve_rb=None)
     prm = {k: (given[k] if given[k] is not None else cfg.extra.get(k, d)) for k, d in SETUP_DEFAULTS.items()}
     pin_degree, arnoldi_m, rtolev, nev = prm["pin_degree"], prm["arnoldi_m"], prm["rtolev"], prm["nev"]
     rtolpoly1, gmres_m, solve_tol = prm["rtolpoly1"], prm["gmres_m"], prm["solve_tol"]
@@ -288,27 +289,30 @@ def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optio
             return p[0] * comps[p].n_out - 1
         return poly_mvps(p)
     for i, lv in enumerate(cfg.levels):
-        N = _batch_size(lv.samples, rb, max_batch)
         if lv.hi == SOLVE:
+            srb = int(prm["solve_rb"])
+            N = _batch_size(lv.samples, srb, max_batch)
             # Tr(A^{-1} - Q) with Q the deflated p_1 (Sec. 4.3): the deflation is in Q,
             # so the samples carry no Monte Carlo deflation term
             lo = _device_poly(roots, comps, lv.lo)
             kind_lo = L.OP_DEFLATED_POLY if (lv.deflated and defl is not None) else L.OP_POLY
-            x64 = L.empty_field(V, N, rb, L.F64)
-            xl = x64 if prec == L.F64 else L.empty_field(V, N, rb, prec)
+            x64 = L.empty_field(V, N, srb, L.F64)
+            xl = x64 if prec == L.F64 else L.empty_field(V, N, srb, prec)
             dlev = L.DeviceLevel(L.OP_SOLVE, None, kind_lo, lo, defl.device if defl is not None else None,
                                  False, None, xl)
             n_in = lv.lo[0] if isinstance(lv.lo, tuple) else (pin_degree or lv.lo) + 1
             l64 = dl64 if dl64 is not None else (dl if prec == L.F64 else lattice(L.F64))
             dl64 = l64
             solver = MixedPPGMRES(l64, dl, roots.device[n_in - 1], defl.device if defl is not None else None,
-                                  gmres_m, N, rb)
-            ws = L.workspace(L.level_workspace_size(dl, dlev, N, rb))
+                                  gmres_m, N, srb)
+            ws = L.workspace(L.level_workspace_size(dl, dlev, N, srb))
             st = LevelState(i, dlev, mvps(lv.lo), None, torch.zeros(8, dtype=torch.float64, device="cuda"),
                             torch.empty((N, 6), dtype=torch.float64, device="cuda"), ws, solver=solver,
-                            b64=L.empty_field(V, N, rb, L.F64), x64=x64, xl=xl, solve_tol=solve_tol, batch=N)
+                            b64=L.empty_field(V, N, srb, L.F64), x64=x64, xl=xl, solve_tol=solve_tol, batch=N,
+                            rb=srb)
             run.levels.append(st)
             continue
+        N = _batch_size(lv.samples, rb, max_batch)
         hi = _device_poly(roots, comps, lv.hi)
         lo = _device_poly(roots, comps, lv.lo) if lv.lo is not None else None
         c = None

@@ -583,3 +583,50 @@ def test_scalar_composite_sweep(dims, prec, nrhs, rb, field_in, n_in, n_out):
         assert err < tol, opt
     if prec == 0:
         assert np.max(np.abs(out[1] - out[0]) / np.abs(out[0])) < 1e-13
+
+
+@pytest.mark.parametrize("dims,prec,nrhs,field_in,dot", [
+    ((8, 8, 8, 8), 0, 256, False, True),      # whole plane, noise input, y and b^H y
+    ((8, 8, 8, 4), 1, 256, True, False),      # FP32, field input, y only
+    ((16, 8, 8, 2), 1, 128, False, False),    # FP32 blocks with a halo
+])
+def test_vector_mode_sweep(dims, prec, nrhs, field_in, dot):
+    """Vector mode y = p(A) x at block width 1 on the t-sweep (y accumulated
+    in the same launches) against the streaming kernel and, for sampled
+    vectors, the oracle."""
+    L = lib()
+    dl, ol = device_lattice(dims, 0.14, 0.4, 37, True, prec=prec)
+    plan = L.sweep_plan(dl, nrhs, 1)
+    assert plan["ok"]
+    deg = 6
+    t = krylov.gmres_polys(ol.apply, synth.gaussian_start(ol.n, 2), [deg]).inv_roots[deg]
+    poly = L.DevicePoly(dev_c128(t))
+    nz = L.Noise(17, 5, 1, 3)
+    if field_in:
+        X = synth.random_fields(nrhs, dl.V, 14).reshape(nrhs, -1)
+        xin = pack(dims, X, 1, prec)
+    else:
+        X, xin = None, None
+    ws = L.workspace(L.poly_workspace_size(dl, poly, nrhs, 1))
+    yt, ys, bs = {}, {}, {}
+    for opt in (1, 0):
+        L.set_option(L.OPT_PLANE_SWEEP, opt)
+        yt[opt] = L.empty_field(dl.V, nrhs, 1, prec)
+        bhy = torch.empty(nrhs, dtype=torch.complex128, device="cuda") if dot else None
+        L.poly_apply(dl, poly, nrhs, 1, xin, None if field_in else nz, yt[opt], bhy, ws)
+        torch.cuda.synchronize()
+        ys[opt] = yt[opt].cpu().numpy()
+        bs[opt] = bhy.cpu().numpy() if dot else None
+    L.set_option(L.OPT_PLANE_SWEEP, 1)
+    scale = np.max(np.abs(ys[0]))
+    tol_same = 1e-13 if prec == 0 else 8 * deg * 50 * U32
+    assert np.max(np.abs(ys[1] - ys[0])) <= tol_same * scale
+    Y = unpack(dims, yt[1], prec)
+    for r in (0, nrhs // 2 + 1, nrhs - 1):
+        x = X[r] if field_in else oracle.z4(17, 5, 1, 3 + r, 1, dl.V)[0]
+        want, _ = ol.poly_apply(t, x)
+        err = rel(Y[r], want)
+        print(dims, "vector", r, f"rel err {err:.2e}")
+        assert err < (1e-12 if prec == 0 else 8 * deg * 50 * U32)
+        if dot:
+            assert abs(bs[1][r] - np.vdot(x, want)) <= 1e-12 * abs(np.vdot(x, want))
