@@ -109,6 +109,15 @@ typedef struct {
     const uint64_t *sample_offset;  /* device counter added to first_sample when the kernels run, or
                                        NULL.  Lets a captured HIP graph draw new samples on every
                                        replay: advance it with mpmc_counter_add inside the graph. */
+    const int32_t *probe_colour;    /* NULL: Z4 noise (seed, lattice, level).  Otherwise probe
+                                       vectors of a distance colouring (Sec. 3.1, Sec. 5 step 3d):
+                                       device int32[V], the colour of every site; vector r is
+                                       b_{g/12, g%12}, g = first_sample + r (+ *sample_offset), with
+                                       b_{c,k} = 1 at unknown k of every site of colour c, 0
+                                       elsewhere.  Accepted only by mpmc_poly_apply in scalar mode
+                                       for a single polynomial with x = NULL on a lattice and batch
+                                       that take the t-sweep (mpmc_sweep_plan); every other use
+                                       returns MPMC_EUNSUPPORTED.  Same vectors as mpmc_probe_fill. */
 } mpmc_noise;
 
 typedef struct {

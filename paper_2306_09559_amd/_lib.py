@@ -45,7 +45,7 @@ class mpmc_shape(ctypes.Structure):
 
 class mpmc_noise(ctypes.Structure):
     _fields_ = [("seed", c_u64), ("lattice", c_u64), ("level", c_u64), ("first_sample", c_u64),
-                ("sample_offset", c_vp)]
+                ("sample_offset", c_vp), ("probe_colour", c_vp)]
 
 
 class mpmc_poly(ctypes.Structure):
@@ -154,9 +154,11 @@ class Noise:
     level: int
     first_sample: int = 0
     sample_offset: Optional[torch.Tensor] = None   # device int64 (1,) counter added to first_sample
+    probe_colour: Optional[torch.Tensor] = None    # device int32 (V,): probe vectors instead of Z4 noise
 
     def c(self) -> mpmc_noise:
-        return mpmc_noise(self.seed, self.lattice, self.level, self.first_sample, _ptr(self.sample_offset))
+        return mpmc_noise(self.seed, self.lattice, self.level, self.first_sample, _ptr(self.sample_offset),
+                          _ptr(self.probe_colour))
 
 
 @dataclass

@@ -169,6 +169,7 @@ int mpmc_unpack_fields(const int32_t dims[4], int32_t prec, mpmc_shape shape, co
 int mpmc_z4_fill(const int32_t dims[4], int32_t prec, mpmc_shape shape, const mpmc_noise *noise, void *field,
                  void *stream) {
     if (!valid_dims(dims) || !valid_shape(shape) || !noise || !field) return MPMC_EINVAL;
+    if (noise->probe_colour) return MPMC_EUNSUPPORTED;          // mpmc_probe_fill writes probe vectors
     if (!valid_prec(prec)) return MPMC_EUNSUPPORTED;
     return z4_fill_impl(dims, prec, shape, *noise, field, stream);
 }
@@ -257,6 +258,8 @@ int mpmc_poly_apply(const mpmc_lattice *lat, const mpmc_poly *poly, mpmc_shape s
     if (!y && !bhy) return MPMC_EINVAL;
     if (!x && !noise) return MPMC_EINVAL;
     if (x && x == y) return MPMC_EINVAL;
+    if (noise && noise->probe_colour && (x || y || !bhy || poly->n_out != 0 || poly->n_in < 2))
+        return MPMC_EUNSUPPORTED;                                 // probes: the scalar t-sweep only
     MPMC_TRY(check_ws(ws, ws_bytes, poly_ws_bytes(lat->dims, lat->prec, *poly, shape)));
     const PolyWs p = carve_poly_ws(lat->dims, lat->prec, *poly, shape, ws);
     return lat->prec == MPMC_F64 ? poly_apply_t<double>(*lat, *poly, shape, x, noise, y, bhy, p, stream)
@@ -276,6 +279,7 @@ int mpmc_deflate_project(const mpmc_lattice *lat, const mpmc_defl *defl, int32_t
     MPMC_TRY(check_defl(defl, mode == MPMC_DEFL_PROJECT));
     if (!valid_shape(shape) || !plane_fits(lat->dims, lat->prec, shape)) return MPMC_EINVAL;
     if (mode != MPMC_DEFL_RECON && !b && !noise) return MPMC_EINVAL;
+    if (noise && noise->probe_colour) return MPMC_EUNSUPPORTED;
     if (mode == MPMC_DEFL_COEFF && !zeta && !omega) return MPMC_EINVAL;
     if (mode == MPMC_DEFL_RECON && (!d || !X)) return MPMC_EINVAL;
     if (mode == MPMC_DEFL_PROJECT && (!d || !X || (b && b == X))) return MPMC_EINVAL;
@@ -295,6 +299,7 @@ int mpmc_mlmc_level_estimate(const mpmc_lattice *lat, const mpmc_level *level, m
                              void *stream) {
     MPMC_TRY(check_lattice(lat));
     if (!level || !noise || !samples || !acc || !valid_shape(shape)) return MPMC_EINVAL;
+    if (noise->probe_colour) return MPMC_EUNSUPPORTED;
     if (!plane_fits(lat->dims, lat->prec, shape)) return MPMC_EINVAL;
     const int kh = level->kind_hi, kl = level->kind_lo;
     if (kh != MPMC_OP_POLY && kh != MPMC_OP_DEFLATED_POLY && kh != MPMC_OP_SOLVE) return MPMC_EUNSUPPORTED;

@@ -156,6 +156,44 @@ template <typename T> __device__ __forceinline__ cplx_t<T> z4_value(unsigned q) 
     return mk<T>(re, im);
 }
 
+// ---------------------------------------------------------------- partial sums
+// out[m] = sum over b < n of term(b)[m], in a fixed order, by one 64-lane
+// workgroup (launch with blockDim.x = kSumLanes): lane j adds the terms
+// j, j + 64, ... in turn, then a fixed tree combines the lanes.  Every lane
+// returns the total.  The order depends only on n, never on timing.
+constexpr int kSumLanes = 64;
+template <int M, typename F> __device__ __forceinline__ void sum_fixed(int n, F term, double2 (&out)[M]) {
+    __shared__ double2 red[M][kSumLanes];
+    const int j = (int)threadIdx.x;
+    double2 acc[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) acc[m] = make_double2(0.0, 0.0);
+    for (int b = j; b < n; b += kSumLanes) {
+        double2 v[M];
+        term(b, v);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            acc[m].x += v[m].x;
+            acc[m].y += v[m].y;
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) red[m][j] = acc[m];
+    __syncthreads();
+    for (int h = kSumLanes / 2; h > 0; h >>= 1) {
+        if (j < h) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                red[m][j].x += red[m][j + h].x;
+                red[m][j].y += red[m][j + h].y;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) out[m] = red[m][0];
+}
+
 // ---------------------------------------------------------------- launch shape
 constexpr int kBlock = 256;   // threads per workgroup of the field kernels
 constexpr int kXcds = 8;      // MI355X: 8 XCDs, workgroups dispatched round-robin

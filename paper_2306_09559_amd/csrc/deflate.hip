@@ -130,25 +130,26 @@ __global__ void __launch_bounds__(kWaves * 64) k_coeff(CoeffArgs<T> a) {
 }
 
 // zeta = up + dn, omega_i = conj(scale_i) (up - dn)[pair_i]; fixed split order
-__global__ void k_coeff_finish(const double2 *part, int nsplit, int kpad, int ldr, int k, int nrhs,
-                               const int32_t *pair, const double2 *scale, double2 *zeta, double2 *omega) {
-    const int e = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (e >= k * nrhs) return;
+// one 64-lane workgroup per (eigenvector, vector): the four split sums in a fixed order (sum_fixed)
+__global__ void __launch_bounds__(kSumLanes) k_coeff_finish(const double2 *part, int nsplit, int kpad, int ldr, int k,
+                                                            int nrhs, const int32_t *pair, const double2 *scale,
+                                                            double2 *zeta, double2 *omega) {
+    const int e = (int)blockIdx.x;
     const int i = e / nrhs, r = e % nrhs;
     const int pr = pair[i];
     const bool pair_ok = pr >= 0 && pr < k;     // a bad pair entry yields NaN, never a stray read
     const int pi = pair_ok ? pr : i;
-    double2 u = {0.0, 0.0}, d = {0.0, 0.0}, up = {0.0, 0.0}, dp = {0.0, 0.0};
-    for (int p = 0; p < nsplit; ++p) {
+    double2 s4[4];
+    sum_fixed<4>(nsplit, [&](int p, double2 (&v)[4]) {
         const double2 *b0 = part + ((size_t)p * 2) * (size_t)kpad * (size_t)ldr;
         const double2 *b1 = b0 + (size_t)kpad * (size_t)ldr;
-        const double2 a0 = b0[(size_t)i * ldr + r], a1 = b1[(size_t)i * ldr + r];
-        const double2 c0 = b0[(size_t)pi * ldr + r], c1 = b1[(size_t)pi * ldr + r];
-        u.x += a0.x; u.y += a0.y;
-        d.x += a1.x; d.y += a1.y;
-        up.x += c0.x; up.y += c0.y;
-        dp.x += c1.x; dp.y += c1.y;
-    }
+        v[0] = b0[(size_t)i * ldr + r];
+        v[1] = b1[(size_t)i * ldr + r];
+        v[2] = b0[(size_t)pi * ldr + r];
+        v[3] = b1[(size_t)pi * ldr + r];
+    }, s4);
+    if (threadIdx.x != 0) return;
+    const double2 u = s4[0], d = s4[1], up = s4[2], dp = s4[3];
     if (zeta) {
         double2 z;
         z.x = u.x + d.x;
@@ -279,7 +280,7 @@ int coeff_t(const mpmc_lattice &lat, const mpmc_defl &df, mpmc_shape sh, const v
     hipLaunchKernelGGL(k_coeff<T>, dim3(p.nti * p.ntr, p.nsplit), dim3(kWaves * 64), 0, (hipStream_t)stream, a);
     if (hipGetLastError() != hipSuccess) return MPMC_EHIP;
     const int tot = df.k * sh.nrhs;
-    hipLaunchKernelGGL(k_coeff_finish, dim3((tot + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+    hipLaunchKernelGGL(k_coeff_finish, dim3((unsigned)tot), dim3(kSumLanes), 0, (hipStream_t)stream,
                        (const double2 *)ws, p.nsplit, df.kpad, p.ldr, df.k, sh.nrhs, df.pair,
                        (const double2 *)df.scale, (double2 *)zeta, (double2 *)omega);
     return hipGetLastError() == hipSuccess ? MPMC_OK : MPMC_EHIP;

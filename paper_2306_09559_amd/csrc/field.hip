@@ -60,18 +60,14 @@ __global__ void __launch_bounds__(kBlock) k_dot_part(const cplx_t<T> *x, const c
     if (ls == 0) part[(size_t)L * rb + jr] = red[lane];
 }
 
-__global__ void k_dot_finish(const double2 *part, int nblk, int rb, int nrhs, double2 *out) {
-    const int r = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (r >= nrhs) return;
+// one 64-lane workgroup per vector (sum_fixed)
+__global__ void __launch_bounds__(kSumLanes) k_dot_finish(const double2 *part, int nblk, int rb, double2 *out) {
+    const int r = (int)blockIdx.x;
     const int nbk = r / rb, jr = r % rb;
-    double re = 0.0, im = 0.0;
-    for (int b = 0; b < nblk; ++b) {
-        const double2 v = part[((size_t)nbk * nblk + b) * rb + jr];
-        re += v.x;
-        im += v.y;
-    }
-    out[r].x = re;
-    out[r].y = im;
+    const double2 *p = part + (size_t)nbk * (size_t)nblk * (size_t)rb + (size_t)jr;
+    double2 tot[1];
+    sum_fixed<1>(nblk, [&](int b, double2 (&v)[1]) { v[0] = p[(size_t)b * (size_t)rb]; }, tot);
+    if (threadIdx.x == 0) out[r] = tot[0];
 }
 
 template <typename T>
@@ -176,18 +172,16 @@ __global__ void __launch_bounds__(kBlock) k_block_dot(const cplx_t<T> *basis, si
     }
 }
 
-__global__ void k_block_dot_finish(const double2 *part, int k, int rb, int nrhs, int SB, double2 *out) {
-    const int e = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (e >= k * nrhs) return;
+// one 64-lane workgroup per (basis vector, vector) (sum_fixed)
+__global__ void __launch_bounds__(kSumLanes) k_block_dot_finish(const double2 *part, int k, int rb, int nrhs, int SB,
+                                                                double2 *out) {
+    const int e = (int)blockIdx.x;
     const int i = e / nrhs, r = e % nrhs;
     const int nbk = r / rb, jr = r % rb;
-    double re = 0.0, im = 0.0;
-    for (int sb = 0; sb < SB; ++sb) {
-        const double2 v = part[(((size_t)nbk * SB + sb) * k + i) * rb + jr];
-        re += v.x;
-        im += v.y;
-    }
-    out[e] = make_double2(re, im);
+    double2 tot[1];
+    sum_fixed<1>(SB, [&](int sb, double2 (&v)[1]) { v[0] = part[(((size_t)nbk * SB + sb) * k + i) * rb + jr]; },
+                 tot);
+    if (threadIdx.x == 0) out[e] = tot[0];
 }
 
 // y = [y +] sum_i coeff[i][r] (v_i)_r, in FP64, rounded once
@@ -260,8 +254,8 @@ int field_dot_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, const voi
         hipLaunchKernelGGL(k_dot_part<float>, dim3(t.groups()), dim3(kBlock), 0, (hipStream_t)stream,
                            (const float2 *)x, (const float2 *)y, V, sh.rb, t.spw, t.nblk, (double2 *)ws);
     if (hipGetLastError() != hipSuccess) return MPMC_EHIP;
-    hipLaunchKernelGGL(k_dot_finish, dim3((sh.nrhs + 255) / 256), dim3(256), 0, (hipStream_t)stream,
-                       (const double2 *)ws, t.nblk, sh.rb, sh.nrhs, (double2 *)out);
+    hipLaunchKernelGGL(k_dot_finish, dim3(sh.nrhs), dim3(kSumLanes), 0, (hipStream_t)stream, (const double2 *)ws,
+                       t.nblk, sh.rb, (double2 *)out);
     return st();
 }
 
@@ -307,8 +301,8 @@ int field_block_dot_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, int
         hipLaunchKernelGGL(k_block_dot<float>, grid, dim3(kBlock), 0, s, (const float2 *)basis, F, k,
                            (const float2 *)x, V, sh.rb, SB, (double2 *)ws);
     if (hipGetLastError() != hipSuccess) return MPMC_EHIP;
-    hipLaunchKernelGGL(k_block_dot_finish, dim3((k * sh.nrhs + 255) / 256), dim3(256), 0, s, (const double2 *)ws, k,
-                       sh.rb, sh.nrhs, SB, (double2 *)out);
+    hipLaunchKernelGGL(k_block_dot_finish, dim3((unsigned)(k * sh.nrhs)), dim3(kSumLanes), 0, s,
+                       (const double2 *)ws, k, sh.rb, sh.nrhs, SB, (double2 *)out);
     return st();
 }
 

@@ -442,22 +442,14 @@ __global__ void __launch_bounds__(kBlock) k_scale_dot(HopArgs<T> a) {
     }
 }
 
-// bhy[r] = sum over site blocks of part, fixed order
-__global__ void k_reduce_part(const double2 *part, int nblk, int rb, int nrhs, double2 *bhy) {
-    const int r = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (r >= nrhs) return;
+// bhy[r] = sum over site blocks of part, fixed order: one 64-lane workgroup per vector
+__global__ void __launch_bounds__(kSumLanes) k_reduce_part(const double2 *part, int nblk, int rb, double2 *bhy) {
+    const int r = (int)blockIdx.x;
     const int nbk = r / rb, jr = r % rb;
-    double re = 0.0, im = 0.0;
     const double2 *p = part + (size_t)nbk * (size_t)nblk * (size_t)rb + (size_t)jr;
-    for (int b = 0; b < nblk; ++b) {
-        const double2 v = p[(size_t)b * (size_t)rb];
-        re += v.x;
-        im += v.y;
-    }
-    double2 o;
-    o.x = re;
-    o.y = im;
-    bhy[r] = o;
+    double2 tot[1];
+    sum_fixed<1>(nblk, [&](int b, double2 (&v)[1]) { v[0] = p[(size_t)b * (size_t)rb]; }, tot);
+    if (threadIdx.x == 0) bhy[r] = tot[0];
 }
 
 // ------------------------------------------------------------------ host side
@@ -621,13 +613,15 @@ int poly_apply_t(const mpmc_lattice &lat, const mpmc_poly &poly, mpmc_shape sh, 
     double2 *part = bhy ? (double2 *)ws.part : nullptr;
     const FieldTiling t = make_tiling(lat.dims[0] * lat.dims[1] * lat.dims[2] * lat.dims[3], sh.nrhs, sh.rb);
     int st;
-    if (poly.n_out == 0 && y == nullptr && bhy != nullptr && poly.n_in >= 2 && g_opt_sweep) {
+    const int32_t *colour = noise ? noise->probe_colour : nullptr;
+    if (poly.n_out == 0 && y == nullptr && bhy != nullptr && poly.n_in >= 2 && (g_opt_sweep || colour)) {
         // scalar mode: t-sweep over xyz-blocks when the lattice admits one
         const SweepPlan plan = sweep_plan(lat, sh);
         if (plan.ok)
             return sweep_newton_t<T>(lat, sh, plan, poly.n_in, poly.inv_roots_in, x, x_noise, bvec, key, first, off,
-                                     part, (double2 *)bhy, ws.f[0], ws.f[1], nullptr, stream);
+                                     part, (double2 *)bhy, ws.f[0], ws.f[1], nullptr, stream, colour);
     }
+    if (colour) return MPMC_EUNSUPPORTED;                          // probe vectors: the t-sweep only
     if (poly.n_out == 0 && poly.n_in >= 2 && y != nullptr && sh.rb == 1 && (noise != nullptr || bhy == nullptr) &&
         g_opt_sweep) {
         // vector mode on the t-sweep: y (block width 1, like the sweep's own
@@ -701,9 +695,8 @@ int poly_apply_t(const mpmc_lattice &lat, const mpmc_poly &poly, mpmc_shape sh, 
         if (st != MPMC_OK) return st;
     }
     if (bhy) {
-        const int thr = 256;
-        hipLaunchKernelGGL(k_reduce_part, dim3((sh.nrhs + thr - 1) / thr), dim3(thr), 0, (hipStream_t)stream,
-                           (const double2 *)ws.part, t.nblk, sh.rb, sh.nrhs, (double2 *)bhy);
+        hipLaunchKernelGGL(k_reduce_part, dim3(sh.nrhs), dim3(kSumLanes), 0, (hipStream_t)stream,
+                           (const double2 *)ws.part, t.nblk, sh.rb, (double2 *)bhy);
         if (hipGetLastError() != hipSuccess) return MPMC_EHIP;
     }
     return MPMC_OK;

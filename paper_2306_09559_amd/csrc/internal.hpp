@@ -44,7 +44,8 @@ SweepPlan sweep_plan(const mpmc_lattice &lat, mpmc_shape sh);
 template <typename T>
 int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, const SweepPlan &plan, int n, const double *troots,
                    const void *x, bool x_is_noise, const void *bvec, uint64_t key, uint64_t first, const uint64_t *off,
-                   double2 *part, double2 *bhy, void *w0, void *w1, void *yacc, void *stream);
+                   double2 *part, double2 *bhy, void *w0, void *w1, void *yacc, void *stream,
+                   const int32_t *colour = nullptr);
 
 // count plain Newton steps w <- w - t_j A w (j = 0 .. count-1, no dot) of
 // nrhs vectors from `in` (block width rb_in); outputs alternate w0, w1 at

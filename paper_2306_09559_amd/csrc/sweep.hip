@@ -35,6 +35,7 @@ template <typename T> struct SweepArgs {
     double kappa;
     uint64_t key, first;       // noise (input when IN_Z4; dot vector when bvec == nullptr)
     const uint64_t *off;       // device sample counter added to first, or nullptr
+    const int32_t *colour;     // probe vectors of this colouring instead of Z4 noise, or nullptr
     const cplx_t<T> *bvec;     // dot vector field (layout rb_b), or nullptr
     int rb_b;
     double2 *part;             // N partial sums, one per vector
@@ -84,12 +85,32 @@ template <typename T> __device__ __forceinline__ Plane<T> plane_of(const void *f
     return p;
 }
 
-template <typename T>
-__device__ __forceinline__ void load_plane_site(const Plane<T> &in, bool z4, uint64_t S, int s, cplx_t<T> (&p)[12]) {
-    if (z4) {
-        const uint32_t codes = z4_site_codes(S, (unsigned)s);
+// the noise of one vector: Z4 from its sample state S, or, with a colouring,
+// the probe vector b_{cg, kk} (1 at unknown kk of the sites of colour cg)
+struct NoiseSrc {
+    uint64_t S;
+    const int32_t *colour;
+    long long cg;
+    int kk;
+};
+
+template <typename T> __device__ __forceinline__ void noise_site(const NoiseSrc &ns, int s, cplx_t<T> (&p)[12]) {
+    if (ns.colour) {
+        const bool on = (long long)ns.colour[s] == ns.cg;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) p[c] = mk<T>((on && c == ns.kk) ? T(1) : T(0), T(0));
+    } else {
+        const uint32_t codes = z4_site_codes(ns.S, (unsigned)s);
 #pragma unroll
         for (int c = 0; c < 12; ++c) p[c] = z4_value<T>((codes >> (2 * c)) & 3u);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_plane_site(const Plane<T> &in, bool z4, const NoiseSrc &ns, int s,
+                                                cplx_t<T> (&p)[12]) {
+    if (z4) {
+        noise_site<T>(ns, s, p);
     } else {
 #pragma unroll
         for (int c = 0; c < 12; ++c) p[c] = in.ld(c, s);
@@ -411,7 +432,8 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
 
     const double2 tj = a.troots[a.j];
     const double2 beta = make_double2(a.kappa * tj.x, a.kappa * tj.y);   // kappa t_j
-    const uint64_t S = sample_state(a.key, sample_base(a.first, a.off) + (uint64_t)r);
+    const uint64_t g = sample_base(a.first, a.off) + (uint64_t)r;      // global sample (or probe) index
+    const NoiseSrc S{sample_state(a.key, g), a.colour, (long long)(g / 12u), (int)(g % 12u)};
     const Plane<T> inp = plane_of<T>(a.in, r, a.V, a.rb_in);
     const Plane<T> outp = plane_of<T>(a.out, r, a.V, 1);
 
@@ -492,9 +514,7 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
         if (DOT && FIRST) {
             C b[12];
             if (!BFIELD) {
-                const uint32_t codes = z4_site_codes(S, (unsigned)s);
-#pragma unroll
-                for (int c = 0; c < 12; ++c) b[c] = z4_value<T>((codes >> (2 * c)) & 3u);
+                noise_site<T>(S, s, b);
             } else {
                 const Plane<T> bp = plane_of<T>(a.bvec, r, a.V, a.rb_b);
 #pragma unroll
@@ -607,9 +627,7 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
         if (DOT) {
             C b[12];
             if (!BFIELD) {
-                const uint32_t codes = z4_site_codes(S, (unsigned)s);
-#pragma unroll
-                for (int c = 0; c < 12; ++c) b[c] = z4_value<T>((codes >> (2 * c)) & 3u);
+                noise_site<T>(S, s, b);
             } else {
                 const Plane<T> bp = plane_of<T>(a.bvec, r, a.V, a.rb_b);
 #pragma unroll
@@ -825,8 +843,10 @@ static SweepArgs<T> sweep_args(const mpmc_lattice &lat, const SweepPlan &plan, c
 template <typename T>
 int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, const SweepPlan &plan, int n, const double *troots,
                    const void *x, bool x_is_noise, const void *bvec, uint64_t key, uint64_t first, const uint64_t *off,
-                   double2 *part, double2 *bhy, void *w0, void *w1, void *yacc, void *stream) {
+                   double2 *part, double2 *bhy, void *w0, void *w1, void *yacc, void *stream,
+                   const int32_t *colour) {
     SweepArgs<T> a = sweep_args<T>(lat, plan, troots);
+    a.colour = colour;
     a.key = key;
     a.first = first;
     a.off = off;
@@ -898,9 +918,9 @@ template int sweep_chain_t<float>(const mpmc_lattice &, mpmc_shape, const SweepP
 
 template int sweep_newton_t<double>(const mpmc_lattice &, mpmc_shape, const SweepPlan &, int, const double *,
                                     const void *, bool, const void *, uint64_t, uint64_t, const uint64_t *, double2 *,
-                                    double2 *, void *, void *, void *, void *);
+                                    double2 *, void *, void *, void *, void *, const int32_t *);
 template int sweep_newton_t<float>(const mpmc_lattice &, mpmc_shape, const SweepPlan &, int, const double *,
                                    const void *, bool, const void *, uint64_t, uint64_t, const uint64_t *, double2 *,
-                                   double2 *, void *, void *, void *, void *);
+                                   double2 *, void *, void *, void *, void *, const int32_t *);
 
 }  // namespace mpmc

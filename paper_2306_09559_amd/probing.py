@@ -15,9 +15,9 @@ reuses the greedy colouring of the m^4 torus (two distinct sites within
 distance d differ by less than m in every coordinate, so their images on the
 small torus are distinct and within distance d there too).
 
-The probe vectors are generated on the device (mpmc_probe_fill) and applied
-in scalar mode (mpmc_poly_apply with the probe batch as both the input and
-the dot vector); the host sums the FP64 results in a fixed order.
+The probe vectors are generated on the device -- inside the t-sweep from the
+colouring (mpmc_noise.probe_colour), or by mpmc_probe_fill -- and applied in
+scalar mode; the host sums the FP64 results in a fixed order.
 """
 from __future__ import annotations
 
@@ -114,23 +114,31 @@ class ProbeResult:
 
 
 def probe_trace(dl: L.DeviceLattice, poly: L.DevicePoly, colour: np.ndarray, nrhs: int = 256, rb: int = 1,
-                degree: Optional[int] = None) -> ProbeResult:
+                in_kernel: Optional[bool] = None) -> ProbeResult:
     """Tr p(A) = sum over probes of b^H p(A) b, probes in batches of nrhs.
 
-    The probe batch is laid out with block width rb = 1 (each component of a
-    vector contiguous over sites): the t-sweep reads its input and dot vector
-    site by site within one vector, which is coalesced only at rb = 1."""
+    Where the t-sweep applies, the probe vectors are generated inside it
+    from the colouring (like Z4 noise: never stored, no dot-vector reads);
+    otherwise each batch is written by mpmc_probe_fill and applied as a
+    field, laid out with block width rb = 1 (the sweep reads its input and
+    dot vector site by site within one vector, coalesced only at rb = 1).
+    in_kernel forces one of the two."""
     col = np.ascontiguousarray(colour, dtype=np.int32)
     ncol = int(col.max()) + 1
     nprobe = 12 * ncol
     nb = (nprobe + nrhs - 1) // nrhs
     dev_col = torch.from_numpy(col).cuda()
-    field = L.empty_field(dl.V, nrhs, rb, dl.prec)
     ws = L.workspace(L.poly_workspace_size(dl, poly, nrhs, rb))
+    if in_kernel is None:
+        in_kernel = poly.inv_out is None and poly.inv_in.numel() >= 2 and L.sweep_plan(dl, nrhs, rb)["ok"]
     # every batch writes its b^H p(A) b into its own slice; one copy to the host at the end
     bhy = torch.empty((nb, nrhs), dtype=torch.complex128, device="cuda")
+    field = None if in_kernel else L.empty_field(dl.V, nrhs, rb, dl.prec)
     for i in range(nb):
-        L.probe_fill(dl.dims, dl.prec, dev_col, i * nrhs, field)
-        L.poly_apply(dl, poly, nrhs, rb, field, None, None, bhy[i], ws)
+        if in_kernel:
+            L.poly_apply(dl, poly, nrhs, rb, None, L.Noise(0, 0, 0, i * nrhs, probe_colour=dev_col), None, bhy[i], ws)
+        else:
+            L.probe_fill(dl.dims, dl.prec, dev_col, i * nrhs, field)
+            L.poly_apply(dl, poly, nrhs, rb, field, None, None, bhy[i], ws)
     vals = bhy.cpu().numpy().reshape(-1)[:nprobe]      # probes past the last colour are zero vectors
     return ProbeResult(complex(np.sum(vals)), ncol, nprobe, nb)
