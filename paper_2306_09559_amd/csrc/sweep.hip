@@ -94,8 +94,9 @@ struct NoiseSrc {
     int kk;
 };
 
-template <typename T> __device__ __forceinline__ void noise_site(const NoiseSrc &ns, int s, cplx_t<T> (&p)[12]) {
-    if (ns.colour) {
+template <typename T, bool PROBE>
+__device__ __forceinline__ void noise_site(const NoiseSrc &ns, int s, cplx_t<T> (&p)[12]) {
+    if constexpr (PROBE) {
         const bool on = (long long)ns.colour[s] == ns.cg;
 #pragma unroll
         for (int c = 0; c < 12; ++c) p[c] = mk<T>((on && c == ns.kk) ? T(1) : T(0), T(0));
@@ -106,11 +107,11 @@ template <typename T> __device__ __forceinline__ void noise_site(const NoiseSrc 
     }
 }
 
-template <typename T>
+template <typename T, bool PROBE = false>
 __device__ __forceinline__ void load_plane_site(const Plane<T> &in, bool z4, const NoiseSrc &ns, int s,
                                                 cplx_t<T> (&p)[12]) {
     if (z4) {
-        noise_site<T>(ns, s, p);
+        noise_site<T, PROBE>(ns, s, p);
     } else {
 #pragma unroll
         for (int c = 0; c < 12; ++c) p[c] = in.ld(c, s);
@@ -345,7 +346,8 @@ __device__ __forceinline__ void dot_acc(const cplx_t<T> (&b)[12], const cplx_t<T
 // for one workgroup's LDS) and stages a one-site halo of the neighbouring
 // blocks next to it; without HALO the block is the whole plane and the x, y,
 // z neighbours wrap inside it.
-template <typename T, bool IN_Z4, bool DOT, bool FIRST, bool BFIELD, bool TWO, bool HALO, bool YACC = false>
+template <typename T, bool IN_Z4, bool DOT, bool FIRST, bool BFIELD, bool TWO, bool HALO, bool YACC = false,
+          bool PROBE = false>
 __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
     using C = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -433,7 +435,7 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
     const double2 tj = a.troots[a.j];
     const double2 beta = make_double2(a.kappa * tj.x, a.kappa * tj.y);   // kappa t_j
     const uint64_t g = sample_base(a.first, a.off) + (uint64_t)r;      // global sample (or probe) index
-    const NoiseSrc S{sample_state(a.key, g), a.colour, (long long)(g / 12u), (int)(g % 12u)};
+    const NoiseSrc S{PROBE ? 0ull : sample_state(a.key, g), a.colour, (long long)(g / 12u), (int)(g % 12u)};
     const Plane<T> inp = plane_of<T>(a.in, r, a.V, a.rb_in);
     const Plane<T> outp = plane_of<T>(a.out, r, a.V, 1);
 
@@ -445,7 +447,7 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
     C stash[2][3];
     {
         C p[12];
-        load_plane_site<T>(inp, IN_Z4, S, gq + (Lt - 1) * P, p);
+        load_plane_site<T, PROBE>(inp, IN_Z4, S, gq + (Lt - 1) * P, p);
         proj<T, 3, false>(p, stash);
         C U[9];
         load_link<T>(gt, estride, gq + (Lt - 1) * P, two, U);
@@ -457,10 +459,10 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
             for (int aa = 0; aa < 3; ++aa) stl[(sp * 3 + aa) * Pb + q] = mk<T>(sg * stash[sp][aa].x, sg * stash[sp][aa].y);
     }
     C cur[12];
-    load_plane_site<T>(inp, IN_Z4, S, gq, cur);
+    load_plane_site<T, PROBE>(inp, IN_Z4, S, gq, cur);
     C hcur[12];
     if constexpr (HALO) {
-        if (q < Hb) load_plane_site<T>(inp, IN_Z4, S, ghq, hcur);
+        if (q < Hb) load_plane_site<T, PROBE>(inp, IN_Z4, S, ghq, hcur);
     }
 
     // out = alpha w + beta D w is formed as beta * ((alpha/beta) w + D w): the
@@ -514,7 +516,7 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
         if (DOT && FIRST) {
             C b[12];
             if (!BFIELD) {
-                noise_site<T>(S, s, b);
+                noise_site<T, PROBE>(S, s, b);
             } else {
                 const Plane<T> bp = plane_of<T>(a.bvec, r, a.V, a.rb_b);
 #pragma unroll
@@ -525,10 +527,10 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
         // prefetch the +t plane (plane 0 again after the last one) and its halo
         const int tn = t + 1 == Lt ? 0 : t + 1;
         C nxt[12];
-        load_plane_site<T>(inp, IN_Z4, S, gq + tn * P, nxt);
+        load_plane_site<T, PROBE>(inp, IN_Z4, S, gq + tn * P, nxt);
         C hnx[12];
         if constexpr (HALO) {
-            if (q < Hb) load_plane_site<T>(inp, IN_Z4, S, ghq + tn * P, hnx);
+            if (q < Hb) load_plane_site<T, PROBE>(inp, IN_Z4, S, ghq + tn * P, hnx);
         }
         __syncthreads();
 
@@ -627,7 +629,7 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
         if (DOT) {
             C b[12];
             if (!BFIELD) {
-                noise_site<T>(S, s, b);
+                noise_site<T, PROBE>(S, s, b);
             } else {
                 const Plane<T> bp = plane_of<T>(a.bvec, r, a.V, a.rb_b);
 #pragma unroll
@@ -802,6 +804,19 @@ template <typename T, bool Y, bool D, bool BF> static const void *sweep_kernel_h
     }
     return tw ? sweep_kernel_v<T, Y, D, BF, true, false>(v) : sweep_kernel_v<T, Y, D, BF, false, false>(v);
 }
+// probe vectors instead of Z4 noise: scalar mode, noise input (first step) or later steps
+template <typename T, bool TW, bool H> static const void *sweep_probe_v(int v) {
+    if (v == 0) return (const void *)k_sweep<T, true, true, true, false, TW, H, false, true>;
+    if (v == 2) return (const void *)k_sweep<T, false, true, false, false, TW, H, false, true>;
+    return nullptr;
+}
+template <typename T> static const void *sweep_probe_kernel(bool tw, bool h, int v) {
+    if (h) {
+        if constexpr (sizeof(T) == 4) return tw ? sweep_probe_v<T, true, true>(v) : sweep_probe_v<T, false, true>(v);
+        return nullptr;
+    }
+    return tw ? sweep_probe_v<T, true, false>(v) : sweep_probe_v<T, false, false>(v);
+}
 template <typename T> static const void *sweep_kernel(bool yacc, bool dot, bool bf, bool tw, bool h, int v) {
     if (!dot && !yacc && v < 2) return nullptr;   // the plain chain has no first-step variants
     if (yacc) {
@@ -870,7 +885,8 @@ int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, const SweepPlan &plan
         a.y_first = first_step;
         a.y_last = (j == d - 1);
         const int v = first_step ? (x_is_noise ? 0 : 1) : 2;
-        const void *k = sweep_kernel<T>(y, dot, bf, tw, h, v);
+        const void *k = colour ? ((y || bf || !dot) ? nullptr : sweep_probe_kernel<T>(tw, h, v))
+                               : sweep_kernel<T>(y, dot, bf, tw, h, v);
         if (!k) return MPMC_EUNSUPPORTED;
         if (ensure_lds_attr(k) != MPMC_OK) return MPMC_EHIP;
         void *args[] = {&a};
