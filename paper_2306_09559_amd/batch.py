@@ -44,9 +44,12 @@ class GraphStep:
     """One step of several lattice runs captured as one HIP graph."""
 
     def __init__(self, runs: Sequence[LatticeRun], batch: Optional[Dict[Tuple[int, int], int]] = None,
-                 parallel: bool = True, warmup: int = 1, only: Optional[Sequence[Tuple[int, int]]] = None):
+                 parallel: bool = True, warmup: int = 1, only: Optional[Sequence[Tuple[int, int]]] = None,
+                 keep_state: bool = False):
         """runs: the lattices; batch: samples per (run, level), default the
-        configured batch; only: restrict to these (run, level) pairs."""
+        configured batch; only: restrict to these (run, level) pairs;
+        keep_state: continue the levels' accumulators and sample counts (a
+        run resumed from a checkpoint) instead of starting from zero."""
         self.runs = list(runs)
         self.parallel = parallel
         self.items: List[List[_Item]] = []
@@ -63,6 +66,11 @@ class GraphStep:
                 row.append(_Item(run, li, n, reps, torch.zeros(1, dtype=torch.int64, device="cuda")))
             self.items.append(row)
         self.replays = 0
+        saved = None
+        if keep_state:
+            torch.cuda.synchronize()
+            saved = [[(it.run.levels[it.level].acc.clone(), it.run.levels[it.level].drawn) for it in row]
+                     for row in self.items]
         self._side = [torch.cuda.Stream() for _ in self.runs] if parallel else []
         # eager warm-up: sets kernel attributes and touches every buffer before capture
         for _ in range(warmup):
@@ -74,7 +82,15 @@ class GraphStep:
         with torch.cuda.graph(self.graph, stream=cap):
             self._enqueue_all(cap)
         torch.cuda.synchronize()
-        self.reset()
+        if saved is None:
+            self.reset()
+        else:
+            for row, srow in zip(self.items, saved):
+                for it, (acc, drawn) in zip(row, srow):
+                    it.run.levels[it.level].acc.copy_(acc)
+                    it.run.levels[it.level].drawn = drawn
+                    it.counter.fill_(drawn)
+            torch.cuda.synchronize()
 
     def _enqueue_run(self, row: List[_Item]):
         for it in row:
@@ -111,6 +127,14 @@ class GraphStep:
         for _ in range(times):
             self.graph.replay()
         self.replays += times
+
+    def sync_drawn(self):
+        """Set every level's sample count from its device counter (the replays
+        advance only the counters), e.g. before driver.save_checkpoint."""
+        torch.cuda.synchronize()
+        for row in self.items:
+            for it in row:
+                it.run.levels[it.level].drawn = int(it.counter.item())
 
     def samples_drawn(self) -> Dict[Tuple[int, int], int]:
         return {(ri, it.level): it.nsamples * it.repeats * self.replays

@@ -12,7 +12,10 @@ level is the accumulator mean plus the exact deflation correction sum_i c_i
 """
 from __future__ import annotations
 
+import json
+import os
 import time
+import types
 from dataclasses import dataclass, field
 from typing import Dict, List, Optional
 
@@ -26,7 +29,7 @@ from synth.configs import SOLVE
 
 from . import _lib as L
 from . import krylov
-from .solve import MixedPPGMRES, SolveStats
+from .solve import MixedPPGMRES, SolveNotConverged, SolveStats
 
 
 @dataclass
@@ -91,6 +94,8 @@ class LatticeRun:
                 raise ValueError(f"level {level} solves batches of {lv.solver.N} vectors")
             L.z4_fill(self.cfg.dims, L.F64, nz, lv.b64)
             lv.last_solve = lv.solver.solve(lv.b64, lv.x64, tol=lv.solve_tol)
+            if not lv.last_solve.converged:
+                raise SolveNotConverged(lv.last_solve)
             if lv.xl is not lv.x64:
                 L.field_axpby_mixed(self.cfg.dims, lv.solver.ones, lv.x64, None, lv.xl)
         self.enqueue(level, nsamples, nz)
@@ -200,7 +205,7 @@ def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optio
           arnoldi_m: Optional[int] = None, nev: Optional[int] = None, verbose: bool = False,
           reuse: Optional["LatticeRun"] = None, gmres_m: Optional[int] = None, solve_tol: Optional[float] = None,
           two_row_links: bool = True, max_batch: int = 1 << 30, rtolev: Optional[float] = None,
-          rtolpoly1: Optional[float] = None) -> LatticeRun:
+          rtolpoly1: Optional[float] = None, resume: Optional[str] = None) -> LatticeRun:
     """Set up a lattice workload: links, GMRES roots, PP-Arnoldi deflation,
     outer roots of composite polynomials (FP64 on the GPU, Sec. 5 setup
     step 2) and the level descriptors in precision `prec`.  With `reuse`,
@@ -211,8 +216,13 @@ def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optio
     SU(3) to 1e-12 are read as two rows (two_row_links).  A level's device
     buffers hold at most max_batch vectors; a step draws its samples in
     samples / batch batches.  Set-up parameters not given here come from
-    cfg.extra, else SETUP_DEFAULTS."""
+    cfg.extra, else SETUP_DEFAULTS.  With `resume`, a checkpoint written by
+    save_checkpoint supplies the set-up and every level's Monte Carlo state
+    (see there)."""
     t0 = time.perf_counter()
+    state = None
+    if resume is not None:
+        reuse, state = _load_checkpoint(resume, cfg)
     given = dict(pin_degree=pin_degree, arnoldi_m=arnoldi_m, rtolev=rtolev, nev=nev, rtolpoly1=rtolpoly1,
                  gmres_m=gmres_m, solve_tol=solve_tol, solve_rb=None)
     prm = {k: (given[k] if given[k] is not None else cfg.extra.get(k, d)) for k, d in SETUP_DEFAULTS.items()}
@@ -327,12 +337,97 @@ def build(cfg: LatticeConfig, prec: int = L.F64, rb: int = 16, pin_degree: Optio
         run.levels.append(LevelState(i, dlev, mvps(lv.hi) + mvps(lv.lo), c,
                                      torch.zeros(8, dtype=torch.float64, device="cuda"),
                                      torch.empty((N, 6), dtype=torch.float64, device="cuda"), ws, batch=N))
+    if state is not None:
+        acc, drawn = state
+        if len(acc) != len(run.levels):
+            raise ValueError(f"checkpoint has {len(acc)} levels, the workload {len(run.levels)}")
+        for lv, a, n in zip(run.levels, acc, drawn):
+            lv.acc.copy_(torch.from_numpy(np.ascontiguousarray(a)))
+            lv.drawn = int(n)
     torch.cuda.synchronize()
     run.setup_seconds = time.perf_counter() - t0
     if verbose:
         print(f"setup {cfg.name}: {run.setup_seconds:.1f} s, k_defl={defl.device.k if defl else 0}, "
               f"GMRES residuals {roots.residual}", flush=True)
     return run
+
+
+# ------------------------------------------------------------------ checkpoint / resume
+CHECKPOINT_VERSION = 1
+
+
+def _identity(cfg: LatticeConfig) -> dict:
+    return {"name": cfg.name, "dims": list(cfg.dims), "kappa": cfg.kappa, "eps": cfg.eps,
+            "antiperiodic_t": bool(cfg.antiperiodic_t), "seed_links": cfg.seed_links, "seed_start": cfg.seed_start,
+            "seed_noise": cfg.seed_noise, "lattice_id": cfg.lattice_id,
+            "levels": [[str(lv.hi), str(lv.lo), int(lv.samples), bool(lv.deflated)] for lv in cfg.levels]}
+
+
+def save_checkpoint(run: LatticeRun, path: str) -> None:
+    """Write a run's Monte Carlo state and set-up to `path` (numpy .npz, no
+    pickled objects): per level the FP64 accumulator (n, mean, M2,
+    non-finite count) and the next sample index; the GMRES roots, the
+    deflation triplets (FP64 right eigenvectors, pair, scale, H^{-1},
+    eigenvalues) and the outer roots of the double polynomials.  The noise
+    is counter-based, so build(cfg, resume=path) continues with exactly the
+    samples the uninterrupted run would have drawn and merges them into the
+    same accumulators."""
+    torch.cuda.synchronize()
+    d = {"meta": np.array(json.dumps({"version": CHECKPOINT_VERSION, "config": _identity(run.cfg)}))}
+    degs = sorted(run.roots.inv_roots)
+    d["root_degrees"] = np.array(degs, dtype=np.int64)
+    d["root_residuals"] = np.array([run.roots.residual[k] for k in degs], dtype=np.float64)
+    for k in degs:
+        d[f"root_{k}"] = np.asarray(run.roots.inv_roots[k], dtype=np.complex128)
+    keys = sorted(run.composites)
+    d["composite_keys"] = np.array(keys, dtype=np.int64).reshape(-1, 2)
+    d["composite_residuals"] = np.array([run.composites[k].residual for k in keys], dtype=np.float64)
+    for k in keys:
+        d[f"outer_{k[0]}_{k[1]}"] = np.asarray(run.composites[k].inv_roots, dtype=np.complex128)
+    if run.defl is not None:
+        df = run.defl
+        d["defl_V"] = run.defl64_V.cpu().numpy()
+        d["defl_pair"] = df.device.pair.cpu().numpy()
+        d["defl_scale"] = df.device.scale.cpu().numpy()
+        d["defl_hinv"] = df.device.hinv.cpu().numpy()
+        d["defl_lam"] = np.asarray(df.lam)
+        d["defl_res"] = np.stack([np.asarray(df.res_right), np.asarray(df.res_left)])
+        d["defl_counts"] = np.array([df.device.k, df.candidates, df.arnoldi_steps], dtype=np.int64)
+        d["defl_arnoldi_residual"] = np.array(df.arnoldi_residual)
+    d["acc"] = np.stack([lv.acc.cpu().numpy() for lv in run.levels])
+    d["drawn"] = np.array([lv.drawn for lv in run.levels], dtype=np.int64)
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, **d)
+    os.replace(tmp, path)
+
+
+def _load_checkpoint(path: str, cfg: LatticeConfig):
+    with np.load(path, allow_pickle=False) as z:
+        meta = json.loads(str(z["meta"]))
+        if meta.get("version") != CHECKPOINT_VERSION:
+            raise ValueError(f"{path}: checkpoint version {meta.get('version')}, expected {CHECKPOINT_VERSION}")
+        if meta["config"] != json.loads(json.dumps(_identity(cfg))):
+            raise ValueError(f"{path} was written for another workload: {meta['config']['name']}")
+        degs = [int(k) for k in z["root_degrees"]]
+        inv = {k: z[f"root_{k}"].copy() for k in degs}
+        roots = krylov.RootSet(inv, {k: L.DevicePoly(krylov._c(inv[k])) for k in degs},
+                               {k: float(r) for k, r in zip(degs, z["root_residuals"])})
+        comps = {}
+        for (n_in, n_out), res in zip(z["composite_keys"], z["composite_residuals"]):
+            key = (int(n_in), int(n_out))
+            out = z[f"outer_{key[0]}_{key[1]}"].copy()
+            comps[key] = krylov.OuterRoots(out, L.DevicePoly(krylov._c(inv[key[0] - 1]), krylov._c(out)), float(res))
+        saved = types.SimpleNamespace(roots=roots, composites=comps, defl=None, defl64_V=None)
+        if "defl_V" in z:
+            k, cand, steps = (int(v) for v in z["defl_counts"])
+            V64 = torch.from_numpy(z["defl_V"].copy()).cuda()
+            dev = L.DeviceDefl(k, V64, torch.from_numpy(z["defl_pair"].copy()).cuda(),
+                               torch.from_numpy(z["defl_scale"].copy()).cuda(),
+                               torch.from_numpy(z["defl_hinv"].copy()).cuda())
+            saved.defl = krylov.Deflation(dev, z["defl_lam"].copy(), z["defl_pair"].copy(), z["defl_res"][0].copy(),
+                                          z["defl_res"][1].copy(), cand, steps, float(z["defl_arnoldi_residual"]))
+            saved.defl64_V = V64
+        return saved, (z["acc"].copy(), z["drawn"].copy())
 
 
 def time_to_error(variances, seconds_per_sample, eps: float) -> float:

@@ -38,6 +38,17 @@ class SolveStats:
     mvps: int = 0                        # operator applications per vector
     rel_res: Optional[np.ndarray] = None  # final ||b - A x|| / ||b|| per vector (FP64)
     history: List[float] = field(default_factory=list)   # max relative residual after each outer step
+    converged: bool = False               # every vector reached the tolerance
+    tol: float = 0.0
+
+
+class SolveNotConverged(RuntimeError):
+    """A top-level solve ended above its tolerance (its samples would be biased)."""
+
+    def __init__(self, stats: "SolveStats"):
+        super().__init__(f"PP-GMRES did not converge: max relative residual {float(np.max(stats.rel_res)):.3e} "
+                         f"> tolerance {stats.tol:.1e} after {stats.outer} refinement steps, {stats.cycles} cycles")
+        self.stats = stats
 
 
 class MixedPPGMRES:
@@ -194,4 +205,6 @@ class MixedPPGMRES:
         if not have_x:
             L.field_axpby(dims, L.F64, _c(np.zeros(N)), b64, None, x64)
         stats.rel_res = self._norms(L.F64, self.r64) / bn
+        stats.tol = float(tol)
+        stats.converged = bool(np.all(stats.rel_res <= tol))
         return stats

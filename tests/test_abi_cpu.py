@@ -104,3 +104,25 @@ def test_workspace_sizes_scale(L):
     assert a >= 2 * field and b >= 5 * field
     lat32 = _lat(L, prec=1)
     assert lib.mpmc_poly_workspace_size(ctypes.byref(lat32), ctypes.byref(single), sh) < a
+
+
+def test_workspace_too_small_is_rejected_on_the_host(L):
+    """A workspace one byte short of the *_workspace_size result returns
+    MPMC_EWORKSPACE before anything is enqueued (fake device pointers: the
+    host never dereferences them)."""
+    lib = L._lib
+    lat = _lat(L)
+    roots = ctypes.c_void_p(64)
+    poly = L.mpmc_poly(4, 0, roots, None)
+    sh = L.mpmc_shape(8, 4)
+    need = lib.mpmc_poly_workspace_size(ctypes.byref(lat), ctypes.byref(poly), sh)
+    assert need > 0
+    x, y, ws = ctypes.c_void_p(256), ctypes.c_void_p(512), ctypes.c_void_p(4096)
+    st = lib.mpmc_poly_apply(ctypes.byref(lat), ctypes.byref(poly), sh, x, None, y, None, ws, need - 1, None)
+    assert st == L.EWORKSPACE
+    # probe noise outside the scalar t-sweep is refused on the host too
+    col = ctypes.c_void_p(8192)
+    nz = L.mpmc_noise(0, 0, 0, 0, None, col)
+    st = lib.mpmc_poly_apply(ctypes.byref(lat), ctypes.byref(poly), sh, None, ctypes.byref(nz), y, None, ws, need,
+                             None)
+    assert st == L.EUNSUPPORTED
