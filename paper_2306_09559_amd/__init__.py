@@ -5,14 +5,19 @@
     _lib         ctypes binding (same entry-point names, marshalling only)
     build        compiles libmpmc.so in-tree for gfx950
     krylov       GPU setup: GMRES/Arnoldi roots and PP-Arnoldi eigenvectors
-    driver       per-lattice state and the multilevel sampling loop
+    solve        deflated PP-GMRES for the top level (FP32 inner, FP64 refinement)
+    driver       per-lattice state, the multilevel sampling loop, the adaptive
+                 stopping rule, checkpoint / resume
+    batch        several lattices' steps as one HIP graph; shape autotuner
+    probing      exact low-degree traces by probing with a distance colouring
+    diagnostics  deflation diagnostics (how many eigenvectors to deflate)
 
 The binding is imported lazily so that `build` works on a machine without a
 GPU; using any entry point requires the built library.
 """
 import importlib
 
-__all__ = ["_lib", "build", "krylov", "driver"]
+__all__ = ["_lib", "build", "krylov", "solve", "driver", "batch", "probing", "diagnostics"]
 
 
 def __getattr__(name):
