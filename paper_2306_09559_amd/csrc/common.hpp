@@ -57,6 +57,16 @@ template <typename T> __device__ __forceinline__ cplx_t<T> axpy_d(double2 a, cpl
     return mk<T>((T)((double)y.x + (a.x * xr - a.y * xi)), (T)((double)y.y + (a.x * xi + a.y * xr)));
 }
 
+// p advanced by an offset the compiler cannot see (zero): address arithmetic
+// built on the result stays inside a rolled loop instead of being hoisted.
+// Hiding the pointer itself would also hide that it points to global memory,
+// and its loads would become flat loads, which hold up every LDS wait.
+template <typename P> __device__ __forceinline__ P *opaque_ptr(P *p) {
+    long z = 0;
+    asm volatile("" : "+s"(z));
+    return p + z;
+}
+
 // i * a and -i * a
 template <typename T> __device__ __forceinline__ cplx_t<T> mul_i(cplx_t<T> a) { return mk<T>(-a.y, a.x); }
 template <typename T> __device__ __forceinline__ cplx_t<T> mul_mi(cplx_t<T> a) { return mk<T>(a.y, -a.x); }

@@ -213,7 +213,7 @@ __device__ __forceinline__ void hop_all(const HopArgs<T> &a, const Blk<T> &in, i
         int sl = s, xl[4] = {x[0], x[1], x[2], x[3]};
         asm volatile("" : "+v"(sl), "+v"(xl[0]), "+v"(xl[1]), "+v"(xl[2]), "+v"(xl[3]));
         Blk<T> il = in;
-        asm volatile("" : "+s"(il.base));
+        il.base = opaque_ptr(il.base);
         switch (d) {
         case 0: hop_one<T, 0, true>(a, il, jr, z4, S, sl, xl, acc); break;
         case 1: hop_one<T, 0, false>(a, il, jr, z4, S, sl, xl, acc); break;

@@ -458,6 +458,15 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
 #pragma unroll
             for (int aa = 0; aa < 3; ++aa) stl[(sp * 3 + aa) * Pb + q] = mk<T>(sg * stash[sp][aa].x, sg * stash[sp][aa].y);
     }
+    // Vector memory operations complete in issue order, so a wait for a link
+    // (an L2 hit) also waits for every HBM load and store issued before it.
+    // The links a step needs first are therefore requested ahead of the plane
+    // traffic: the -t link of the next step before this step's stores, the
+    // first spatial hop's link before the next plane's loads (measured at
+    // 8^4 x 256 vectors FP64, with the hops unrolled: 112 -> 106 us per launch;
+    // at 64 vectors 83 -> 75 us).
+    C Ust[9];
+    link_raw<T, TWO>(gt, estride, gq, Ust);
     C cur[12];
     load_plane_site<T, PROBE>(inp, IN_Z4, S, gq, cur);
     C hcur[12];
@@ -503,11 +512,10 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
         }
         // the -t term of (x, t+1): (1 + g_t) U_t(x, t)^H w(x, t)
         {
-            C U[9];
             C st[2][3];
-            load_link<T>(gt, estride, s, two, U);
+            link_complete<T, TWO>(Ust);
             proj<T, 3, false>(cur, st);
-            mul_link<T, true>(U, st);
+            mul_link<T, true>(Ust, st);
 #pragma unroll
             for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
@@ -524,7 +532,11 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
             }
             dot_acc<T>(b, cur, d0re, d0im);
         }
-        // prefetch the +t plane (plane 0 again after the last one) and its halo
+        // the first spatial hop's link, then the +t plane (plane 0 again after
+        // the last one) and its halo
+        C U0[9];
+        link_raw<T, TWO>(gx, estride, s, U0);
+        __builtin_amdgcn_sched_barrier(0);
         const int tn = t + 1 == Lt ? 0 : t + 1;
         C nxt[12];
         load_plane_site<T, PROBE>(inp, IN_Z4, S, gq + tn * P, nxt);
@@ -544,20 +556,16 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
             // spare: there the prefetch spills, and FP64 without the spills
             // measured no faster.
             C Ua[9];
-            {
-                int s0 = s;
-                const char *g0p = gx;
-                asm volatile("" : "+v"(s0), "+s"(g0p));
-                link_raw<T, TWO>(g0p, estride, s0, Ua);
-            }
+#pragma unroll
+            for (int e = 0; e < 9; ++e) Ua[e] = U0[e];
 #pragma nounroll
             for (int k2 = 0; k2 < 3; ++k2) {
                 C Ub[9];
                 int qf = k2 == 0 ? sxp : k2 == 1 ? syp : szp;
                 int qb = k2 == 0 ? sxm : k2 == 1 ? sym : szm;
                 int sb = (k2 == 0 ? gxm : k2 == 1 ? gym : gzm) + t * P;
-                const char *gm = k2 == 0 ? gx : k2 == 1 ? gy : gz;
-                asm volatile("" : "+v"(qf), "+v"(qb), "+v"(sb), "+s"(gm));
+                const char *gm = opaque_ptr(k2 == 0 ? gx : k2 == 1 ? gy : gz);
+                asm volatile("" : "+v"(qf), "+v"(qb), "+v"(sb));
                 link_raw<T, TWO>(gm, estride, sb, Ub);
                 link_complete<T, TWO>(Ua);
                 switch (k2) {
@@ -566,8 +574,8 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
                 default: plane_hop_u<T, 2, true>(lds, Sl, qf, Ua, acc); break;
                 }
                 int sn = s;
-                const char *gn = k2 == 0 ? gy : k2 == 1 ? gz : gt;
-                asm volatile("" : "+v"(sn), "+s"(gn));
+                const char *gn = opaque_ptr(k2 == 0 ? gy : k2 == 1 ? gz : gt);
+                asm volatile("" : "+v"(sn));
                 link_raw<T, TWO>(gn, estride, sn, Ua);
                 link_complete<T, TWO>(Ub);
                 switch (k2) {
@@ -587,24 +595,24 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
                 for (int aa = 0; aa < 3; ++aa) h[sp][aa] = mk<T>(sg * h[sp][aa].x, sg * h[sp][aa].y);
             recon<T, 3, true>(h, acc);
         } else {
-        // The six spatial hops run as a rolled loop with opaque copies of the
-        // loop-invariant inputs: the compiler can then neither interleave the
-        // hops nor hoist their addresses, which bounds the live registers.
-#pragma nounroll
-        for (int k = 0; k < 6; ++k) {
-            int qn = k == 0 ? sxp : k == 1 ? sxm : k == 2 ? syp : k == 3 ? sym : k == 4 ? szp : szm;
-            int gs = k == 1 ? gxm + t * P : k == 3 ? gym + t * P : k == 5 ? gzm + t * P : s;
-            const char *gg = k < 2 ? gx : k < 4 ? gy : gz;
-            asm volatile("" : "+v"(qn), "+v"(gs), "+s"(gg));
-            switch (k) {
-            case 0: plane_hop<T, 0, true>(lds, Sl, qn, gg, estride, gs, two, acc); break;
-            case 1: plane_hop<T, 0, false>(lds, Sl, qn, gg, estride, gs, two, acc); break;
-            case 2: plane_hop<T, 1, true>(lds, Sl, qn, gg, estride, gs, two, acc); break;
-            case 3: plane_hop<T, 1, false>(lds, Sl, qn, gg, estride, gs, two, acc); break;
-            case 4: plane_hop<T, 2, true>(lds, Sl, qn, gg, estride, gs, two, acc); break;
-            default: plane_hop<T, 2, false>(lds, Sl, qn, gg, estride, gs, two, acc); break;
-            }
-        }
+        // The six spatial hops in sequence, with scheduling barriers between
+        // them so that the compiler cannot interleave them (which bounds the
+        // live registers).  Unrolled they cost no loop overhead: a rolled loop
+        // over a switch spent ~230 of ~1750 instructions per site and step on
+        // dispatch and on copying the accumulator (83 -> 77 us at 64 vectors).
+        link_complete<T, TWO>(U0);
+        plane_hop_u<T, 0, true>(lds, Sl, sxp, U0, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        plane_hop<T, 0, false>(lds, Sl, sxm, gx, estride, gxm + t * P, two, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        plane_hop<T, 1, true>(lds, Sl, syp, gy, estride, s, two, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        plane_hop<T, 1, false>(lds, Sl, sym, gy, estride, gym + t * P, two, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        plane_hop<T, 2, true>(lds, Sl, szp, gz, estride, s, two, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        plane_hop<T, 2, false>(lds, Sl, szm, gz, estride, gzm + t * P, two, acc);
+        __builtin_amdgcn_sched_barrier(0);
         // +t hop: (1 - g_t) U_t(x, t) w(x, t+1)
         {
             C U[9];
@@ -621,6 +629,10 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
             recon<T, 3, true>(h, acc);
         }
         }
+        // the next step's -t link ahead of the stores (the site clamped on the
+        // last step: a conditional load here made the compiler spill)
+        link_raw<T, TWO>(gt, estride, t + 1 < Lt ? s + P : s, Ust);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
             acc[c] = cmul_d<T>(beta, acc[c]);
