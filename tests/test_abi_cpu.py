@@ -58,6 +58,11 @@ def test_validation_without_device(L):
     assert lib.mpmc_wilson_apply(ctypes.byref(zero), sh, x, y, None) == L.EINVAL
     nog = _lat(L, gauge=None)
     assert lib.mpmc_wilson_apply(ctypes.byref(nog), sh, x, y, None) == L.EINVAL
+    # an empty or negative batch (the header requires N >= 1) is an argument error, not a no-op launch
+    for n in (0, -4):
+        assert lib.mpmc_wilson_apply(ctypes.byref(lat), L.mpmc_shape(n, 4), x, y, None) == L.EINVAL
+        assert lib.mpmc_z4_fill((ctypes.c_int32 * 4)(4, 4, 4, 4), 0, L.mpmc_shape(n, 1),
+                                ctypes.byref(L.mpmc_noise(1, 2, 3, 0)), x, None) == L.EINVAL
     # polynomial: no roots, no outputs, workspace too small
     roots = ctypes.c_void_p(64)
     p0 = L.mpmc_poly(0, 0, roots, None)
@@ -89,6 +94,12 @@ def test_validation_without_device(L):
     lv2 = L.mpmc_level(1, 0, p, p, ctypes.pointer(d16), 1, None)
     assert lib.mpmc_mlmc_level_estimate(ctypes.byref(lat), ctypes.byref(lv2), sh, ctypes.byref(nz), z, z, None, 0,
                                         None) == L.EINVAL
+    # no samples
+    lv1 = L.mpmc_level(1, 0, p, p, None, 0, None)
+    assert lib.mpmc_mlmc_level_estimate(ctypes.byref(lat), ctypes.byref(lv1), L.mpmc_shape(0, 1), ctypes.byref(nz),
+                                        z, z, None, 0, None) == L.EINVAL
+    assert lib.mpmc_poly_apply(ctypes.byref(lat), ctypes.byref(p), L.mpmc_shape(0, 1), x, None, y, None, None, 0,
+                               None) == L.EINVAL
 
 
 def test_workspace_sizes_scale(L):
