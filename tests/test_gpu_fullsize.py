@@ -6,6 +6,11 @@
   own GMRES roots.  FP64 within max(1e-12, 4 d kappa_N u64) relative (the
   workload is near-critical, so the amplification kappa_N of the Newton
   recurrence is measured and reported); FP32 within 8 d kappa_N u32.
+* 24^3 x 48 workload (n = 7.96M, the largest): its lowest level's polynomial
+  (degree 4, GMRES roots at full size) over 16 Z4 vectors in FP32 on the
+  blocked t-sweep (24 x 4 x 4 blocks of the 24^3 plane with a one-site halo)
+  and on the streaming kernel; the first and last samples are recomputed by
+  the oracle at full size, within 8 d kappa_N u32.
 * 16^3 x 32 workload (n = 1.57M, 64 vectors): the top-level solutions of one
   batch satisfy ||b - A x|| <= 1e-6 ||b|| through the oracle operator, for
   sampled vectors (a property that holds at any size).
@@ -78,6 +83,44 @@ def test_c2_top_level_sampled_vs_oracle(c2, prec):
             bound = max(1e-12, 4 * d * kN * U64) if prec == 0 else 8 * d * kN * U32
             err = abs(got - want) / abs(want)
             print(f"prec {prec} r {r} d {d}: rel err {err:.2e}, kappa_N {kN:.3g}, bound {bound:.2e}")
+            assert err <= bound
+
+
+def test_c4_planes_blocked_sweep_sampled_vs_oracle():
+    L = lib()
+    from synth.configs import C4
+    dims, V, N, rb, prec = C4.dims, C4.volume, 16, 1, 1
+    U = synth.gauge_links(dims, C4.eps, C4.seed_links)
+    ol = oracle.Lattice(dims, C4.kappa, U, C4.antiperiodic_t)
+    d = C4.levels[3].hi
+    t = krylov.gmres_polys(ol.apply, synth.gaussian_start(ol.n, C4.seed_start), [d]).inv_roots[d]
+    gauge = torch.empty(36 * V, dtype=L.complex_dtype(prec), device="cuda")
+    L.pack_gauge(dims, prec, torch.from_numpy(U).cuda(), gauge)
+    del U
+    dl = L.DeviceLattice(tuple(dims), C4.kappa, C4.antiperiodic_t, prec, gauge)
+    plan = L.sweep_plan(dl, N, rb)
+    assert plan["ok"] and plan["halo"], plan
+    print("block", plan["block"], "halo sites", plan["halo_sites"])
+    poly = L.DevicePoly(dev_c128(t))
+    ws = L.workspace(L.poly_workspace_size(dl, poly, N, rb))
+    nz = L.Noise(C4.seed_noise, C4.lattice_id, 3, 0)
+    out = {}
+    for opt in (1, 0):
+        L.set_option(L.OPT_PLANE_SWEEP, opt)
+        bhy = torch.empty(N, dtype=torch.complex128, device="cuda")
+        L.poly_apply(dl, poly, N, rb, None, nz, None, bhy, ws)
+        torch.cuda.synchronize()
+        out[opt] = bhy.cpu().numpy()
+    L.set_option(L.OPT_PLANE_SWEEP, 1)
+    del ws, gauge
+    for r in (0, N - 1):
+        b = oracle.z4(C4.seed_noise, C4.lattice_id, 3, r, 1, V)[0]
+        _, want = ol.poly_apply(t, b)
+        kN = _kappa_N(ol, t, b)
+        bound = 8 * d * kN * U32
+        for opt in (1, 0):
+            err = abs(out[opt][r] - want[0]) / abs(want[0])
+            print(f"r {r} {'sweep' if opt else 'streaming'}: rel err {err:.2e}, kappa_N {kN:.3g}, bound {bound:.2e}")
             assert err <= bound
 
 
