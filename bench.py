@@ -90,6 +90,27 @@ def calibrate_copy():
     torch.cuda.synchronize()
 
 
+def copy_bandwidth_gbs(reps: int = 10) -> float:
+    """Measured HBM bandwidth of a plain device copy on this GPU (the
+    library's streaming copy, mpmc_field_copy_bytes): 1 GiB read and 1 GiB
+    written per copy, timed with HIP events over `reps` copies."""
+    import torch
+    from paper_2306_09559_amd import _lib as L
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    L.field_copy_bytes(a, b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        L.field_copy_bytes(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    return 2 * (1 << 30) / sec / 1e9
+
+
 def cpu_baseline(cfg, run_prec: str):
     """The oracle (plain C FP64, OpenMP over sites) on a bounded sample of the
     same workload: rounds of one Z4 sample per level (every polynomial of
@@ -342,6 +363,7 @@ def main():
     per_launch_bytes = driver.launch_bytes(V, N, prec)
     achieved = per_launch_bytes / launch_s / 1e9
     traffic = measured_traffic(args.prec)
+    copy_gbs = copy_bandwidth_gbs()
 
     est = run.estimates()
     eps = 0.0005 * V
@@ -368,7 +390,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": KERNEL, "bytes_per_launch": per_launch_bytes,
-                     "avg_launch_us": round(launch_s * 1e6, 3)},
+                     "avg_launch_us": round(launch_s * 1e6, 3),
+                     "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
         "time_to_eps_s": round(t_eps, 4),
         "eps": eps,
         "levels": [{"estimate": [round(e["estimate"].real, 6), round(e["estimate"].imag, 6)],

@@ -233,6 +233,13 @@ int mpmc_field_dot(const int32_t dims[4], int32_t prec, mpmc_shape shape, const 
 int mpmc_field_copy_vector(const int32_t dims[4], int32_t prec, mpmc_shape src_shape, const void *src,
                            int32_t src_index, mpmc_shape dst_shape, void *dst, int32_t dst_index, void *stream);
 
+/* dst[0 .. bytes) = src[0 .. bytes): a plain streaming device copy (16-byte
+ * nontemporal loads and stores).  Moves whole batches, and is the reference
+ * copy against which the kernels' HBM rates are compared.  bytes a multiple
+ * of 16, both pointers 16-byte aligned, the ranges disjoint; bytes == 0 is a
+ * no-op.  Violations return MPMC_EINVAL before anything is enqueued. */
+int mpmc_field_copy_bytes(const void *src, void *dst, size_t bytes, void *stream);
+
 /* ---- Krylov bases of a batch (GMRES cycles, Sec. 2.1, Sec. 5 step 3a) --
  * A basis is k fields of one shape stored back to back: vector i of the
  * basis starts N*12*V complex numbers after vector i-1.  Every vector r of

@@ -79,6 +79,7 @@ _sig = {
     "mpmc_field_dot": (ctypes.c_int, [P(c_i32), c_i32, mpmc_shape, c_vp, c_vp, c_vp, c_vp, c_size, c_vp]),
     "mpmc_field_copy_vector": (ctypes.c_int, [P(c_i32), c_i32, mpmc_shape, c_vp, c_i32, mpmc_shape, c_vp, c_i32,
                                               c_vp]),
+    "mpmc_field_copy_bytes": (ctypes.c_int, [c_vp, c_vp, c_size, c_vp]),
     "mpmc_field_axpby_mixed": (ctypes.c_int, [P(c_i32), mpmc_shape, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp]),
     "mpmc_field_block_dot_workspace_size": (c_size, [P(c_i32), mpmc_shape, c_i32]),
     "mpmc_field_block_dot": (ctypes.c_int, [P(c_i32), c_i32, mpmc_shape, c_i32, c_vp, c_vp, c_vp, c_vp, c_size,
@@ -321,6 +322,14 @@ def field_copy_vector(dims, prec: int, src: torch.Tensor, src_index: int, dst: t
     _check("mpmc_field_copy_vector", _lib.mpmc_field_copy_vector(
         _dims(dims), prec, field_shape(src), _ptr(src), int(src_index), field_shape(dst), _ptr(dst),
         int(dst_index), _stream()))
+
+
+def field_copy_bytes(src: torch.Tensor, dst: torch.Tensor):
+    """dst = src for two contiguous device tensors of the same byte size."""
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb or not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("field_copy_bytes needs contiguous tensors of equal byte size")
+    _check("mpmc_field_copy_bytes", _lib.mpmc_field_copy_bytes(_ptr(src), _ptr(dst), nb, _stream()))
 
 
 def field_axpby_mixed(dims, alpha: torch.Tensor, x: torch.Tensor, beta: Optional[torch.Tensor], y: torch.Tensor):

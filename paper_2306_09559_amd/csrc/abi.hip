@@ -245,6 +245,15 @@ int mpmc_field_copy_vector(const int32_t dims[4], int32_t prec, mpmc_shape src_s
     return field_copy_vector_impl(dims, prec, src_shape, src, src_index, dst_shape, dst, dst_index, stream);
 }
 
+int mpmc_field_copy_bytes(const void *src, void *dst, size_t bytes, void *stream) {
+    if (bytes == 0) return MPMC_OK;
+    if (!src || !dst || bytes % 16 != 0) return MPMC_EINVAL;
+    if (((uintptr_t)src | (uintptr_t)dst) % 16 != 0) return MPMC_EINVAL;
+    const char *s = (const char *)src, *d = (const char *)dst;
+    if (d < s + bytes && s < d + bytes) return MPMC_EINVAL;
+    return field_copy_bytes_impl(src, dst, bytes, stream);
+}
+
 size_t mpmc_poly_workspace_size(const mpmc_lattice *lat, const mpmc_poly *poly, mpmc_shape shape) {
     if (check_lattice(lat) != MPMC_OK || check_poly(poly) != MPMC_OK || !valid_shape(shape)) return 0;
     return poly_ws_bytes(lat->dims, lat->prec, *poly, shape);

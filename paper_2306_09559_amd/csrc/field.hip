@@ -334,6 +334,31 @@ int field_relayout_impl(const int32_t dims[4], int32_t prec, int32_t nrhs, const
     return st();
 }
 
+// 16-byte elements i < n, grid-stride: four workgroups per CU streaming
+// with the nontemporal hint measured fastest for large copies (5.9 TB/s at
+// 1 GiB against 4.6-5.4 TB/s with more workgroups or cached accesses)
+__global__ void __launch_bounds__(256) k_copy_bytes(const double2 *__restrict__ x, double2 *__restrict__ y, size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double2 v;
+        v.x = __builtin_nontemporal_load(&x[i].x);
+        v.y = __builtin_nontemporal_load(&x[i].y);
+        __builtin_nontemporal_store(v.x, &y[i].x);
+        __builtin_nontemporal_store(v.y, &y[i].y);
+    }
+}
+
+int field_copy_bytes_impl(const void *src, void *dst, size_t bytes, void *stream) {
+    const size_t n = bytes / 16;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const size_t want = (n + 255) / 256, cap = (size_t)4 * (size_t)(cus > 0 ? cus : 256);
+    const unsigned g = (unsigned)(want < cap ? want : cap);
+    hipLaunchKernelGGL(k_copy_bytes, dim3(g), dim3(256), 0, (hipStream_t)stream, (const double2 *)src, (double2 *)dst,
+                       n);
+    return st();
+}
+
 int field_copy_vector_impl(const int32_t dims[4], int32_t prec, mpmc_shape ssh, const void *src, int32_t si,
                            mpmc_shape dsh, void *dst, int32_t di, void *stream) {
     const int V = dims[0] * dims[1] * dims[2] * dims[3];

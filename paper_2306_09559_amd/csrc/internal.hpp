@@ -86,6 +86,7 @@ int field_relayout_impl(const int32_t dims[4], int32_t prec, int32_t nrhs, const
                         int32_t dst_rb, void *stream);
 int field_copy_vector_impl(const int32_t dims[4], int32_t prec, mpmc_shape ssh, const void *src, int32_t si,
                            mpmc_shape dsh, void *dst, int32_t di, void *stream);
+int field_copy_bytes_impl(const void *src, void *dst, size_t bytes, void *stream);
 int field_axpby_mixed_impl(const int32_t dims[4], mpmc_shape sh, int32_t xp, const double *alpha, const void *x,
                            int32_t yp, const double *beta, void *y, void *stream);
 size_t block_dot_ws_bytes(const int32_t dims[4], mpmc_shape sh, int k);

@@ -63,6 +63,12 @@ def test_validation_without_device(L):
         assert lib.mpmc_wilson_apply(ctypes.byref(lat), L.mpmc_shape(n, 4), x, y, None) == L.EINVAL
         assert lib.mpmc_z4_fill((ctypes.c_int32 * 4)(4, 4, 4, 4), 0, L.mpmc_shape(n, 1),
                                 ctypes.byref(L.mpmc_noise(1, 2, 3, 0)), x, None) == L.EINVAL
+    # plain copy: zero bytes is a no-op; ragged sizes, misaligned or overlapping ranges are rejected
+    assert lib.mpmc_field_copy_bytes(None, None, 0, None) == L.OK
+    assert lib.mpmc_field_copy_bytes(ctypes.c_void_p(4096), ctypes.c_void_p(1 << 20), 24, None) == L.EINVAL
+    assert lib.mpmc_field_copy_bytes(ctypes.c_void_p(4104), ctypes.c_void_p(1 << 20), 32, None) == L.EINVAL
+    assert lib.mpmc_field_copy_bytes(ctypes.c_void_p(4096), ctypes.c_void_p(4096 + 64), 128, None) == L.EINVAL
+    assert lib.mpmc_field_copy_bytes(None, ctypes.c_void_p(4096), 32, None) == L.EINVAL
     # polynomial: no roots, no outputs, workspace too small
     roots = ctypes.c_void_p(64)
     p0 = L.mpmc_poly(0, 0, roots, None)

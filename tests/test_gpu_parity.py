@@ -41,6 +41,21 @@ def test_z4_bit_exact(dims, nrhs, rb, prec):
     assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("nbytes", [16, 4096 * 16 + 48, 3 << 24])
+def test_copy_bytes_bit_exact(nbytes):
+    """The plain streaming copy moves every byte (sizes below one workgroup,
+    ragged, and larger than its grid-stride cap), and leaves the bytes past
+    the end untouched."""
+    L = lib()
+    g = torch.Generator().manual_seed(nbytes)
+    src = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, generator=g).cuda()
+    dst = torch.zeros(nbytes + 64, dtype=torch.uint8, device="cuda")
+    L.field_copy_bytes(src, dst[:nbytes])
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:nbytes], src)
+    assert int(dst[nbytes:].sum()) == 0
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_pack_roundtrip(prec):
     dims = (4, 2, 2, 6)
