@@ -53,10 +53,13 @@ namespace {
 
 template <typename T> __device__ __forceinline__ cplx_t<T> neg(cplx_t<T> a) { return mk<T>(-a.x, -a.y); }
 
-// Every spinor of a sweep is read once and written once, so the plane loads
-// and stores carry the nontemporal hint: they stream through L2 without
-// evicting the links, which every workgroup of the launch reads again
-// (measured: 139 -> 110 us per FP64 launch at 8^4 x 256 vectors).
+// Every spinor of a sweep is read once, so the plane loads carry the
+// nontemporal hint: they stream through L2 without evicting the links, which
+// every workgroup of the launch reads again (measured: 139 -> 110 us per FP64
+// launch at 8^4 x 256 vectors, loads and stores nontemporal).  The stores are
+// plain: the step's next link wait also waits for them (vector memory
+// operations complete in issue order), and plain stores complete sooner
+// (FP64 106 -> 102 us at 8^4 x 256 vectors, 74 -> 72 us at 64; FP32 even).
 // Component c of vector r of a batch with block width rb, site s, lives at
 // byte  cbase(r, c) + s * rb * sizeof(C)  where cbase is wavefront-uniform
 // (scalar registers) and the per-site offset fits 32 bits (V * rb * sizeof(C)
@@ -71,8 +74,8 @@ template <typename T> struct Plane {
     }
     __device__ __forceinline__ void st(int c, int s, cplx_t<T> v) const {
         T *p = (T *)(const_cast<char *>(base) + (size_t)c * cstride + (uint32_t)s * sstride);
-        __builtin_nontemporal_store(v.x, p);
-        __builtin_nontemporal_store(v.y, p + 1);
+        p[0] = v.x;
+        p[1] = v.y;
     }
 };
 
