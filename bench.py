@@ -334,8 +334,8 @@ def c4_step():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                          "(sample-parallel sharding across GPUs is a design note, not implemented)"}))
+        print(json.dumps({"error": "the library runs on one GPU: --gpus must be 1 "
+                          "(sample-parallel sharding across GPUs is not implemented)"}))
         sys.exit(2)
     import numpy as np
     import torch
