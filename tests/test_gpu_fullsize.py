@@ -11,6 +11,12 @@
   blocked t-sweep (24 x 4 x 4 blocks of the 24^3 plane with a one-site halo)
   and on the streaming kernel; the first and last samples are recomputed by
   the oracle at full size, within 8 d kappa_N u32.
+* 16^3 x 32 workload (n = 1.57M, 64 vectors): its double polynomial
+  p_1 = p_in(A) p_out(A p_in(A)) (PP(20) x 15, degree 299, roots from the GPU
+  set-up) in FP32 scalar mode, the inner chains on the blocked t-sweep and the
+  outer update on the streaming kernel; samples 0 and 63 recomputed by the
+  oracle at full size with the same roots, within 8 d 50 u32 (the bound of the
+  small-size composite tests).
 * 16^3 x 32 workload (n = 1.57M, 64 vectors): the top-level solutions of one
   batch satisfy ||b - A x|| <= 1e-6 ||b|| through the oracle operator, for
   sampled vectors (a property that holds at any size).
@@ -122,6 +128,36 @@ def test_c4_planes_blocked_sweep_sampled_vs_oracle():
             err = abs(out[opt][r] - want[0]) / abs(want[0])
             print(f"r {r} {'sweep' if opt else 'streaming'}: rel err {err:.2e}, kappa_N {kN:.3g}, bound {bound:.2e}")
             assert err <= bound
+
+
+def test_c3_double_polynomial_sampled_vs_oracle():
+    L = lib()
+    from paper_2306_09559_amd import driver
+    from synth.configs import C3
+    run = driver.build(C3, prec=L.F32, rb=16)
+    key = sorted(run.composites)[0]
+    comp = run.composites[key]
+    t_in, t_out = run.roots.inv_roots[key[0] - 1], comp.inv_roots
+    N, rb, V = C3.levels[0].samples, 16, C3.volume
+    assert L.sweep_plan(run.dl, N, 1)["halo"]
+    nz = L.Noise(C3.seed_noise, C3.lattice_id, 5, 0)
+    ws = L.workspace(L.poly_workspace_size(run.dl, comp.device, N, rb))
+    bhy = torch.empty(N, dtype=torch.complex128, device="cuda")
+    L.set_option(L.OPT_PLANE_SWEEP, 1)
+    L.poly_apply(run.dl, comp.device, N, rb, None, nz, None, bhy, ws)
+    torch.cuda.synchronize()
+    got = bhy.cpu().numpy()
+    del ws
+    assert np.all(np.isfinite(got))
+    ol = oracle.Lattice(C3.dims, C3.kappa, synth.gauge_links(C3.dims, C3.eps, C3.seed_links), C3.antiperiodic_t)
+    d = len(t_in) * len(t_out) - 1
+    bound = 8 * d * 50 * U32
+    for r in (0, N - 1):
+        b = oracle.z4(C3.seed_noise, C3.lattice_id, 5, r, 1, V)[0]
+        _, want = ol.composite_apply(t_in, t_out, b)
+        err = abs(got[r] - want[0]) / abs(want[0])
+        print(f"{key} degree {d} r {r}: rel err {err:.2e}, bound {bound:.2e}")
+        assert err <= bound
 
 
 def test_c3_top_level_solutions_full_size():
