@@ -16,6 +16,11 @@
   blocked t-sweep (24 x 4 x 4 blocks of the 24^3 plane with a one-site halo)
   and on the streaming kernel; the first and last samples are recomputed by
   the oracle at full size, within 8 d kappa_N u32.
+* the deflation coefficients V^H b and U^H b over the 24^3 x 48 lattice's
+  n = 7.96M rows in FP32 on MFMA (k = 20 padded to 32, 128 Z4 vectors):
+  eigenvector entries in {-1, 0, 1} + i{-1, 0, 1} and left vectors g5 z / 2
+  make every product and partial sum exact in FP32, so sampled columns must
+  equal the oracle's exactly, whatever the summation order.
 * 16^3 x 32 workload (n = 1.57M, 64 vectors): its double polynomial
   p_1 = p_in(A) p_out(A p_in(A)) (PP(20) x 15, degree 299, roots from the GPU
   set-up) in FP32 scalar mode, the inner chains on the blocked t-sweep and the
@@ -33,7 +38,7 @@ import torch
 import oracle
 import synth
 from oracle import krylov, solve as osolve
-from gpu_helpers import dev_c128, lib
+from gpu_helpers import dev_c128, lib, pack
 
 pytestmark = pytest.mark.gpu
 
@@ -175,6 +180,39 @@ def test_c4_planes_blocked_sweep_sampled_vs_oracle():
             err = abs(out[opt][r] - want[0]) / abs(want[0])
             print(f"r {r} {'sweep' if opt else 'streaming'}: rel err {err:.2e}, kappa_N {kN:.3g}, bound {bound:.2e}")
             assert err <= bound
+
+
+def test_c4_size_deflation_coefficients_exact():
+    L = lib()
+    dims = (24, 24, 24, 48)
+    V = int(np.prod(dims))
+    n, k, kpad, N, rb = 12 * V, 20, 32, 128, 16
+    rng = np.random.default_rng(11)
+    Z = (rng.integers(-1, 2, (k, n)) + 1j * rng.integers(-1, 2, (k, n))).astype(np.complex128)
+    ol = oracle.Lattice(dims, 0.15, synth.unit_links(dims))
+    U = 0.5 * np.stack([ol.gamma5(Z[i]) for i in range(k)])
+    # u_i = scale_i g5 z_i with scale_i = 1/2 exactly (a ratio of two inner products
+    # computed in complex arithmetic can come out one unit in the last place off)
+    Zp = np.zeros((kpad, n), dtype=np.complex128)
+    Zp[:k] = Z
+    D = L.DeviceDefl(k, pack(dims, Zp, kpad, 1), torch.arange(k, dtype=torch.int32, device="cuda"),
+                     dev_c128(np.full(k, 0.5)), None)
+    del Zp
+    gauge = torch.zeros(36 * V, dtype=L.complex_dtype(1), device="cuda")
+    dl = L.DeviceLattice(dims, 0.15, True, 1, gauge)
+    nz = L.Noise(17, 9, 1, 0)
+    zeta = torch.empty((k, N), dtype=torch.complex128, device="cuda")
+    omega = torch.empty_like(zeta)
+    ws = L.workspace(L.deflate_workspace_size(dl, D, N, rb))
+    L.deflate_project(dl, D, L.DEFL_COEFF, N, rb, None, nz, zeta, omega, None, None, ws)
+    zg, og = zeta.cpu().numpy(), omega.cpu().numpy()
+    del D, ws
+    for r in (0, 77, N - 1):
+        b = oracle.z4(17, 9, 1, r, 1, V)[0]
+        rz, ro = Z.conj() @ b, U.conj() @ b
+        print(f"r {r}: |zeta| up to {np.max(np.abs(rz)):.0f}, max |diff| {np.max(np.abs(zg[:, r] - rz)):.1e} / "
+              f"{np.max(np.abs(og[:, r] - ro)):.1e}")
+        assert np.array_equal(zg[:, r], rz) and np.array_equal(og[:, r], ro)
 
 
 def test_c3_double_polynomial_sampled_vs_oracle():
