@@ -81,6 +81,27 @@ def unit_links(dims) -> np.ndarray:
     return U
 
 
+def monomial_links(dims, seed: int) -> np.ndarray:
+    """SU(3) links that are permutation matrices with phases in {1, i, -1, -i}
+    (determinant 1).  Products with them only move and re-sign entries, so
+    operator applications to Gaussian-integer fields are exact in floating
+    point: inputs for bit-exact comparisons at full size."""
+    rng = np.random.default_rng(seed)
+    count = 4 * volume(dims)
+    perms = np.array([(0, 1, 2), (1, 2, 0), (2, 0, 1), (0, 2, 1), (2, 1, 0), (1, 0, 2)])
+    odd = np.array([0, 0, 0, 1, 1, 1])                       # the last three are transpositions
+    phase = np.array([1, 1j, -1, -1j], dtype=np.complex128)  # i^q, exactly
+    which = rng.integers(0, 6, count)
+    q = rng.integers(0, 4, (count, 3))
+    # det = sign(perm) i^(q0 + q1 + q2) = 1
+    q[:, 2] = (-q[:, 0] - q[:, 1] - 2 * odd[which]) % 4
+    U = np.zeros((count, 3, 3), dtype=np.complex128)
+    rows = np.arange(count)
+    for a in range(3):
+        U[rows, a, perms[which, a]] = phase[q[:, a]]
+    return U.reshape(4, -1, 3, 3)
+
+
 def random_su3(count: int, seed: int) -> np.ndarray:
     """`count` Haar-ish random SU(3) matrices (QR of a complex Gaussian,
     phases fixed, determinant divided out).  Used for gauge transformations."""

@@ -6,6 +6,14 @@
   own GMRES roots.  FP64 within max(1e-12, 4 d kappa_N u64) relative (the
   workload is near-critical, so the amplification kappa_N of the Newton
   recurrence is measured and reported); FP32 within 8 d kappa_N u32.
+* bit-exact, in the same launch configuration (8^4 x 256, rb = 16, FP64
+  t-sweep, two-row links) and on the 24^3 x 48 lattice (FP32 blocked t-sweep
+  and streaming kernel): with monomial SU(3) links (permutations with phases
+  in {1, i, -1, -i}), kappa = 1/8 and dyadic inverse roots every product and
+  sum of the Newton recurrence and of b^H w is exact in the kernels' and the
+  oracle's arithmetic, so the samples must equal the oracle's bit for bit --
+  an indexing, layout or spin-algebra mistake anywhere fails, whatever the
+  rounding.
 * the same level deflated as the workload runs it (k = 20 eigenvectors from
   the GPU set-up, FP64): the deflated samples b^H p150 b - b^H p30 b -
   sum_i c_i conj(zeta_i) omega_i of three vectors, with zeta = V^H b, the left
@@ -100,6 +108,68 @@ def test_c2_top_level_sampled_vs_oracle(c2, prec):
             err = abs(got - want) / abs(want)
             print(f"prec {prec} r {r} d {d}: rel err {err:.2e}, kappa_N {kN:.3g}, bound {bound:.2e}")
             assert err <= bound
+
+
+# dyadic inverse roots: with kappa = 1/8 every Newton step w - t A w of a
+# Gaussian-integer field is exact (few fraction bits per step)
+T_EXACT_HI = np.array([1.0, 0.5 + 0.5j, 0.5, 1.0, 0.5 - 0.5j])
+T_EXACT_LO = np.array([0.5, 1.0, 0.5 + 0.5j])
+
+
+def _exact_lattice(L, dims, prec, apbc, seed):
+    U = synth.monomial_links(dims, seed)
+    ol = oracle.Lattice(dims, 0.125, U, apbc)
+    V = int(np.prod(dims))
+    gauge = torch.empty(36 * V, dtype=L.complex_dtype(prec), device="cuda")
+    L.pack_gauge(dims, prec, torch.from_numpy(U).cuda(), gauge)
+    return ol, L.DeviceLattice(tuple(dims), 0.125, apbc, prec, gauge, 2)
+
+
+def test_c2_launch_bit_exact_with_monomial_links():
+    L = lib()
+    from synth.configs import C2
+    dims, N, rb, V = C2.dims, C2.levels[0].samples, 16, C2.volume
+    ol, dl = _exact_lattice(L, dims, 0, C2.antiperiodic_t, 5)
+    assert L.sweep_plan(dl, N, 1)["ok"]
+    lvl = L.DeviceLevel(L.OP_POLY, L.DevicePoly(dev_c128(T_EXACT_HI)), L.OP_POLY, L.DevicePoly(dev_c128(T_EXACT_LO)))
+    L.set_option(L.OPT_PLANE_SWEEP, 1)
+    samples = torch.empty((N, 6), dtype=torch.float64, device="cuda")
+    acc = torch.zeros(8, dtype=torch.float64, device="cuda")
+    ws = L.workspace(L.level_workspace_size(dl, lvl, N, rb))
+    L.mlmc_level_estimate(dl, lvl, N, rb, L.Noise(C2.seed_noise, C2.lattice_id, 0, 0), samples, acc, ws)
+    S = samples.cpu().numpy()
+    s, hi, lo = S[:, 0] + 1j * S[:, 1], S[:, 2] + 1j * S[:, 3], S[:, 4] + 1j * S[:, 5]
+    B = oracle.z4(C2.seed_noise, C2.lattice_id, 0, 0, N, V)
+    _, rh = ol.poly_apply(T_EXACT_HI, B)
+    _, rl = ol.poly_apply(T_EXACT_LO, B)
+    print("hi up to", np.max(np.abs(rh)), "mismatches", np.count_nonzero(hi != rh), np.count_nonzero(lo != rl))
+    assert np.array_equal(hi, rh) and np.array_equal(lo, rl) and np.array_equal(s, rh - rl)
+
+
+def test_c4_lattice_bit_exact_with_monomial_links():
+    L = lib()
+    from synth.configs import C4
+    dims, N, rb, V = C4.dims, 16, 1, C4.volume
+    ol, dl = _exact_lattice(L, dims, 1, C4.antiperiodic_t, 6)
+    assert L.sweep_plan(dl, N, rb)["halo"]
+    t = T_EXACT_HI[:4]
+    poly = L.DevicePoly(dev_c128(t))
+    ws = L.workspace(L.poly_workspace_size(dl, poly, N, rb))
+    nz = L.Noise(C4.seed_noise, C4.lattice_id, 3, 0)
+    out = {}
+    for opt in (1, 0):
+        L.set_option(L.OPT_PLANE_SWEEP, opt)
+        bhy = torch.empty(N, dtype=torch.complex128, device="cuda")
+        L.poly_apply(dl, poly, N, rb, None, nz, None, bhy, ws)
+        torch.cuda.synchronize()
+        out[opt] = bhy.cpu().numpy()
+    L.set_option(L.OPT_PLANE_SWEEP, 1)
+    assert np.array_equal(out[1], out[0])
+    for r in (0, N - 1):
+        b = oracle.z4(C4.seed_noise, C4.lattice_id, 3, r, 1, V)[0]
+        _, want = ol.poly_apply(t, b)
+        print(f"r {r}: {want[0]} sweep {out[1][r]} streaming {out[0][r]}")
+        assert out[1][r] == want[0]
 
 
 def test_c2_deflated_level_sampled_vs_oracle(c2):

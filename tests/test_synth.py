@@ -38,3 +38,14 @@ def test_tiled_operator_contains_the_base_spectrum():
     bs = (x % 2) + 2 * ((y % 2) + 2 * ((z % 2) + 2 * (t % 2)))
     zt = zb[bs].reshape(-1)
     assert np.linalg.norm(ot.apply(zt) - w[i] * zt) < 1e-10 * np.linalg.norm(zt)
+
+
+def test_monomial_links_are_su3_with_exact_row_two():
+    """Permutation-with-phases links: unitary, determinant 1, entries in
+    {0, 1, i, -1, -i}, and row 2 = conj(row 0 x row 1) holds exactly (the
+    two-row storage rebuilds them without rounding)."""
+    U = synth.monomial_links((4, 2, 3, 5), 3).reshape(-1, 3, 3)
+    assert np.allclose(np.linalg.det(U), 1.0, atol=1e-15)
+    assert np.array_equal(U @ U.conj().transpose(0, 2, 1), np.broadcast_to(np.eye(3), U.shape))
+    assert set(np.unique(U)) <= {0, 1, -1, 1j, -1j}
+    assert np.array_equal(np.conj(np.cross(U[:, 0, :], U[:, 1, :])), U[:, 2, :])
