@@ -46,7 +46,7 @@ import torch
 import oracle
 import synth
 from oracle import krylov, solve as osolve
-from gpu_helpers import dev_c128, lib, pack
+from gpu_helpers import dev_c128, lib, pack, unpack
 
 pytestmark = pytest.mark.gpu
 
@@ -170,6 +170,49 @@ def test_c4_lattice_bit_exact_with_monomial_links():
         _, want = ol.poly_apply(t, b)
         print(f"r {r}: {want[0]} sweep {out[1][r]} streaming {out[0][r]}")
         assert out[1][r] == want[0]
+
+
+def test_c2_double_polynomial_bit_exact_with_monomial_links():
+    """The double polynomial in scalar mode on the 8^4 x 256 launch: inner
+    chains on the FP64 t-sweep, the outer update on the streaming kernel."""
+    L = lib()
+    from synth.configs import C2
+    dims, N, rb, V = C2.dims, 256, 16, C2.volume
+    ol, dl = _exact_lattice(L, dims, 0, C2.antiperiodic_t, 8)
+    t_in, t_out = np.array([1.0, 0.5]), np.array([1.0, 0.5 + 0.5j])
+    poly = L.DevicePoly(dev_c128(t_in), dev_c128(t_out))
+    ws = L.workspace(L.poly_workspace_size(dl, poly, N, rb))
+    bhy = torch.empty(N, dtype=torch.complex128, device="cuda")
+    L.set_option(L.OPT_PLANE_SWEEP, 1)
+    L.poly_apply(dl, poly, N, rb, None, L.Noise(9, 2, 4, 0), None, bhy, ws)
+    got = bhy.cpu().numpy()
+    _, want = ol.composite_apply(t_in, t_out, oracle.z4(9, 2, 4, 0, N, V))
+    print("double polynomial: mismatches", np.count_nonzero(got != want), "of", N)
+    assert np.array_equal(got, want)
+
+
+def test_c3_vector_mode_bit_exact_with_monomial_links():
+    """y = p(A) b materialised (vector mode at block width 1, the top-level
+    solver's p_in) on the 16^3 x 32 lattice in FP32: the blocked t-sweep
+    accumulates y in the same launches; whole output vectors compared."""
+    L = lib()
+    from synth.configs import C3
+    dims, N, V = C3.dims, C3.levels[0].samples, C3.volume
+    ol, dl = _exact_lattice(L, dims, 1, C3.antiperiodic_t, 9)
+    assert L.sweep_plan(dl, N, 1)["halo"]
+    t = T_EXACT_HI[:4]
+    poly = L.DevicePoly(dev_c128(t))
+    ws = L.workspace(L.poly_workspace_size(dl, poly, N, 1))
+    y = L.empty_field(V, N, 1, 1)
+    L.set_option(L.OPT_PLANE_SWEEP, 1)
+    L.poly_apply(dl, poly, N, 1, None, L.Noise(21, 3, 0, 0), y, None, ws)
+    one = L.empty_field(V, 1, 1, 1)
+    for r in (0, N - 1):
+        L.field_copy_vector(dims, 1, y, r, one, 0)
+        got = unpack(dims, one, 1)[0]
+        want, _ = ol.poly_apply(t, oracle.z4(21, 3, 0, r, 1, V)[0])
+        print(f"vector mode r {r}: mismatches {np.count_nonzero(got != want)} of {got.size}")
+        assert np.array_equal(got, want)
 
 
 def test_c2_deflated_level_sampled_vs_oracle(c2):
