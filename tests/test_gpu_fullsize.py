@@ -215,6 +215,43 @@ def test_c3_vector_mode_bit_exact_with_monomial_links():
         assert np.array_equal(got, want)
 
 
+def test_c2_deflated_level_bit_exact_with_monomial_links():
+    """The deflated level kernel on the 8^4 x 256 launch: b^H p_hi b - b^H p_lo b
+    - sum_i c_i conj(zeta_i) omega_i with 20 Gaussian-integer vectors in the
+    place of eigenvectors (k padded to 32, as the workload runs it), left
+    vectors g5 z / 2 and dyadic c: every sample equals the oracle's exactly."""
+    L = lib()
+    from oracle import estimator
+    from synth.configs import C2
+    dims, N, rb, V = C2.dims, C2.levels[0].samples, 16, C2.volume
+    n, k, kpad = 12 * V, 20, 32
+    ol, dl = _exact_lattice(L, dims, 0, C2.antiperiodic_t, 10)
+    rng = np.random.default_rng(12)
+    Z = (rng.integers(-1, 2, (k, n)) + 1j * rng.integers(-1, 2, (k, n))).astype(np.complex128)
+    Uv = 0.5 * np.stack([ol.gamma5(Z[i]) for i in range(k)])
+    Zp = np.zeros((kpad, n), dtype=np.complex128)
+    Zp[:k] = Z
+    D = L.DeviceDefl(k, pack(dims, Zp, kpad, 0), torch.arange(k, dtype=torch.int32, device="cuda"),
+                     dev_c128(np.full(k, 0.5)), None)
+    c = (rng.integers(-4, 5, k) + 1j * rng.integers(-4, 5, k)) / 8.0
+    lvl = L.DeviceLevel(L.OP_POLY, L.DevicePoly(dev_c128(T_EXACT_HI)), L.OP_POLY, L.DevicePoly(dev_c128(T_EXACT_LO)),
+                        D, True, dev_c128(c))
+    L.set_option(L.OPT_PLANE_SWEEP, 1)
+    samples = torch.empty((N, 6), dtype=torch.float64, device="cuda")
+    acc = torch.zeros(8, dtype=torch.float64, device="cuda")
+    ws = L.workspace(L.level_workspace_size(dl, lvl, N, rb))
+    L.mlmc_level_estimate(dl, lvl, N, rb, L.Noise(C2.seed_noise, C2.lattice_id, 1, 0), samples, acc, ws)
+    S = samples.cpu().numpy()
+    got = S[:, 0] + 1j * S[:, 1]
+    B = oracle.z4(C2.seed_noise, C2.lattice_id, 1, 0, N, V)
+    _, rh = ol.poly_apply(T_EXACT_HI, B)
+    _, rl = ol.poly_apply(T_EXACT_LO, B)
+    zeta, omega = Z.conj() @ B.T, Uv.conj() @ B.T
+    want = estimator.level_samples(rh, rl, zeta, omega, c)
+    print("deflated level: mismatches", np.count_nonzero(got != want), "of", N)
+    assert np.array_equal(got, want)
+
+
 def test_c2_deflated_level_sampled_vs_oracle(c2):
     L = lib()
     from paper_2306_09559_amd import driver
