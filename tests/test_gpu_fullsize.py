@@ -252,6 +252,26 @@ def test_c2_deflated_level_bit_exact_with_monomial_links():
     assert np.array_equal(got, want)
 
 
+def test_c2_probing_bit_exact_with_monomial_links():
+    """Tr p(A) by probing on the 8^4 lattice (degree 4: a distance-4
+    colouring, probe vectors generated inside the FP64 t-sweep, 256 per
+    launch): the trace equals the oracle's probe sum over the same colouring
+    exactly."""
+    L = lib()
+    from paper_2306_09559_amd import probing
+    from oracle import probing as oprobe
+    from synth.configs import C2
+    dims = C2.dims
+    ol, dl = _exact_lattice(L, dims, 0, C2.antiperiodic_t, 11)
+    t = T_EXACT_HI
+    d = len(t) - 1
+    col = probing.colouring(dims, d)
+    res = probing.probe_trace(dl, L.DevicePoly(dev_c128(t)), col, nrhs=256, rb=1, in_kernel=True)
+    want = oprobe.probe_trace(ol, t, col.astype(np.int64))
+    print(f"probing: {res.ncolours} colours, {res.probes} probes, trace {res.trace} oracle {want}")
+    assert res.trace == want
+
+
 def test_c2_deflated_level_sampled_vs_oracle(c2):
     L = lib()
     from paper_2306_09559_amd import driver
