@@ -125,13 +125,18 @@ def _exact_lattice(L, dims, prec, apbc, seed):
     return ol, L.DeviceLattice(tuple(dims), 0.125, apbc, prec, gauge, 2)
 
 
-def test_c2_launch_bit_exact_with_monomial_links():
+@pytest.mark.parametrize("prec", [0, 1])
+def test_c2_launch_bit_exact_with_monomial_links(prec):
+    """FP64 (the bench's level kernel) and FP32 (its mixed-precision run, the
+    whole-plane sweep with the link prefetch; degree 3 so that every FP32
+    entry stays within 24 bits)."""
     L = lib()
     from synth.configs import C2
     dims, N, rb, V = C2.dims, C2.levels[0].samples, 16, C2.volume
-    ol, dl = _exact_lattice(L, dims, 0, C2.antiperiodic_t, 5)
+    ol, dl = _exact_lattice(L, dims, prec, C2.antiperiodic_t, 5)
     assert L.sweep_plan(dl, N, 1)["ok"]
-    lvl = L.DeviceLevel(L.OP_POLY, L.DevicePoly(dev_c128(T_EXACT_HI)), L.OP_POLY, L.DevicePoly(dev_c128(T_EXACT_LO)))
+    t_hi = T_EXACT_HI if prec == 0 else T_EXACT_HI[:4]
+    lvl = L.DeviceLevel(L.OP_POLY, L.DevicePoly(dev_c128(t_hi)), L.OP_POLY, L.DevicePoly(dev_c128(T_EXACT_LO)))
     L.set_option(L.OPT_PLANE_SWEEP, 1)
     samples = torch.empty((N, 6), dtype=torch.float64, device="cuda")
     acc = torch.zeros(8, dtype=torch.float64, device="cuda")
@@ -140,9 +145,9 @@ def test_c2_launch_bit_exact_with_monomial_links():
     S = samples.cpu().numpy()
     s, hi, lo = S[:, 0] + 1j * S[:, 1], S[:, 2] + 1j * S[:, 3], S[:, 4] + 1j * S[:, 5]
     B = oracle.z4(C2.seed_noise, C2.lattice_id, 0, 0, N, V)
-    _, rh = ol.poly_apply(T_EXACT_HI, B)
+    _, rh = ol.poly_apply(t_hi, B)
     _, rl = ol.poly_apply(T_EXACT_LO, B)
-    print("hi up to", np.max(np.abs(rh)), "mismatches", np.count_nonzero(hi != rh), np.count_nonzero(lo != rl))
+    print("prec", prec, "hi up to", np.max(np.abs(rh)), "mismatches", np.count_nonzero(hi != rh), np.count_nonzero(lo != rl))
     assert np.array_equal(hi, rh) and np.array_equal(lo, rl) and np.array_equal(s, rh - rl)
 
 
