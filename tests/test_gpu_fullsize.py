@@ -277,6 +277,27 @@ def test_c2_probing_bit_exact_with_monomial_links():
     assert res.trace == want
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_c4_lattice_operator_bit_exact_with_monomial_links(prec):
+    """A x through mpmc_wilson_apply (the streaming kernel) on the 24^3 x 48
+    lattice, 16 Z4 vectors at block width 16: whole output vectors equal the
+    oracle's entry for entry."""
+    L = lib()
+    from synth.configs import C4
+    dims, N, rb, V = C4.dims, 16, 16, C4.volume
+    ol, dl = _exact_lattice(L, dims, prec, C4.antiperiodic_t, 12)
+    x = L.empty_field(V, N, rb, prec)
+    L.z4_fill(dims, prec, L.Noise(31, 4, 0, 0), x)
+    y = L.empty_field(V, N, rb, prec)
+    L.wilson_apply(dl, x, y)
+    one = L.empty_field(V, 1, 1, prec)
+    for r in (0, 9, N - 1):
+        L.field_copy_vector(dims, prec, y, r, one, 0)
+        got = unpack(dims, one, prec)[0]
+        want = ol.apply(oracle.z4(31, 4, 0, r, 1, V)[0])
+        assert np.array_equal(got, want), (r, np.count_nonzero(got != want))
+
+
 def test_c2_deflated_level_sampled_vs_oracle(c2):
     L = lib()
     from paper_2306_09559_amd import driver
