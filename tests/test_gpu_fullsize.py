@@ -411,6 +411,49 @@ def test_c4_size_deflation_coefficients_exact():
         assert np.array_equal(zg[:, r], rz) and np.array_equal(og[:, r], ro)
 
 
+def test_c4_size_reconstruction_and_projection_exact():
+    """X = V d (RECON) and the Left-right Projection X = b - A V H^{-1} U^H b
+    (PROJECT) on the 24^3 x 48 lattice in FP32 (k = 20 padded to 32, 16
+    vectors): Gaussian-integer vectors, dyadic d and H^{-1}, monomial links
+    and kappa = 1/8 keep every step exact, so sampled output vectors equal the
+    oracle's entry for entry."""
+    L = lib()
+    from synth.configs import C4
+    dims, V = C4.dims, C4.volume
+    n, k, kpad, N, rb = 12 * V, 20, 32, 16, 16
+    ol, dl = _exact_lattice(L, dims, 1, C4.antiperiodic_t, 13)
+    rng = np.random.default_rng(14)
+    Z = (rng.integers(-1, 2, (k, n)) + 1j * rng.integers(-1, 2, (k, n))).astype(np.complex128)
+    Uv = 0.5 * np.stack([ol.gamma5(Z[i]) for i in range(k)])
+    hinv = (rng.integers(-2, 3, (k, k)) + 1j * rng.integers(-2, 3, (k, k))) / 4.0
+    Zp = np.zeros((kpad, n), dtype=np.complex128)
+    Zp[:k] = Z
+    D = L.DeviceDefl(k, pack(dims, Zp, kpad, 1), torch.arange(k, dtype=torch.int32, device="cuda"),
+                     dev_c128(np.full(k, 0.5)), dev_c128(hinv))
+    del Zp
+    ws = L.workspace(L.deflate_workspace_size(dl, D, N, rb))
+    X = L.empty_field(V, N, rb, 1)
+    one = L.empty_field(V, 1, 1, 1)
+    d = (rng.integers(-8, 9, (k, N)) + 1j * rng.integers(-8, 9, (k, N))) / 8.0
+    L.deflate_project(dl, D, L.DEFL_RECON, N, rb, None, None, None, None, dev_c128(d), X, ws)
+    for r in (0, N - 1):
+        L.field_copy_vector(dims, 1, X, r, one, 0)
+        assert np.array_equal(unpack(dims, one, 1)[0], Z.T @ d[:, r]), ("recon", r)
+    nz = L.Noise(41, 4, 2, 0)
+    dd = torch.empty((k, N), dtype=torch.complex128, device="cuda")
+    L.deflate_project(dl, D, L.DEFL_PROJECT, N, rb, None, nz, None, None, dd, X, ws)
+    ddh = dd.cpu().numpy()
+    for r in (0, N - 1):
+        b = oracle.z4(41, 4, 2, r, 1, V)[0]
+        dr = hinv @ (Uv.conj() @ b)
+        assert np.array_equal(ddh[:, r], dr), ("d", r)
+        L.field_copy_vector(dims, 1, X, r, one, 0)
+        want = b - ol.apply(Z.T @ dr)
+        got = unpack(dims, one, 1)[0]
+        print(f"projection r {r}: mismatches {np.count_nonzero(got != want)} of {got.size}")
+        assert np.array_equal(got, want)
+
+
 def test_c3_double_polynomial_sampled_vs_oracle():
     L = lib()
     from paper_2306_09559_amd import driver
