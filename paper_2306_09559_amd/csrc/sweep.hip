@@ -322,6 +322,35 @@ __device__ __forceinline__ void plane_hop_u(const cplx_t<T> *lds, int P, int q, 
     }
 }
 
+// FP32 whole planes: the backward-hop product U_mu(x)^H (1 + g_mu) w(x) of
+// this site's own link, left in LDS (bwl[(mu * 6 + 3 sp + a) * Pb + q]) for
+// the neighbour x + mu
+template <typename T, int MU>
+__device__ __forceinline__ void own_backward(const cplx_t<T> (&w)[12], const cplx_t<T> (&U)[9], cplx_t<T> *bwl,
+                                             int Pb, int q) {
+    cplx_t<T> h[2][3];
+    proj<T, MU, false>(w, h);
+    mul_link<T, true>(U, h);
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) bwl[(MU * 6 + sp * 3 + a) * Pb + q] = h[sp][a];
+}
+
+// the forward hop with this site's link U_mu(x), then the backward hop
+// from the product the neighbour x - mu (LDS slot qb) left
+template <typename T, int MU>
+__device__ __forceinline__ void own_hops(const cplx_t<T> *lds, int Sl, int qf, int qb, const cplx_t<T> (&U)[9],
+                                         const cplx_t<T> *bwl, int Pb, cplx_t<T> (&acc)[12]) {
+    plane_hop_u<T, MU, true>(lds, Sl, qf, U, acc);
+    cplx_t<T> g[2][3];
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) g[sp][a] = bwl[(MU * 6 + sp * 3 + a) * Pb + qb];
+    recon<T, MU, false>(g, acc);
+}
+
 __device__ __forceinline__ double2 zmul2(double2 a, double2 b) {
     double2 r;
     r.x = a.x * b.x - a.y * b.y;
@@ -446,6 +475,12 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
     // colour-rotated half spinor (1 + g_t) U_t^H psi, sign included), which
     // keeps it out of the registers during the hops.
     C *stl = lds + 12 * Sl;
+    // FP32 whole planes: every site forms the backward-hop products of its own
+    // x-, y- and z-links, U_mu(x)^H (1 + g_mu) w(x), and leaves them in LDS
+    // for its neighbours x + mu; links are read as three rows (no rebuild)
+    constexpr bool OWN = sizeof(T) == 4 && !HALO && !FIRST;
+    constexpr bool TWOL = OWN ? false : TWO;
+    C *bwl = stl + 6 * Pb;
     // prologue: -t term of plane 0 from plane Lt-1; cur (and halo) = plane 0
     C stash[2][3];
     {
@@ -469,7 +504,7 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
     // 8^4 x 256 vectors FP64, with the hops unrolled: 112 -> 106 us per launch;
     // at 64 vectors 83 -> 75 us).
     C Ust[9];
-    link_raw<T, TWO>(gt, estride, gq, Ust);
+    link_raw<T, TWOL>(gt, estride, gq, Ust);
     C cur[12];
     load_plane_site<T, PROBE>(inp, IN_Z4, S, gq, cur);
     C hcur[12];
@@ -516,7 +551,7 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
         // the -t term of (x, t+1): (1 + g_t) U_t(x, t)^H w(x, t)
         {
             C st[2][3];
-            link_complete<T, TWO>(Ust);
+            link_complete<T, TWOL>(Ust);
             proj<T, 3, false>(cur, st);
             mul_link<T, true>(Ust, st);
 #pragma unroll
@@ -538,8 +573,19 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
         // the first spatial hop's link, then the +t plane (plane 0 again after
         // the last one) and its halo
         C U0[9];
-        link_raw<T, TWO>(gx, estride, s, U0);
+        link_raw<T, TWOL>(gx, estride, s, U0);
+        C Uy[OWN ? 9 : 1], Uz[OWN ? 9 : 1];
+        if constexpr (OWN) {
+            link_raw<T, false>(gy, estride, s, Uy);
+            link_raw<T, false>(gz, estride, s, Uz);
+        }
         __builtin_amdgcn_sched_barrier(0);
+        if constexpr (OWN) {
+            own_backward<T, 0>(cur, U0, bwl, Pb, q);
+            own_backward<T, 1>(cur, Uy, bwl, Pb, q);
+            own_backward<T, 2>(cur, Uz, bwl, Pb, q);
+            __builtin_amdgcn_sched_barrier(0);
+        }
         const int tn = t + 1 == Lt ? 0 : t + 1;
         C nxt[12];
         load_plane_site<T, PROBE>(inp, IN_Z4, S, gq + tn * P, nxt);
@@ -549,7 +595,25 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
         }
         __syncthreads();
 
-        if constexpr (sizeof(T) == 4 && !FIRST) {
+        if constexpr (OWN) {
+            // forward hops with this site's links; backward hops read the
+            // products the neighbours x - mu left in LDS
+            own_hops<T, 0>(lds, Sl, sxp, sxm, U0, bwl, Pb, acc);
+            __builtin_amdgcn_sched_barrier(0);
+            own_hops<T, 1>(lds, Sl, syp, sym, Uy, bwl, Pb, acc);
+            __builtin_amdgcn_sched_barrier(0);
+            own_hops<T, 2>(lds, Sl, szp, szm, Uz, bwl, Pb, acc);
+            __builtin_amdgcn_sched_barrier(0);
+            // +t hop: (1 - g_t) U_t(x, t) w(x, t+1), the stash's link
+            C h[2][3];
+            proj<T, 3, true>(nxt, h);
+            mul_link<T, false>(Ust, h);
+#pragma unroll
+            for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+                for (int aa = 0; aa < 3; ++aa) h[sp][aa] = mk<T>(sg * h[sp][aa].x, sg * h[sp][aa].y);
+            recon<T, 3, true>(h, acc);
+        } else if constexpr (sizeof(T) == 4 && !FIRST) {
             // FP32 after the first step: the link of each hop is loaded one hop
             // ahead (the +t link during the -z hop), a (+mu, -mu) pair per
             // rolled iteration.  This kernel has the registers for the second
@@ -634,7 +698,7 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
         }
         // the next step's -t link ahead of the stores (the site clamped on the
         // last step: a conditional load here made the compiler spill)
-        link_raw<T, TWO>(gt, estride, t + 1 < Lt ? s + P : s, Ust);
+        link_raw<T, TWOL>(gt, estride, t + 1 < Lt ? s + P : s, Ust);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
@@ -740,14 +804,15 @@ SweepPlan sweep_plan(const mpmc_lattice &lat, mpmc_shape sh) {
         return p;
     const size_t min_threads = (size_t)cus[dev] * 512;
     p.fills = (size_t)sh.nrhs * (size_t)P >= min_threads;
-    if (P >= 64 && P <= 512 && P % 64 == 0 && 18 * (size_t)P * csz <= kLds) {
+    const size_t whole = (lat.prec == MPMC_F32 ? 36 : 18) * (size_t)P * csz;
+    if (P >= 64 && P <= 512 && P % 64 == 0 && whole <= kLds) {
         // the whole xyz-plane in one workgroup (neighbours wrap inside it)
         p.ok = true;
         p.B[0] = Lx;
         p.B[1] = Ly;
         p.B[2] = Lz;
         p.Pb = P;
-        p.lds = 18 * (size_t)P * csz;
+        p.lds = whole;
         return p;
     }
     if (lat.prec != MPMC_F32) return p;                        // FP64 blocks + halo exceed the registers
