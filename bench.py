@@ -21,6 +21,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -294,8 +295,9 @@ def top_level_c3(cfg=None):
                       "rtolle": prm["solve_tol"]},
             "estimate": [round(e["estimate"].real, 4), round(e["estimate"].imag, 4)], "stderr": round(e["stderr"], 4),
             "sample_variance": round(var, 2), "target_stderr": round(target, 3),
-            # time for this level alone to reach its share eps/sqrt(3) of eps = 0.0005 V
-            "seconds_to_target": round(var / target ** 2 * dt / N, 3)}
+            # time for this level alone to reach its share eps/sqrt(3) of eps = 0.0005 V: the samples
+            # that variance needs, and at least the two the first check is taken at (Sec. 5 step 3a)
+            "seconds_to_target": round(max(2, math.ceil(var / target ** 2)) * dt / N, 3)}
 
 
 def c4_step():
