@@ -159,14 +159,18 @@ def _key(run: LatticeRun, level: int) -> str:
 
 
 def _candidates(run: LatticeRun, level: int) -> List[Tuple[int, bool]]:
+    """(rb, sweep) shapes to time for one level: every block width dividing
+    the batch on the streaming kernel, and on the t-sweep wherever the
+    library's plan takes it (whole planes, or FP32 blocks with a halo); the
+    level's current shape is always among them."""
     N = run.levels[level].batch
     rbs = [rb for rb in (1, 2, 4, 8, 16, 32) if N % rb == 0]
-    P = run.cfg.dims[0] * run.cfg.dims[1] * run.cfg.dims[2]
-    csz = 16 if run.prec == L.F64 else 8
-    sweep_ok = 64 <= P <= 512 and P % 64 == 0 and P * 18 * csz <= 160 * 1024
     out = [(rb, False) for rb in rbs]
-    if sweep_ok:
-        out += [(rb, True) for rb in rbs if rb >= 8]      # the sweep reads the noise, rb only shapes the first step
+    # the sweep reads the noise itself: rb only shapes the first step's input, so wide blocks suffice
+    out += [(rb, True) for rb in rbs if rb >= 8 and L.sweep_plan(run.dl, N, rb)["ok"]]
+    current = (run.level_rb(level), bool(run.levels[level].sweep))
+    if current not in out:
+        out.append(current)
     return out
 
 

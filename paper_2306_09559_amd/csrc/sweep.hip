@@ -204,17 +204,10 @@ __device__ __forceinline__ void proj_lds(const cplx_t<T> *lds, int P, int q, cpl
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const cplx_t<T> p0 = lds[a * P + q], pk = lds[(3 * k0 + a) * P + q];
-        cplx_t<T> v[12];
-        v[a] = p0;
-        v[3 * k0 + a] = pk;
-        cplx_t<T> hh[2][3];
-        // only h[0][a] is formed from this pair
-        if (MU == 0) hh[0][a] = FWD ? cadd<T>(p0, mul_mi<T>(pk)) : cadd<T>(p0, mul_i<T>(pk));
-        else if (MU == 1) hh[0][a] = FWD ? cadd<T>(p0, pk) : csub<T>(p0, pk);
-        else if (MU == 2) hh[0][a] = FWD ? cadd<T>(p0, mul_mi<T>(pk)) : cadd<T>(p0, mul_i<T>(pk));
-        else hh[0][a] = FWD ? csub<T>(p0, pk) : cadd<T>(p0, pk);
-        h[0][a] = hh[0][a];
-        (void)v;
+        if (MU == 0) h[0][a] = FWD ? cadd<T>(p0, mul_mi<T>(pk)) : cadd<T>(p0, mul_i<T>(pk));
+        else if (MU == 1) h[0][a] = FWD ? cadd<T>(p0, pk) : csub<T>(p0, pk);
+        else if (MU == 2) h[0][a] = FWD ? cadd<T>(p0, mul_mi<T>(pk)) : cadd<T>(p0, mul_i<T>(pk));
+        else h[0][a] = FWD ? csub<T>(p0, pk) : cadd<T>(p0, pk);
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -368,6 +361,100 @@ __device__ __forceinline__ void dot_acc(const cplx_t<T> (&b)[12], const cplx_t<T
     }
 }
 
+// The scalar-mode dot of one launch: t_{j+1} b^H w_{j+1} (+ t_j b^H w_j on the
+// first step) from each thread's FP64 partial, summed over the block in a
+// fixed-order tree (LDS plane buffer reused) and added to the vector's (or
+// block's) running partial.
+template <typename T, bool FIRST, bool HALO>
+__device__ __forceinline__ void sweep_dot_finish(const SweepArgs<T> &a, int r, int blk, int q, int Pb, double2 tj,
+                                                 double dre, double dim, double d0re, double d0im,
+                                                 unsigned char *smem) {
+    double2 *red = reinterpret_cast<double2 *>(smem);
+    double2 v = zmul2(a.troots[a.j + 1], make_double2(dre, dim));
+    if (FIRST) {
+        const double2 v0 = zmul2(tj, make_double2(d0re, d0im));
+        v.x += v0.x;
+        v.y += v0.y;
+    }
+    red[q] = v;
+    __syncthreads();
+    int n = Pb;
+    while (n > 1) {
+        const int h = (n + 1) >> 1;
+        if (q < n - h) {
+            red[q].x += red[q + h].x;
+            red[q].y += red[q + h].y;
+        }
+        __syncthreads();
+        n = h;
+    }
+    if (q == 0) {
+        // one partial per (vector, block); whole-plane blocks also write b^H y at the end
+        const size_t pi = HALO ? (size_t)r * (size_t)a.nbp + (size_t)blk : (size_t)r;
+        double2 tot = red[0];
+        if (!FIRST) {
+            tot.x += a.part[pi].x;
+            tot.y += a.part[pi].y;
+        }
+        a.part[pi] = tot;
+        if (!HALO && a.bhy) a.bhy[r] = tot;
+    }
+}
+
+// A step with kappa t_j = 0 (kappa = 0, i.e. A = I, or an inverse root 0):
+// w_{j+1} = (1 - t_j) w_j involves no hop.  The main path forms
+// kappa t_j ((1 - t_j) / (kappa t_j) w + D w), which does not exist here, so
+// such a launch takes this separate path at entry: each thread scales its own
+// sites plane by plane, with the same dot, vector-mode update and reduction.
+// Taken at entry, its registers are not live in the main loop (folded into
+// the step's epilogue instead, the same update cost 2% per FP64 launch at
+// 8^4 x 256 vectors; as an out-of-line call it made every variant spill).
+template <typename T, bool IN_Z4, bool DOT, bool FIRST, bool BFIELD, bool HALO, bool YACC, bool PROBE>
+__device__ __forceinline__ void sweep_step_no_hop(const SweepArgs<T> &a, int r, int blk, int q, int Pb, int gq,
+                                               NoiseSrc S, unsigned char *smem) {
+    using C = cplx_t<T>;
+    const int P = a.P, Lt = a.L[3];
+    const double2 tj = a.troots[a.j];
+    const double2 alpha = make_double2(1.0 - tj.x, -tj.y);
+    const Plane<T> inp = plane_of<T>(a.in, r, a.V, a.rb_in);
+    const Plane<T> outp = plane_of<T>(a.out, r, a.V, 1);
+    double dre = 0.0, dim = 0.0, d0re = 0.0, d0im = 0.0;
+    for (int t = 0; t < Lt; ++t) {
+        const int s = gq + t * P;
+        C w[12], o[12];
+        load_plane_site<T, PROBE>(inp, IN_Z4, S, s, w);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            o[c] = cmul_d<T>(alpha, w[c]);
+            outp.st(c, s, o[c]);
+        }
+        if (DOT) {
+            C b[12];
+            if (!BFIELD) {
+                noise_site<T, PROBE>(S, s, b);
+            } else {
+                const Plane<T> bp = plane_of<T>(a.bvec, r, a.V, a.rb_b);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) b[c] = bp.ld(c, s);
+            }
+            if (FIRST) dot_acc<T>(b, w, d0re, d0im);
+            dot_acc<T>(b, o, dre, dim);
+        }
+        if constexpr (YACC) {
+            const Plane<T> yp = plane_of<T>(a.y, r, a.V, 1);
+            const double2 tn = a.y_last ? a.troots[a.j + 1] : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                C yv = a.y_first ? mk<T>(T(0), T(0)) : yp.ld(c, s);
+                yv = axpy_d<T>(tj, w[c], yv);
+                if (a.y_last) yv = axpy_d<T>(tn, o[c], yv);
+                yp.st(c, s, yv);
+            }
+        }
+    }
+    if (DOT) sweep_dot_finish<T, FIRST, HALO>(a, r, blk, q, Pb, tj, dre, dim, d0re, d0im, smem);
+}
+
 }  // namespace
 
 // IN_Z4: the input is the noise itself; FIRST: also accumulate t_0 b^H w
@@ -468,6 +555,10 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
     const double2 beta = make_double2(a.kappa * tj.x, a.kappa * tj.y);   // kappa t_j
     const uint64_t g = sample_base(a.first, a.off) + (uint64_t)r;      // global sample (or probe) index
     const NoiseSrc S{PROBE ? 0ull : sample_state(a.key, g), a.colour, (long long)(g / 12u), (int)(g % 12u)};
+    if (a.kappa * (tj.x * tj.x + tj.y * tj.y) == 0.0) {   // kappa t_j = 0 (uniform over the launch)
+        sweep_step_no_hop<T, IN_Z4, DOT, FIRST, BFIELD, HALO, YACC, PROBE>(a, r, blk, q, Pb, gq, S, smem);
+        return;
+    }
     const Plane<T> inp = plane_of<T>(a.in, r, a.V, a.rb_in);
     const Plane<T> outp = plane_of<T>(a.out, r, a.V, 1);
 
@@ -519,7 +610,7 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
 
     // out = alpha w + beta D w is formed as beta * ((alpha/beta) w + D w): the
     // current spinor then enters the accumulator at the start of the step and
-    // is dead during the hops (beta = kappa t_j is never 0 for finite roots)
+    // is dead during the hops (beta = kappa t_j = 0 took the path above)
     double2 aob;
     {
         // (1 - t) / (kappa t) = (1 - t) conj(t) / (kappa |t|^2)
@@ -745,39 +836,7 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
         }
     }
 
-    if (DOT) {
-        // fixed-order tree over the block's threads (LDS plane buffer reused)
-        double2 *red = reinterpret_cast<double2 *>(smem);
-        double2 v = zmul2(a.troots[a.j + 1], make_double2(dre, dim));
-        if (FIRST) {
-            const double2 v0 = zmul2(tj, make_double2(d0re, d0im));
-            v.x += v0.x;
-            v.y += v0.y;
-        }
-        red[q] = v;
-        __syncthreads();
-        int n = Pb;
-        while (n > 1) {
-            const int h = (n + 1) >> 1;
-            if (q < n - h) {
-                red[q].x += red[q + h].x;
-                red[q].y += red[q + h].y;
-            }
-            __syncthreads();
-            n = h;
-        }
-        if (q == 0) {
-            // one partial per (vector, block); whole-plane blocks also write b^H y at the end
-            const size_t pi = HALO ? (size_t)r * (size_t)a.nbp + (size_t)blk : (size_t)r;
-            double2 tot = red[0];
-            if (!FIRST) {
-                tot.x += a.part[pi].x;
-                tot.y += a.part[pi].y;
-            }
-            a.part[pi] = tot;
-            if (!HALO && a.bhy) a.bhy[r] = tot;
-        }
-    }
+    if (DOT) sweep_dot_finish<T, FIRST, HALO>(a, r, blk, q, Pb, tj, dre, dim, d0re, d0im, smem);
 }
 
 // b^H y of a blocked sweep: the blocks' partials of each vector in a fixed order

@@ -221,6 +221,45 @@ def gmres_roots(dl: L.DeviceLattice, degrees: Sequence[int], start: np.ndarray) 
     return RootSet(inv, dev, res)
 
 
+def select_eigenvalues(lam: np.ndarray, right_res: np.ndarray, left_res: Callable[[int, int], float],
+                       imaglim: float, evectol: float, kmax: int):
+    """The selection walk of Sec. 4 over candidates sorted by |lambda|.
+
+    A value with |Im lambda| < imaglim is taken as real: accepted when its
+    right residual ||A z - lambda z|| and the left residual of u = g5 z are
+    both below evectol.  Otherwise, when the next value lies within imaglim of
+    conj(lambda), the two are a conjugate pair whose left vectors are g5 of
+    the partner's right vector: both are accepted when all four residuals are
+    below evectol.  Any other value is skipped.  At most kmax values are
+    accepted (a pair only as a whole).
+
+    right_res[i] is the right residual of candidate i; left_res(i, src) the
+    residual ||A^H u - conj(lambda_i) u|| of the unit vector u = g5 z_src.
+    Returns the accepted candidate indices, each one's partner index (itself
+    for a real value), and their right and left residuals."""
+    acc: List[int] = []
+    pair: List[int] = []
+    rrs: List[float] = []
+    rls: List[float] = []
+    i, k = 0, len(lam)
+    while i < k and len(acc) < kmax:
+        l = lam[i]
+        if abs(l.imag) < imaglim:
+            if right_res[i] < evectol and left_res(i, i) < evectol:
+                acc.append(i); pair.append(i); rrs.append(float(right_res[i])); rls.append(left_res(i, i))
+            i += 1
+        elif i + 1 < k and abs(lam[i + 1] - np.conj(l)) < imaglim:
+            if len(acc) + 2 <= kmax:
+                r1, r2 = float(right_res[i]), float(right_res[i + 1])
+                b1, b2 = left_res(i, i + 1), left_res(i + 1, i)
+                if max(r1, r2, b1, b2) < evectol:
+                    acc += [i, i + 1]; pair += [i + 1, i]; rrs += [r1, r2]; rls += [b1, b2]
+            i += 2
+        else:
+            i += 1
+    return acc, pair, rrs, rls
+
+
 @dataclass
 class Deflation:
     device: L.DeviceDefl
@@ -231,11 +270,12 @@ class Deflation:
     candidates: int
     arnoldi_steps: int = 0       # PP-Arnoldi steps taken
     arnoldi_residual: float = float("nan")   # PP-GMRES relative residual on that basis
+    ritz: Optional[dict] = None  # with keep_candidates: the Ritz pairs the selection walked
 
 
 def pp_arnoldi_deflation(dl: L.DeviceLattice, pin: L.DevicePoly, start: np.ndarray, m: int, nev: int,
                          kmax: int, imaglim: float = 2e-4, evectol: float = 1e-3,
-                         rtolev: Optional[float] = None) -> Deflation:
+                         rtolev: Optional[float] = None, keep_candidates: bool = False) -> Deflation:
     """Setup step 2(b): PP-Arnoldi, Ritz pairs nearest the origin, selection.
     The Arnoldi run takes m steps, or stops earlier once the relative residual
     of the PP-GMRES solution of B y = start on the same basis is at most
@@ -290,13 +330,6 @@ def pp_arnoldi_deflation(dl: L.DeviceLattice, pin: L.DevicePoly, start: np.ndarr
 
     lam_s = lam_all[order]
     rr_all = resid(lam_s, order)
-    # selection walk (enumerated algorithm of Sec. 4)
-    acc: List[int] = []
-    pair: List[int] = []
-    rrs: List[float] = []
-    rls: List[float] = []
-    i = 0
-    k = len(order)
     left_cache: Dict[tuple, float] = {}
 
     def left_res(a: int, src: int) -> float:
@@ -306,21 +339,7 @@ def pp_arnoldi_deflation(dl: L.DeviceLattice, pin: L.DevicePoly, start: np.ndarr
             left_cache[key] = float(resid(np.array([np.conj(lam_s[a])]), np.array([order[src]]))[0])
         return left_cache[key]
 
-    while i < k and len(acc) < kmax:
-        l = lam_s[i]
-        if abs(l.imag) < imaglim:
-            if rr_all[i] < evectol and left_res(i, i) < evectol:
-                acc.append(i); pair.append(i); rrs.append(rr_all[i]); rls.append(left_res(i, i))
-            i += 1
-        elif i + 1 < k and abs(lam_s[i + 1] - np.conj(l)) < imaglim:
-            if len(acc) + 2 <= kmax:
-                r1, r2 = rr_all[i], rr_all[i + 1]
-                b1, b2 = left_res(i, i + 1), left_res(i + 1, i)
-                if max(r1, r2, b1, b2) < evectol:
-                    acc += [i, i + 1]; pair += [i + 1, i]; rrs += [r1, r2]; rls += [b1, b2]
-            i += 2
-        else:
-            i += 1
+    acc, pair, rrs, rls = select_eigenvalues(lam_s, rr_all, left_res, imaglim, evectol, kmax)
     if not acc:
         raise RuntimeError("no eigenvalue passed the deflation selection")
     arnoldi_steps = mm
@@ -350,8 +369,12 @@ def pp_arnoldi_deflation(dl: L.DeviceLattice, pin: L.DevicePoly, start: np.ndarr
     Hm = UAV.cpu().numpy()[:, :ka]
     defl.hinv = _c(np.linalg.inv(Hm))
     torch.cuda.synchronize()
-    return Deflation(defl, lam, pr, np.array(rrs), np.array(rls), k, arnoldi_steps,
-                     gmres_residual(H, beta, mm) / beta)
+    ritz = None
+    if keep_candidates:
+        # lam: candidates in walk order; Z: unit Ritz vectors (batch of width kp), candidate i at column order[i]
+        ritz = dict(lam=lam_s, Z=Zb, order=order, right_res=rr_all)
+    return Deflation(defl, lam, pr, np.array(rrs), np.array(rls), len(order), arnoldi_steps,
+                     gmres_residual(H, beta, mm) / beta, ritz)
 
 
 @dataclass

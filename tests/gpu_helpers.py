@@ -67,3 +67,41 @@ def device_defl(dims, Z, pair, U, H, prec=0, kpad=16):
     assert np.allclose(U, scale[:, None] * g5z[pair])
     return L.DeviceDefl(k, Vf, torch.from_numpy(pair.astype(np.int32)).cuda(), dev_c128(scale),
                         dev_c128(np.linalg.inv(H)) if H is not None else None)
+
+
+def newton_amplification(apply, t, B) -> float:
+    """kappa_N = max_j ||w_j|| / ||b|| over the Newton recurrence
+    w_{j+1} = w_j - t_j A w_j (rows b of B): the growth that multiplies the
+    rounding errors of a polynomial application.  At least 1."""
+    out = 1.0
+    for b in np.atleast_2d(B):
+        w = b.copy()
+        nb = np.linalg.norm(b)
+        for tj in t[:-1]:
+            w = w - tj * apply(w)
+            out = max(out, float(np.linalg.norm(w) / nb))
+    return out
+
+
+def composite_amplification(apply, t_in, t_out, B) -> float:
+    """kappa_N of the double polynomial p_in(A) p_out(A p_in(A)) b as the
+    library evaluates it: the outer Newton recurrence over B = I - pi_in(A),
+    each application a product chain prod_i (1 - t_i A) w, then p_in(A) on the
+    outer sum.  Max over every intermediate vector of ||.|| / ||b||."""
+    out = 1.0
+    for b in np.atleast_2d(B):
+        nb = np.linalg.norm(b)
+        w, y = b.copy(), np.zeros_like(b)
+        for j, ph in enumerate(t_out):
+            y = y + ph * w
+            out = max(out, float(np.linalg.norm(y) / nb))
+            if j + 1 == len(t_out):
+                break
+            v = w.copy()
+            for ti in t_in:
+                v = v - ti * apply(v)
+                out = max(out, float(np.linalg.norm(v) / nb))
+            w = w - ph * (w - v)
+            out = max(out, float(np.linalg.norm(w) / nb))
+        out = max(out, newton_amplification(apply, t_in, y[None, :]) * float(np.linalg.norm(y) / nb))
+    return out

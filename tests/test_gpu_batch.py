@@ -102,3 +102,27 @@ def test_autotune_keeps_values(tmp_path):
     # second call is served from the cache
     res2 = autotune(run, reps=1, cache_path=str(tmp_path / "tune.json"))
     assert all(res2.cached.values()) and res2.choice == res.choice
+
+
+def test_autotune_offers_the_blocked_sweep(tmp_path):
+    """On an FP32 lattice whose xyz-plane exceeds one workgroup (16^3 planes:
+    the t-sweep cuts them into blocks with a halo), the candidates include
+    the blocked t-sweep, and the tuner keeps it when it is the faster shape."""
+    from paper_2306_09559_amd import driver
+    from paper_2306_09559_amd.batch import _candidates, autotune
+    from synth.configs import Level
+    L = lib()
+    cfg = dataclasses.replace(_small_cfgs()[0], name="C1p", dims=(16, 16, 16, 4), kappa=0.14,
+                              levels=(Level(12, None, 64),), seed_links=121, lattice_id=12)
+    run = driver.build(cfg, prec=L.F32, rb=16)
+    assert L.sweep_plan(run.dl, 64, 16)["halo"]
+    cands = _candidates(run, 0)
+    assert (16, True) in cands and (16, False) in cands
+    res = autotune(run, reps=3, use_cache=False, cache_path=str(tmp_path / "t.json"))
+    t = res.timings[0]
+    print(t)
+    best_sweep = min(v for k, v in t.items() if k.endswith("-sweep"))
+    best_stream = min(v for k, v in t.items() if not k.endswith("-sweep"))
+    # the blocked sweep moves ~1.7x the streaming kernel's bytes per second on these planes
+    assert best_sweep < best_stream
+    assert res.choice[0][1]

@@ -79,3 +79,69 @@ def test_unconverged_top_level_solve_is_reported():
     with pytest.raises(SolveNotConverged):
         run.draw(0, 16)
     assert lv.drawn == 0 and lv.acc.cpu().numpy()[0] == 0
+
+
+@pytest.mark.parametrize("dims,prec,nrhs,rb", [
+    ((8, 8, 8, 8), 0, 64, 16),      # FP64 whole-plane t-sweep
+    ((8, 8, 8, 8), 1, 64, 16),      # FP32 whole-plane t-sweep (own backward products)
+    ((16, 16, 16, 2), 1, 32, 4),    # FP32 blocks with a halo
+])
+def test_kappa_zero_polynomial_is_p_of_one(dims, prec, nrhs, rb):
+    """kappa = 0 gives A = I, so b^H p(A) b = p(1) b^H b = 12 V p(1) for every
+    Z4 sample, with p(1) from the scalar Newton form of the oracle.  A 5-root
+    polynomial runs 4 Newton steps on the t-sweep (every kappa t_j is 0) and
+    on the streaming kernel; vector mode gives y = p(1) b."""
+    from oracle import deflation
+    L = lib()
+    dl, ol = device_lattice(dims, 0.0, 0.4, 43, True, prec=prec)
+    assert L.sweep_plan(dl, nrhs, rb)["ok"] and L.sweep_plan(dl, nrhs, 1)["ok"]
+    t = np.array([0.6, 0.5 + 0.1j, 0.4, 0.3j, 0.2])
+    p1 = complex(deflation.poly_eval(t, 1.0))
+    poly = L.DevicePoly(dev_c128(t))
+    want = 12 * dl.V * p1
+    # amplification of the recurrence: max_j |prod_{i<j} (1 - t_i)|
+    kN = max(1.0, max(abs(np.prod(1.0 - t[:j])) for j in range(1, len(t))))
+    tol = 1e-13 if prec == 0 else 8 * len(t) * kN * 2.0 ** -24
+    nz = L.Noise(3, 1, 0, 0)
+    for sweep in (1, 0):
+        L.set_option(L.OPT_PLANE_SWEEP, sweep)
+        bhy = torch.empty(nrhs, dtype=torch.complex128, device="cuda")
+        ws = L.workspace(L.poly_workspace_size(dl, poly, nrhs, rb))
+        L.poly_apply(dl, poly, nrhs, rb, None, nz, None, bhy, ws)
+        y = L.empty_field(dl.V, nrhs, 1, prec)
+        ws1 = L.workspace(L.poly_workspace_size(dl, poly, nrhs, 1))
+        L.poly_apply(dl, poly, nrhs, 1, None, nz, y, None, ws1)
+        torch.cuda.synchronize()
+        got = bhy.cpu().numpy()
+        assert np.all(np.isfinite(got)), sweep
+        assert np.max(np.abs(got - want)) <= tol * abs(want), (sweep, got[:3], want)
+        Y = unpack(dims, y, prec)
+        B = oracle.z4(3, 1, 0, 0, nrhs, dl.V)
+        for r in (0, nrhs - 1):
+            assert np.max(np.abs(Y[r] - p1 * B[r])) <= tol * abs(p1), (sweep, r)
+    L.set_option(L.OPT_PLANE_SWEEP, 1)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_zero_inverse_root_on_the_sweep(prec):
+    """An inverse root t_j = 0 makes kappa t_j = 0 with kappa != 0: that Newton
+    step is w_{j+1} = w_j.  The t-sweep agrees with the oracle (and with the
+    streaming kernel) on the 8^4 lattice."""
+    L = lib()
+    dims, nrhs, rb = (8, 8, 8, 8), 32, 16
+    dl, ol = device_lattice(dims, 0.12, 0.4, 44, True, prec=prec)
+    t = np.array([0.9, 0.0, 0.7 + 0.2j, 0.0, 0.5 - 0.1j, 0.8])
+    poly = L.DevicePoly(dev_c128(t))
+    B = oracle.z4(9, 2, 0, 0, nrhs, dl.V)
+    _, ref = ol.poly_apply(t, B)
+    tol = 1e-12 if prec == 0 else 8 * len(t) * 4 * 2.0 ** -24
+    out = {}
+    for sweep in (1, 0):
+        L.set_option(L.OPT_PLANE_SWEEP, sweep)
+        bhy = torch.empty(nrhs, dtype=torch.complex128, device="cuda")
+        ws = L.workspace(L.poly_workspace_size(dl, poly, nrhs, rb))
+        L.poly_apply(dl, poly, nrhs, rb, None, L.Noise(9, 2, 0, 0), None, bhy, ws)
+        torch.cuda.synchronize()
+        out[sweep] = bhy.cpu().numpy()
+        assert np.max(np.abs(out[sweep] - ref) / np.abs(ref)) < tol, sweep
+    L.set_option(L.OPT_PLANE_SWEEP, 1)

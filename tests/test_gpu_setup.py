@@ -138,3 +138,43 @@ def test_extra_deflation_setup_small():
     assert np.max(run.levels[0].last_solve.rel_res) <= 1e-6
     e = run.estimates()[0]
     assert e["n"] == 16 and np.isfinite(e["estimate"])
+
+
+def test_selection_matches_oracle_on_the_same_ritz_pairs():
+    """The product's selection walk (Sec. 4: imaglim, evectol, gamma_5 left
+    vectors) and the oracle's select_eigs, given the same Ritz candidates,
+    accept the same eigenvalues with the same pair map, and the product's left
+    vectors u_q = scale_q g5 z_pair(q) equal the oracle's biorthonormal ones.
+    The oracle takes its left residuals with the dense A^H (an independent
+    route: the product uses g5-hermiticity, ||A z_src - conj(l) z_src||)."""
+    from paper_2306_09559_amd import krylov
+    from synth.configs import C1
+    dims = C1.dims
+    dl, ol = device_lattice(dims, C1.kappa, C1.eps, C1.seed_links, True)
+    start = synth.gaussian_start(ol.n, C1.seed_start)
+    rs = krylov.gmres_roots(dl, [5], start)
+    imaglim, evectol = 2e-4, 1e-3
+    df = krylov.pp_arnoldi_deflation(dl, rs.device[5], start, 40, 24, 24, imaglim, evectol, keep_candidates=True)
+    rz = df.ritz
+    lam_c = rz["lam"]
+    Zall = unpack(dims, rz["Z"], 0)
+    Zc = Zall[rz["order"]]
+    A = dense.dense_matrix(ol)
+    AH = A.conj().T
+    AZ = ol.apply(Zc)
+    tr = okr.select_eigs(lam_c, Zc, AZ, ol.gamma5, lambda v: AH @ v, imaglim, evectol)
+    k = df.device.k
+    print(f"candidates {len(lam_c)}, accepted {k}, pairs {int(np.sum(df.pair != np.arange(k)))}")
+    # the walk made choices: some candidates rejected, some accepted, conjugate pairs among them
+    assert 0 < k < len(lam_c)
+    assert np.any(df.pair != np.arange(k))
+    # residuals agree (FP64, different routes), and none sits within their difference of evectol
+    assert np.allclose(df.res_right, tr.res_right, rtol=1e-7, atol=1e-14)
+    assert np.allclose(df.res_left, tr.res_left, rtol=1e-7, atol=1e-14)
+    assert np.array_equal(df.lam, tr.lam)
+    assert np.array_equal(df.pair, tr.pair)
+    Vs = unpack(dims, df.device.V, 0)[:k]
+    assert np.array_equal(Vs, tr.Z)
+    scale = df.device.scale.cpu().numpy()[:k]
+    U_prod = scale[:, None] * ol.gamma5(Vs[df.pair])
+    assert np.max(np.abs(U_prod - tr.U)) <= 1e-10 * np.max(np.abs(tr.U))

@@ -67,7 +67,7 @@ def test_deflation_unbiased_identity(small):
     assert abs(np.trace(M - D) + np.sum(c * uz) - np.trace(M)) < 1e-10
     # sample form: b^* D b = sum c_i conj(zeta_i) omega_i
     b = oracle.z4(1, 0, 0, 0, 3, lat.V)
-    zeta, omega = Z.conj() @ b.T, U.conj() @ b.T
+    zeta, omega = deflation.projection_coefficients(Z, U, b)
     s = estimator.level_samples(np.einsum("ri,ij,rj->r", b.conj(), M, b), None, zeta, omega, c)
     direct = np.einsum("ri,ij,rj->r", b.conj(), M - D, b)
     assert np.allclose(s, direct, rtol=1e-12)
