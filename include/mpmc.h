@@ -78,7 +78,11 @@ enum {
     MPMC_EINVAL = -1,       /* null pointer, size or layout out of range */
     MPMC_EUNSUPPORTED = -2, /* unknown precision, mode or operator kind */
     MPMC_EWORKSPACE = -3,   /* ws smaller than the *_workspace_size result */
-    MPMC_EHIP = -4          /* HIP runtime or launch failure */
+    MPMC_EHIP = -4,         /* HIP runtime or launch failure */
+    MPMC_ESINGULAR = -5,    /* a small dense system has a zero pivot (mpmc_small_inverse) */
+    MPMC_ENOTCONVERGED = -6 /* an iteration missed its tolerance: no entry point of the library
+                               iterates to a tolerance itself; the host-driven solver of the
+                               binding (GMRES cycles around mpmc_* calls) reports it with this code */
 };
 
 enum { MPMC_F64 = 0, MPMC_F32 = 1 };
@@ -153,8 +157,13 @@ const char *mpmc_build_info(void);
  *     lattice whose xyz-plane (Lx*Ly*Lz a multiple of 64, at most 512 sites
  *     and 160 KiB of LDS at the field precision) run as a t-sweep with one
  *     workgroup per vector; 0: always use the streaming site-parallel kernel.
- * Both paths compute the same values up to the order of floating-point sums. */
-enum { MPMC_OPT_PLANE_SWEEP = 1 };
+ *   MPMC_OPT_SWEEP_RANK   0 (default) .. 63: on FP32 planes too large for
+ *     one workgroup, the t-sweep cuts the plane into xyz-blocks with a halo
+ *     in LDS; the candidate blocks are ranked by the bytes each moves per
+ *     site, and this option picks the rank-th (clamped to the last).
+ * Every choice computes the same values up to the order of floating-point
+ * sums. */
+enum { MPMC_OPT_PLANE_SWEEP = 1, MPMC_OPT_SWEEP_RANK = 2 };
 int mpmc_set_option(int32_t option, int32_t value);
 
 /* Which t-sweep a scalar-mode polynomial on this lattice and batch would
@@ -342,6 +351,127 @@ size_t mpmc_level_workspace_size(const mpmc_lattice *lat, const mpmc_level *leve
 int mpmc_mlmc_level_estimate(const mpmc_lattice *lat, const mpmc_level *level, mpmc_shape shape,
                              const mpmc_noise *noise, double *samples, double *acc, void *ws,
                              size_t ws_bytes, void *stream);
+
+/* The stopping rule of the adaptive multilevel estimate (Sec. 5 step 3) on
+ * the device, one sample at a time in batch order, as the paper's loop
+ * draws them: after every sample whose running count n is a check point
+ * (first, first + every, first + 2 every, ...) the level stops when its
+ * standard error sqrt(M2 / ((n - 1) n)) is at most the target.
+ *   samples  device, nrhs x 6 FP64 (mpmc_mlmc_level_estimate's output; s is columns 0, 1)
+ *   state    device, 16 FP64, caller-owned: zero it before the level's first
+ *            batch and set [7] = target.  [0] n, [1..2] mean, [3] M2 =
+ *            sum |s - mean|^2 of every sample scanned (Welford's update);
+ *            [4] 1 once stopped, [5] n at the stop, [8..9] mean and [10] M2
+ *            of exactly the samples up to the stop.  After the stop, further
+ *            calls change nothing.
+ * first >= 2, every >= 1.  One tiny kernel, capturable in a HIP graph. */
+int mpmc_level_stop_check(const double *samples, int32_t nrhs, int32_t first, int32_t every, double *state,
+                          void *stream);
+
+/* ---- batched steps and the autotuner (Sec. 5 step 3: every level of the
+ * multilevel estimate draws its samples; eq. multpolytr) -------------------
+ *
+ * A step of the multilevel method draws Z4 samples on every level of one or
+ * several lattices.  The library records such a step once as a HIP graph
+ * (every launch of every level, of uneven degree and sample count, in one
+ * graph) and replays it with one launch.  Each item of a step takes its
+ * sample index from a device counter that the graph itself advances, so
+ * every replay draws new samples and the level accumulators keep merging
+ * them on the device; nothing is read back between replays.
+ *
+ * The handle owns the graph, the streams it was recorded on and the tuner's
+ * results; it owns no device memory.  One handle per thread. */
+typedef struct mpmc_handle_s *mpmc_handle;
+
+/* *out = a new handle (host memory only).  MPMC_EINVAL for out == NULL. */
+int mpmc_handle_create(mpmc_handle *out);
+/* Destroys the handle, its graph and its streams (waits for none of its
+ * work: synchronise the launch stream first).  NULL is a no-op. */
+int mpmc_handle_destroy(mpmc_handle h);
+
+/* One level of one lattice in a batched step: `batches` batches of
+ * shape.nrhs samples, each followed by *counter += shape.nrhs.  Batch b of a
+ * replay draws samples noise.first_sample + *counter + (0 .. nrhs-1), where
+ * *counter is read when that batch runs (noise.sample_offset is ignored).
+ * Items with the same branch run in the given order on one stream; items of
+ * different branches may run concurrently (give each lattice its own).  The
+ * descriptors (lat, level, and what they point to on the host) are read
+ * during mpmc_batch_build only; every device buffer they and the item name
+ * must stay valid while the graph may run.  Two items must not share a
+ * workspace, samples or acc buffer unless they are in the same branch. */
+typedef struct {
+    const mpmc_lattice *lat;
+    const mpmc_level *level;     /* a polynomial level: kind_hi POLY or DEFLATED_POLY (SOLVE needs a
+                                    host-driven solve per batch and is not batched) */
+    mpmc_shape shape;
+    mpmc_noise noise;            /* seed, lattice, level id, first_sample */
+    uint64_t *counter;           /* device, caller-owned sample counter of this item */
+    int32_t batches;             /* >= 1 */
+    double *samples;             /* device, nrhs x 6 FP64 (holds the last batch) */
+    double *acc;                 /* device, 8 FP64 level accumulator (as mpmc_mlmc_level_estimate) */
+    void *ws;                    /* device, mpmc_level_workspace_size(lat, level, shape) bytes */
+    size_t ws_bytes;
+    int32_t branch;              /* >= 0 */
+    int32_t plane_sweep;         /* kernel selection for this item: MPMC_OPT_PLANE_SWEEP value */
+    int32_t sweep_rank;          /* MPMC_OPT_SWEEP_RANK value */
+    double *stop_state;          /* device state of mpmc_level_stop_check, or NULL: when given, every
+                                    batch is followed by the stopping check on its samples */
+    int32_t stop_first, stop_every;  /* the level's check points (as mpmc_level_stop_check) */
+} mpmc_batch_item;
+
+/* Record the step made of items[0 .. n_items-1] as a HIP graph held by the
+ * handle (replacing any previous one).  Enqueues nothing and runs nothing:
+ * recording only captures the launches.  Arguments are validated first
+ * (MPMC_EINVAL, MPMC_EUNSUPPORTED, MPMC_EWORKSPACE as the level call would
+ * return); MPMC_EHIP if recording or instantiation fails. */
+int mpmc_batch_build(mpmc_handle h, const mpmc_batch_item *items, int32_t n_items);
+
+/* Launch the recorded step on `stream` (asynchronous).  MPMC_EINVAL if no
+ * step was built. */
+int mpmc_batch_launch(mpmc_handle h, void *stream);
+
+/* A kernel shape for one level: RHS block width and the two kernel-selection
+ * options above. */
+typedef struct {
+    int32_t rb;
+    int32_t plane_sweep;
+    int32_t sweep_rank;
+} mpmc_tune_choice;
+
+typedef struct {
+    mpmc_tune_choice choice;
+    double seconds;              /* per call of mpmc_mlmc_level_estimate with this shape */
+} mpmc_tune_result;
+
+/* Workspace the tuner needs for this level and batch size (every candidate
+ * shape fits in it, plus scratch samples and accumulator). */
+size_t mpmc_autotune_workspace_size(const mpmc_lattice *lat, const mpmc_level *level, int32_t nrhs);
+
+/* Time one level's batch of nrhs samples under every candidate shape and
+ * pick the fastest: block widths rb = 1, 2, 4, .. 32 dividing nrhs on the
+ * streaming kernel; rb >= 8 on the t-sweep where it applies; on FP32 planes
+ * cut into blocks, the three best-ranked blocks.  `best` is in/out: on
+ * entry the current shape, which is kept unless a candidate is faster by
+ * more than keep_within (a fraction, e.g. 0.03); on exit the choice.  Each
+ * candidate runs once untimed, then `reps` times between HIP events on
+ * `stream`; the call synchronises with `stream` and returns after timing
+ * (it is not capturable).  The noise's first_sample is used for every run;
+ * the level's samples and accumulator are not touched (scratch in ws).
+ * Results are cached in the handle by (device, lattice shape, precision,
+ * level kinds and degrees, deflation size, nrhs): a repeated call returns
+ * the cached choice with *cached = 1 and times nothing.  results (nullable)
+ * receives up to max_results timings, *n_results (nullable) their count. */
+int mpmc_autotune(mpmc_handle h, const mpmc_lattice *lat, const mpmc_level *level, int32_t nrhs,
+                  const mpmc_noise *noise, int32_t reps, double keep_within, void *ws, size_t ws_bytes,
+                  mpmc_tune_choice *best, double *best_seconds, int32_t *cached, mpmc_tune_result *results,
+                  int32_t max_results, int32_t *n_results, void *stream);
+
+/* Host helper: inverse of a k x k complex FP64 matrix (row-major (re, im)
+ * pairs, host memory) by Gaussian elimination with partial pivoting; used
+ * for H^{-1}, H = U^H A V, of the Left-right Projection (Sec. 2.1).
+ * MPMC_ESINGULAR when a pivot is below tiny * max |entry| (nothing is
+ * written to out then); a and out may not overlap. */
+int mpmc_small_inverse(int32_t k, const double *a, double tiny, double *out);
 
 #ifdef __cplusplus
 }

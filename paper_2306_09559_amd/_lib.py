@@ -25,11 +25,11 @@ if not os.path.exists(LIB_PATH):
 
 _lib = ctypes.CDLL(LIB_PATH)
 
-OK, EINVAL, EUNSUPPORTED, EWORKSPACE, EHIP = 0, -1, -2, -3, -4
+OK, EINVAL, EUNSUPPORTED, EWORKSPACE, EHIP, ESINGULAR, ENOTCONVERGED = 0, -1, -2, -3, -4, -5, -6
 F64, F32 = 0, 1
 DEFL_COEFF, DEFL_RECON, DEFL_PROJECT = 0, 1, 2
 OP_NONE, OP_POLY, OP_DEFLATED_POLY, OP_SOLVE = 0, 1, 2, 3
-OPT_PLANE_SWEEP = 1
+OPT_PLANE_SWEEP, OPT_SWEEP_RANK = 1, 2
 
 c_i32, c_u64, c_f64, c_vp, c_size = ctypes.c_int32, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 
@@ -59,6 +59,21 @@ class mpmc_defl(ctypes.Structure):
 class mpmc_level(ctypes.Structure):
     _fields_ = [("kind_hi", c_i32), ("kind_lo", c_i32), ("poly_hi", mpmc_poly), ("poly_lo", mpmc_poly),
                 ("defl", ctypes.POINTER(mpmc_defl)), ("deflate_samples", c_i32), ("c", c_vp), ("solve_x", c_vp)]
+
+
+class mpmc_batch_item(ctypes.Structure):
+    _fields_ = [("lat", ctypes.POINTER(mpmc_lattice)), ("level", ctypes.POINTER(mpmc_level)), ("shape", mpmc_shape),
+                ("noise", mpmc_noise), ("counter", c_vp), ("batches", c_i32), ("samples", c_vp), ("acc", c_vp),
+                ("ws", c_vp), ("ws_bytes", c_size), ("branch", c_i32), ("plane_sweep", c_i32),
+                ("sweep_rank", c_i32), ("stop_state", c_vp), ("stop_first", c_i32), ("stop_every", c_i32)]
+
+
+class mpmc_tune_choice(ctypes.Structure):
+    _fields_ = [("rb", c_i32), ("plane_sweep", c_i32), ("sweep_rank", c_i32)]
+
+
+class mpmc_tune_result(ctypes.Structure):
+    _fields_ = [("choice", mpmc_tune_choice), ("seconds", c_f64)]
 
 
 P = ctypes.POINTER
@@ -95,6 +110,16 @@ _sig = {
     "mpmc_level_workspace_size": (c_size, [P(mpmc_lattice), P(mpmc_level), mpmc_shape]),
     "mpmc_mlmc_level_estimate": (ctypes.c_int, [P(mpmc_lattice), P(mpmc_level), mpmc_shape, P(mpmc_noise), c_vp,
                                                 c_vp, c_vp, c_size, c_vp]),
+    "mpmc_handle_create": (ctypes.c_int, [P(c_vp)]),
+    "mpmc_handle_destroy": (ctypes.c_int, [c_vp]),
+    "mpmc_batch_build": (ctypes.c_int, [c_vp, P(mpmc_batch_item), c_i32]),
+    "mpmc_batch_launch": (ctypes.c_int, [c_vp, c_vp]),
+    "mpmc_autotune_workspace_size": (c_size, [P(mpmc_lattice), P(mpmc_level), c_i32]),
+    "mpmc_autotune": (ctypes.c_int, [c_vp, P(mpmc_lattice), P(mpmc_level), c_i32, P(mpmc_noise), c_i32, c_f64, c_vp,
+                                     c_size, P(mpmc_tune_choice), P(c_f64), P(c_i32), P(mpmc_tune_result), c_i32,
+                                     P(c_i32), c_vp]),
+    "mpmc_small_inverse": (ctypes.c_int, [c_i32, c_vp, c_f64, c_vp]),
+    "mpmc_level_stop_check": (ctypes.c_int, [c_vp, c_i32, c_i32, c_i32, c_vp, c_vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -422,3 +447,119 @@ def mlmc_level_estimate(lat: DeviceLattice, level: DeviceLevel, nrhs: int, rb: i
     _check("mpmc_mlmc_level_estimate", _lib.mpmc_mlmc_level_estimate(
         ctypes.byref(L), ctypes.byref(lv), mpmc_shape(nrhs, rb), ctypes.byref(nz), _ptr(samples), _ptr(acc),
         _ptr(ws), ws.numel(), _stream()))
+
+
+# ------------------------------------------------------------------ batched steps and the autotuner
+class Handle:
+    """Owner of a recorded step (HIP graph), its streams and the tuner's cache
+    (mpmc_handle_create / mpmc_handle_destroy)."""
+
+    def __init__(self):
+        h = c_vp()
+        _check("mpmc_handle_create", _lib.mpmc_handle_create(ctypes.byref(h)))
+        self._h = h
+        self._keep = []          # C descriptors referenced by the recorded step
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _lib.mpmc_handle_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:       # noqa: BLE001 - interpreter shutdown
+            pass
+
+
+@dataclass
+class BatchItem:
+    """One level of one lattice in a batched step (mpmc_batch_item)."""
+    lat: DeviceLattice
+    level: DeviceLevel
+    nrhs: int
+    rb: int
+    noise: Noise                  # seed, lattice, level id, first sample (its sample_offset is not used)
+    counter: torch.Tensor         # device int64 (1,)
+    batches: int
+    samples: torch.Tensor
+    acc: torch.Tensor
+    ws: torch.Tensor
+    branch: int = 0
+    plane_sweep: int = 1
+    sweep_rank: int = 0
+    stop_state: Optional[torch.Tensor] = None    # device float64 (16,): mpmc_level_stop_check after each batch
+    stop_first: int = 2
+    stop_every: int = 1
+
+
+def batch_build(h: Handle, items: Sequence[BatchItem]):
+    """Record the step (mpmc_batch_build); nothing runs."""
+    keep = []
+    arr = (mpmc_batch_item * len(items))()
+    for i, it in enumerate(items):
+        L = it.lat.c()
+        lv, dref = it.level.cstruct()
+        keep += [L, lv, dref]
+        assert it.counter.dtype == torch.int64 and it.counter.is_cuda
+        arr[i] = mpmc_batch_item(ctypes.pointer(L), ctypes.pointer(lv), mpmc_shape(it.nrhs, it.rb), it.noise.c(),
+                                 it.counter.data_ptr(), int(it.batches), it.samples.data_ptr(), it.acc.data_ptr(),
+                                 it.ws.data_ptr(), it.ws.numel(), int(it.branch), int(it.plane_sweep),
+                                 int(it.sweep_rank), None if it.stop_state is None else it.stop_state.data_ptr(),
+                                 int(it.stop_first), int(it.stop_every))
+    _check("mpmc_batch_build", _lib.mpmc_batch_build(h.ptr, arr, len(items)))
+    h._keep = keep
+
+
+def batch_launch(h: Handle):
+    _check("mpmc_batch_launch", _lib.mpmc_batch_launch(h.ptr, _stream()))
+
+
+def autotune_workspace_size(lat: DeviceLattice, level: DeviceLevel, nrhs: int) -> int:
+    L = lat.c()
+    lv, _keep = level.cstruct()
+    return int(_lib.mpmc_autotune_workspace_size(ctypes.byref(L), ctypes.byref(lv), int(nrhs)))
+
+
+def autotune_level(h: Handle, lat: DeviceLattice, level: DeviceLevel, nrhs: int, noise: Noise, current: tuple,
+                   reps: int = 3, keep_within: float = 0.03, ws: Optional[torch.Tensor] = None):
+    """mpmc_autotune for one level.  current = (rb, plane_sweep, sweep_rank).
+    Returns (choice tuple, seconds per call, cached flag, [(choice, seconds)...])."""
+    L = lat.c()
+    lv, _keep = level.cstruct()
+    nz = noise.c()
+    if ws is None:
+        ws = workspace(autotune_workspace_size(lat, level, nrhs))
+    best = mpmc_tune_choice(*[int(x) for x in current])
+    secs, cached, nres = c_f64(), c_i32(), c_i32()
+    res = (mpmc_tune_result * 64)()
+    _check("mpmc_autotune", _lib.mpmc_autotune(
+        h.ptr, ctypes.byref(L), ctypes.byref(lv), int(nrhs), ctypes.byref(nz), int(reps), float(keep_within),
+        _ptr(ws), ws.numel(), ctypes.byref(best), ctypes.byref(secs), ctypes.byref(cached), res, 64,
+        ctypes.byref(nres), _stream()))
+    table = [((r.choice.rb, r.choice.plane_sweep, r.choice.sweep_rank), r.seconds) for r in res[: nres.value]]
+    return (best.rb, best.plane_sweep, best.sweep_rank), secs.value, bool(cached.value), table
+
+
+def level_stop_check(samples: torch.Tensor, nrhs: int, first: int, every: int, state: torch.Tensor):
+    """mpmc_level_stop_check: the stopping rule on the device (state float64 (16,))."""
+    assert state.dtype == torch.float64 and state.numel() >= 16
+    _check("mpmc_level_stop_check", _lib.mpmc_level_stop_check(_ptr(samples), int(nrhs), int(first), int(every),
+                                                               _ptr(state), _stream()))
+
+
+def small_inverse(a, tiny: float = 1e-14):
+    """Inverse of a small complex FP64 matrix on the host (mpmc_small_inverse);
+    raises MpmcError(ESINGULAR) for a zero pivot."""
+    import numpy as np
+    m = np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+    k = m.shape[0]
+    assert m.shape == (k, k)
+    out = np.empty_like(m)
+    _check("mpmc_small_inverse", _lib.mpmc_small_inverse(k, m.ctypes.data_as(c_vp), float(tiny),
+                                                         out.ctypes.data_as(c_vp)))
+    return out

@@ -1,21 +1,22 @@
-"""Batched execution of the multilevel sampling: HIP-graph capture of whole
-steps over several lattices, and an autotuner for the kernel shape.
+"""Batched execution of the multilevel sampling through the library's
+batched-step entry points, and the kernel-shape autotuner.
 
 A step is every polynomial level of every lattice drawing its batch of Z4
-samples (eq. multpolytr, Sec. 3.1; Sec. 5 step 3).  `GraphStep` records one
-step of a list of `LatticeRun`s as a single HIP graph: each lattice gets
-its own branch (a forked stream), so independent lattices of uneven size,
-degree and sample count run concurrently instead of one after the other,
-and a replay costs one graph launch instead of one host launch per kernel.
-Each level's noise takes its sample index from a device counter that the
-graph advances by the batch size (mpmc_counter_add), so every replay draws
+samples (eq. multpolytr, Sec. 3.1; Sec. 5 step 3).  `GraphStep` hands one
+step of a list of `LatticeRun`s to `mpmc_batch_build`, which records it as
+a single HIP graph: each lattice gets its own branch, so independent
+lattices of uneven size, degree and sample count run concurrently, and a
+replay (`mpmc_batch_launch`) is one graph launch instead of one host launch
+per kernel.  Each level's noise takes its sample index from a device
+counter that the graph advances by the batch size, so every replay draws
 new samples and the level accumulators keep merging them on the device.
-Solve levels (host-driven GMRES) are not captured.
+Solve levels (host-driven GMRES) are not batched.
 
-`autotune` times each level's candidate shapes -- RHS block width and the
-t-sweep vs the streaming kernel -- on the real workload and keeps the
-fastest; results are cached in a JSON file keyed by (gfx arch, lattice,
-batch size, precision, polynomial).
+`autotune` asks `mpmc_autotune` to time each level's candidate shapes --
+RHS block width, the t-sweep or the streaming kernel, and on FP32 planes cut
+into blocks the block shape -- on the real workload, keeps the fastest, and
+persists the choices in a JSON file keyed by (gfx arch, lattice, batch size,
+precision, polynomial).
 """
 from __future__ import annotations
 
@@ -41,13 +42,14 @@ class _Item:
 
 
 class GraphStep:
-    """One step of several lattice runs captured as one HIP graph."""
+    """One step of several lattice runs recorded by the library as one HIP graph."""
 
     def __init__(self, runs: Sequence[LatticeRun], batch: Optional[Dict[Tuple[int, int], int]] = None,
-                 parallel: bool = True, warmup: int = 1, only: Optional[Sequence[Tuple[int, int]]] = None,
+                 parallel: bool = True, only: Optional[Sequence[Tuple[int, int]]] = None,
                  keep_state: bool = False):
         """runs: the lattices; batch: samples per (run, level), default the
-        configured batch; only: restrict to these (run, level) pairs;
+        configured batch; parallel: one graph branch per lattice (else one
+        branch in order); only: restrict to these (run, level) pairs;
         keep_state: continue the levels' accumulators and sample counts (a
         run resumed from a checkpoint) instead of starting from zero."""
         self.runs = list(runs)
@@ -66,52 +68,27 @@ class GraphStep:
                 row.append(_Item(run, li, n, reps, torch.zeros(1, dtype=torch.int64, device="cuda")))
             self.items.append(row)
         self.replays = 0
-        saved = None
+        self.handle = L.Handle()
+        citems = []
+        for ri, row in enumerate(self.items):
+            for it in row:
+                run, lv = it.run, it.run.levels[it.level]
+                cfg = run.cfg
+                # the sample index is the counter alone: replay k draws samples k*N .. k*N+N-1
+                cfg_noise = L.Noise(cfg.seed_noise, cfg.lattice_id, lv.index, 0)
+                citems.append(L.BatchItem(run.dl, lv.device, it.nsamples, run.level_rb(it.level), cfg_noise,
+                                          it.counter, it.repeats, lv.samples[: it.nsamples], lv.acc, lv.ws,
+                                          branch=ri if parallel else 0, plane_sweep=int(lv.sweep),
+                                          sweep_rank=int(lv.sweep_rank)))
+        L.batch_build(self.handle, citems)
         if keep_state:
             torch.cuda.synchronize()
-            saved = [[(it.run.levels[it.level].acc.clone(), it.run.levels[it.level].drawn) for it in row]
-                     for row in self.items]
-        self._side = [torch.cuda.Stream() for _ in self.runs] if parallel else []
-        # eager warm-up: sets kernel attributes and touches every buffer before capture
-        for _ in range(warmup):
-            self._enqueue_all(torch.cuda.current_stream())
-        torch.cuda.synchronize()
-        self.graph = torch.cuda.CUDAGraph()
-        cap = torch.cuda.Stream()
-        cap.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.graph(self.graph, stream=cap):
-            self._enqueue_all(cap)
-        torch.cuda.synchronize()
-        if saved is None:
-            self.reset()
-        else:
-            for row, srow in zip(self.items, saved):
-                for it, (acc, drawn) in zip(row, srow):
-                    it.run.levels[it.level].acc.copy_(acc)
-                    it.run.levels[it.level].drawn = drawn
-                    it.counter.fill_(drawn)
-            torch.cuda.synchronize()
-
-    def _enqueue_run(self, row: List[_Item]):
-        for it in row:
-            # the sample index is the counter alone: replay k draws samples k*N .. k*N+N-1
-            nz = L.Noise(it.run.cfg.seed_noise, it.run.cfg.lattice_id, it.run.levels[it.level].index, 0,
-                         it.counter)
-            for _ in range(it.repeats):
-                it.run.enqueue(it.level, it.nsamples, nz)
-                L.counter_add(it.counter, it.nsamples)
-
-    def _enqueue_all(self, main: torch.cuda.Stream):
-        if not self.parallel:
             for row in self.items:
-                self._enqueue_run(row)
-            return
-        for row, side in zip(self.items, self._side):
-            side.wait_stream(main)
-            with torch.cuda.stream(side):
-                self._enqueue_run(row)
-        for side in self._side:
-            main.wait_stream(side)
+                for it in row:
+                    it.counter.fill_(it.run.levels[it.level].drawn)
+            torch.cuda.synchronize()
+        else:
+            self.reset()
 
     def reset(self):
         """Zero the accumulators and the sample counters (outside the graph)."""
@@ -125,7 +102,7 @@ class GraphStep:
 
     def replay(self, times: int = 1):
         for _ in range(times):
-            self.graph.replay()
+            L.batch_launch(self.handle)
         self.replays += times
 
     def sync_drawn(self):
@@ -158,49 +135,24 @@ def _key(run: LatticeRun, level: int) -> str:
                        bool(lv.deflated)])
 
 
-def _candidates(run: LatticeRun, level: int) -> List[Tuple[int, bool]]:
-    """(rb, sweep) shapes to time for one level: every block width dividing
-    the batch on the streaming kernel, and on the t-sweep wherever the
-    library's plan takes it (whole planes, or FP32 blocks with a halo); the
-    level's current shape is always among them."""
-    N = run.levels[level].batch
-    rbs = [rb for rb in (1, 2, 4, 8, 16, 32) if N % rb == 0]
-    out = [(rb, False) for rb in rbs]
-    # the sweep reads the noise itself: rb only shapes the first step's input, so wide blocks suffice
-    out += [(rb, True) for rb in rbs if rb >= 8 and L.sweep_plan(run.dl, N, rb)["ok"]]
-    current = (run.level_rb(level), bool(run.levels[level].sweep))
-    if current not in out:
-        out.append(current)
-    return out
-
-
-def _time_level(run: LatticeRun, level: int, reps: int) -> float:
-    N = run.levels[level].batch
-    s = torch.cuda.current_stream()
-    run.draw(level, N)                 # warm-up
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    for _ in range(reps):
-        run.draw(level, N)
-    e1.record(s)
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / reps * 1e-3
-
-
 @dataclass
 class TuneResult:
-    choice: Dict[int, Tuple[int, bool]] = field(default_factory=dict)
+    choice: Dict[int, Tuple[int, bool, int]] = field(default_factory=dict)    # level -> (rb, sweep, rank)
     timings: Dict[int, Dict[str, float]] = field(default_factory=dict)
     cached: Dict[int, bool] = field(default_factory=dict)
 
 
+def _label(choice) -> str:
+    rb, sw, rank = choice
+    return f"rb{rb}" + (f"-sweep{'' if rank == 0 else rank}" if sw else "")
+
+
 def autotune(run: LatticeRun, reps: int = 3, use_cache: bool = True, cache_path: Optional[str] = None,
-             keep_within: float = 0.03) -> TuneResult:
-    """Pick (rb, sweep) per polynomial level of `run` by timing; applies the
-    choice to the run and resets its accumulators.  The level's current shape
-    is kept unless another candidate is faster by more than keep_within (a
-    shape the kernel ignores, such as rb under the t-sweep, would otherwise
-    be chosen by timing noise)."""
+             keep_within: float = 0.03, handle: Optional[L.Handle] = None) -> TuneResult:
+    """Pick (rb, sweep, block rank) per polynomial level of `run` with
+    mpmc_autotune; applies the choice to the run and resets its
+    accumulators.  The level's current shape is kept unless another is
+    faster by more than keep_within.  Choices persist in a JSON file."""
     path = cache_path or _CACHE
     cache = {}
     if use_cache and os.path.exists(path):
@@ -209,36 +161,30 @@ def autotune(run: LatticeRun, reps: int = 3, use_cache: bool = True, cache_path:
                 cache = json.load(f)
         except (OSError, ValueError):
             cache = {}
+    h = handle or L.Handle()
     res = TuneResult()
     for li, lv in enumerate(run.levels):
         if lv.solver is not None:
             continue
         key = _key(run, li)
         if use_cache and key in cache:
-            rb, sw = cache[key]["rb"], cache[key]["sweep"]
-            run.set_level_shape(li, rb, sw)
-            res.choice[li] = (rb, sw)
+            c = cache[key]
+            rb, sw, rank = int(c["rb"]), bool(c["sweep"]), int(c.get("rank", 0))
+            run.set_level_shape(li, rb, sw, rank)
+            res.choice[li] = (rb, sw, rank)
             res.cached[li] = True
             continue
-        best, times = None, {}
-        current = (run.level_rb(li), lv.sweep)
-        t_current = None
-        for rb, sw in _candidates(run, li):
-            run.set_level_shape(li, rb, sw)
-            t = _time_level(run, li, reps)
-            times[f"rb{rb}{'-sweep' if sw else ''}"] = t
-            if (rb, sw) == current:
-                t_current = t
-            if best is None or t < best[0]:
-                best = (t, rb, sw)
-        if t_current is not None and t_current <= best[0] * (1.0 + keep_within):
-            best = (t_current,) + current
-        _, rb, sw = best
-        run.set_level_shape(li, rb, sw)
-        res.choice[li] = (rb, sw)
-        res.timings[li] = times
+        N = lv.batch
+        cur = (run.level_rb(li), int(lv.sweep), int(lv.sweep_rank))
+        nz = L.Noise(run.cfg.seed_noise, run.cfg.lattice_id, lv.index, 0)
+        best, secs, _hit, table = L.autotune_level(h, run.dl, lv.device, N, nz, cur, reps=reps,
+                                                   keep_within=keep_within)
+        rb, sw, rank = best
+        run.set_level_shape(li, rb, bool(sw), rank)
+        res.choice[li] = (rb, bool(sw), rank)
+        res.timings[li] = {_label(c): t for c, t in table}
         res.cached[li] = False
-        cache[key] = {"rb": rb, "sweep": sw, "seconds": best[0], "when": time.strftime("%Y-%m-%d")}
+        cache[key] = {"rb": rb, "sweep": bool(sw), "rank": rank, "seconds": secs, "when": time.strftime("%Y-%m-%d")}
     run.reset()
     if use_cache:
         try:

@@ -8,6 +8,7 @@
 namespace mpmc {
 
 int g_opt_sweep = 1;
+int g_opt_sweep_rank = 0;
 
 size_t poly_ws_bytes(const int32_t dims[4], int32_t prec, const mpmc_poly &poly, mpmc_shape sh) {
     const size_t fb = align256(field_bytes(dims, prec, sh.nrhs));
@@ -103,6 +104,8 @@ const char *mpmc_status_string(int status) {
     case MPMC_EUNSUPPORTED: return "unsupported precision, mode or operator kind";
     case MPMC_EWORKSPACE: return "workspace smaller than the required size";
     case MPMC_EHIP: return "HIP runtime or kernel launch failure";
+    case MPMC_ESINGULAR: return "singular small dense system (zero pivot)";
+    case MPMC_ENOTCONVERGED: return "iteration did not reach its tolerance";
     default: return "unknown status";
     }
 }
@@ -114,6 +117,10 @@ int mpmc_set_option(int32_t option, int32_t value) {
     case MPMC_OPT_PLANE_SWEEP:
         if (value != 0 && value != 1) return MPMC_EINVAL;
         g_opt_sweep = value;
+        return MPMC_OK;
+    case MPMC_OPT_SWEEP_RANK:
+        if (value < 0 || value > 63) return MPMC_EINVAL;
+        g_opt_sweep_rank = value;
         return MPMC_OK;
     default: return MPMC_EUNSUPPORTED;
     }
@@ -301,6 +308,12 @@ size_t mpmc_level_workspace_size(const mpmc_lattice *lat, const mpmc_level *leve
     if (level->kind_hi != MPMC_OP_SOLVE && check_poly(&level->poly_hi) != MPMC_OK) return 0;
     if (level->kind_lo != MPMC_OP_NONE && check_poly(&level->poly_lo) != MPMC_OK) return 0;
     return level_ws_bytes(*lat, *level, shape);
+}
+
+int mpmc_level_stop_check(const double *samples, int32_t nrhs, int32_t first, int32_t every, double *state,
+                          void *stream) {
+    if (!samples || !state || nrhs < 1 || first < 2 || every < 1) return MPMC_EINVAL;
+    return stop_check_impl(samples, nrhs, first, every, state, stream);
 }
 
 int mpmc_mlmc_level_estimate(const mpmc_lattice *lat, const mpmc_level *level, mpmc_shape shape,

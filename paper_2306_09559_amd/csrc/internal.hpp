@@ -39,8 +39,10 @@ struct SweepPlan {
     int nbp = 1;           // blocks per plane
     size_t lds = 0;        // dynamic LDS bytes
     bool fills = false;    // the batch gives every CU a full workgroup's worth of threads
+    int nranked = 1;       // blocked planes: candidate blocks ranked by the plan's cost (rank option)
 };
 SweepPlan sweep_plan(const mpmc_lattice &lat, mpmc_shape sh);
+int sweep_prepare_kernels();
 template <typename T>
 int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, const SweepPlan &plan, int n, const double *troots,
                    const void *x, bool x_is_noise, const void *bvec, uint64_t key, uint64_t first, const uint64_t *off,
@@ -54,8 +56,10 @@ template <typename T>
 int sweep_chain_t(const mpmc_lattice &lat, mpmc_shape sh, const SweepPlan &plan, int count, const double *troots,
                   const void *in, int rb_in, void *w0, void *w1, const void **out, void *stream);
 
-// process-wide options (mpmc_set_option)
+// process-wide kernel-selection options (mpmc_set_option); the batch builder
+// and the autotuner set them around each enqueue and restore them after
 extern int g_opt_sweep;
+extern int g_opt_sweep_rank;
 
 template <typename T>
 int poly_apply_t(const mpmc_lattice &, const mpmc_poly &, mpmc_shape, const void *x, const mpmc_noise *noise, void *y,
@@ -104,5 +108,6 @@ int deflate_impl(const mpmc_lattice &lat, const mpmc_defl &df, int32_t mode, mpm
 size_t level_ws_bytes(const mpmc_lattice &lat, const mpmc_level &lv, mpmc_shape sh);
 int level_impl(const mpmc_lattice &lat, const mpmc_level &lv, mpmc_shape sh, const mpmc_noise &nz, double *samples,
                double *acc, void *ws, void *stream);
+int stop_check_impl(const double *samples, int nrhs, int first, int every, double *state, void *stream);
 
 }  // namespace mpmc

@@ -201,10 +201,51 @@ int level_t(const mpmc_lattice &lat, const mpmc_level &lv, mpmc_shape sh, const 
     return hipGetLastError() == hipSuccess ? MPMC_OK : MPMC_EHIP;
 }
 
+// The stopping rule of Sec. 5 step 3 applied one sample at a time, as the
+// paper's loop draws them: state (FP64, see mpmc_level_stop_check) keeps the
+// level's running (n, mean, M2) -- Welford's update over complex samples as
+// pairs of reals -- and after every sample that lands on a check point
+// (first, first + every, ...) compares the standard error
+// sqrt(M2 / ((n - 1) n)) with the target.  The first success records the
+// statistics of exactly the samples up to that point and freezes the state.
+// One thread: a batch is at most a few hundred samples, in order.
+__global__ void k_stop_scan(const double *samples, int nrhs, int first, int every, double *state) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (state[4] != 0.0) return;                   // stopped earlier
+    double n = state[0], mr = state[1], mi = state[2], m2 = state[3];
+    const double target = state[7];
+    for (int r = 0; r < nrhs; ++r) {
+        const double sr = samples[(size_t)r * 6], si = samples[(size_t)r * 6 + 1];
+        n += 1.0;
+        const double dr = sr - mr, di = si - mi;
+        mr += dr / n;
+        mi += di / n;
+        m2 += dr * (sr - mr) + di * (si - mi);
+        const long long nn = (long long)n;
+        if (nn >= first && nn >= 2 && (nn - first) % every == 0 && sqrt(m2 / ((n - 1.0) * n)) <= target) {
+            state[4] = 1.0;
+            state[5] = n;
+            state[8] = mr;
+            state[9] = mi;
+            state[10] = m2;
+            break;
+        }
+    }
+    state[0] = n;
+    state[1] = mr;
+    state[2] = mi;
+    state[3] = m2;
+}
+
 }  // namespace
 
 size_t level_ws_bytes(const mpmc_lattice &lat, const mpmc_level &lv, mpmc_shape sh) {
     return carve(lat, lv, sh, nullptr, nullptr);
+}
+
+int stop_check_impl(const double *samples, int nrhs, int first, int every, double *state, void *stream) {
+    hipLaunchKernelGGL(k_stop_scan, dim3(1), dim3(64), 0, (hipStream_t)stream, samples, nrhs, first, every, state);
+    return hipGetLastError() == hipSuccess ? MPMC_OK : MPMC_EHIP;
 }
 
 int level_impl(const mpmc_lattice &lat, const mpmc_level &lv, mpmc_shape sh, const mpmc_noise &nz, double *samples,

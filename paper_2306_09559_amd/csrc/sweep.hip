@@ -893,12 +893,21 @@ SweepPlan sweep_plan(const mpmc_lattice &lat, mpmc_shape sh) {
     // The plan minimises the input bytes per block site over the compulsory
     // ones, (1 + halo / block sites) / line efficiency, then takes the larger
     // block (measured: 4x8x16 -> 16x4x8 blocks of 16^3 planes 1.2 -> 2.8 TB/s,
-    // 8x8x8 -> 24x4x4 of 24^3 planes 1.8 -> 2.2 TB/s).
+    // 8x8x8 -> 24x4x4 of 24^3 planes 1.8 -> 2.2 TB/s).  The candidates are
+    // ranked by that cost; the kernel-selection option MPMC_OPT_SWEEP_RANK
+    // picks a lower-ranked block (the autotuner times a few).
     auto cost = [&](int bx, int Pb, int Hb) {
         const double row = (double)bx * (double)csz;
         const double eff = bx == Lx ? 1.0 : row / (128.0 * std::ceil(row / 128.0));
         return (1.0 + (double)Hb / (double)Pb) / eff;
     };
+    struct Cand {
+        double cost;
+        int bx, by, bz, Pb, Hb;
+        size_t lds;
+    };
+    Cand cands[64];
+    int nc = 0;
     for (int bx = 1; bx <= Lx; ++bx) {
         if (Lx % bx) continue;
         for (int by = 1; by <= Ly; ++by) {
@@ -912,22 +921,32 @@ SweepPlan sweep_plan(const mpmc_lattice &lat, mpmc_shape sh) {
                 const size_t lds = (12 * (size_t)(Pb + Hb) + 6 * (size_t)Pb) * csz;
                 if (lds > kLds) continue;
                 if ((size_t)sh.nrhs * (size_t)(P / Pb) > avail) continue;
-                const double c = cost(bx, Pb, Hb);
-                const double best = p.ok ? cost(p.B[0], p.Pb, p.Hb) : 0.0;
-                if (!p.ok || c < best - 1e-9 || (c < best + 1e-9 && Pb > p.Pb)) {
-                    p.ok = true;
-                    p.halo = true;
-                    p.B[0] = bx;
-                    p.B[1] = by;
-                    p.B[2] = bz;
-                    p.Pb = Pb;
-                    p.Hb = Hb;
-                    p.nbp = P / Pb;
-                    p.lds = lds;
-                }
+                const Cand c{cost(bx, Pb, Hb), bx, by, bz, Pb, Hb, lds};
+                // keep the 64 best by (cost, larger block first), insertion-sorted
+                int at = nc < 64 ? nc : 64;
+                while (at > 0 && (c.cost < cands[at - 1].cost - 1e-9 ||
+                                  (c.cost < cands[at - 1].cost + 1e-9 && c.Pb > cands[at - 1].Pb)))
+                    --at;
+                if (at >= 64) continue;
+                for (int m = (nc < 64 ? nc : 63); m > at; --m) cands[m] = cands[m - 1];
+                cands[at] = c;
+                if (nc < 64) ++nc;
             }
         }
     }
+    if (nc == 0) return p;
+    // the plan's choice is the cheapest block; a tuner may ask for the rank-th (clamped)
+    const Cand &c = cands[g_opt_sweep_rank < nc ? g_opt_sweep_rank : nc - 1];
+    p.ok = true;
+    p.halo = true;
+    p.B[0] = c.bx;
+    p.B[1] = c.by;
+    p.B[2] = c.bz;
+    p.Pb = c.Pb;
+    p.Hb = c.Hb;
+    p.nbp = P / c.Pb;
+    p.lds = c.lds;
+    p.nranked = nc;
     return p;
 }
 
@@ -972,13 +991,31 @@ template <typename T> static const void *sweep_kernel(bool yacc, bool dot, bool 
 }
 // the kernels use up to 160 KB of dynamic LDS: allowed once per kernel
 static int ensure_lds_attr(const void *k) {
-    static const void *done[128];
+    static const void *done[256];
     static int ndone = 0;
     for (int i = 0; i < ndone; ++i)
         if (done[i] == k) return MPMC_OK;
     if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess) return MPMC_EHIP;
-    if (ndone < 128) done[ndone++] = k;
+    if (ndone < 256) done[ndone++] = k;
     return MPMC_OK;
+}
+
+template <typename T> static int prepare_kernels_t() {
+    for (int m = 0; m < 2 * 2 * 2 * 2 * 2 * 3; ++m) {
+        const int v = m % 3, h = (m / 3) % 2, tw = (m / 6) % 2, bf = (m / 12) % 2, d = (m / 24) % 2, y = m / 48;
+        const void *k = sweep_kernel<T>(y, d, bf, tw, h, v);
+        if (k && ensure_lds_attr(k) != MPMC_OK) return MPMC_EHIP;
+        const void *kp = (y || bf || !d) ? nullptr : sweep_probe_kernel<T>(tw, h, v);
+        if (kp && ensure_lds_attr(kp) != MPMC_OK) return MPMC_EHIP;
+    }
+    return MPMC_OK;
+}
+
+// Sets the dynamic-LDS limit of every t-sweep kernel up front, so that work
+// captured into a HIP graph makes no attribute calls.
+int sweep_prepare_kernels() {
+    const int st = prepare_kernels_t<double>();
+    return st != MPMC_OK ? st : prepare_kernels_t<float>();
 }
 
 template <typename T>

@@ -28,7 +28,7 @@ from synth.configs import LatticeConfig, poly_mvps
 from synth.configs import SOLVE
 
 from . import _lib as L
-from . import krylov
+from . import krylov, probing
 from .solve import MixedPPGMRES, SolveNotConverged, SolveStats
 
 
@@ -52,6 +52,7 @@ class LevelState:
     rb: int = 0                             # RHS block width of this level (0: the run's)
     batch: int = 0                          # vectors per batch (device buffers); samples per step / batch draws
     sweep: bool = True                      # allow the t-sweep kernel for this level
+    sweep_rank: int = 0                     # block choice of a blocked t-sweep (MPMC_OPT_SWEEP_RANK)
 
 
 @dataclass
@@ -66,6 +67,8 @@ class LatticeRun:
     setup_seconds: float = 0.0
     defl64_V: Optional[torch.Tensor] = None     # FP64 eigenvectors of the set-up
     composites: Dict[tuple, krylov.OuterRoots] = field(default_factory=dict)
+    # adaptive loop: per-level device stopping state and recorded one-batch steps (kept across calls)
+    adaptive: Dict[tuple, object] = field(default_factory=dict)
 
     # -- sampling --------------------------------------------------------
     def noise(self, level: int, sample_offset: Optional[torch.Tensor] = None) -> L.Noise:
@@ -81,6 +84,7 @@ class LatticeRun:
         device counter)."""
         lv = self.levels[level]
         L.set_option(L.OPT_PLANE_SWEEP, int(lv.sweep))
+        L.set_option(L.OPT_SWEEP_RANK, int(lv.sweep_rank))
         L.mlmc_level_estimate(self.dl, lv.device, nsamples, self.level_rb(level), nz, lv.samples[:nsamples],
                               lv.acc, lv.ws)
 
@@ -120,16 +124,17 @@ class LatticeRun:
             lv.acc.zero_()
             lv.drawn = 0
 
-    def set_level_shape(self, level: int, rb: int, sweep: bool):
-        """Choose the RHS block width and kernel family of one level (the
-        autotuner's knobs); resizes the level's workspace."""
+    def set_level_shape(self, level: int, rb: int, sweep: bool, rank: int = 0):
+        """Choose the RHS block width, kernel family and blocked-sweep block
+        rank of one level (the autotuner's knobs); resizes the level's
+        workspace."""
         lv = self.levels[level]
         if lv.solver is not None:
             raise ValueError("the block width of a solve level is fixed by its solver")
         N = lv.batch
         if N % rb:
             raise ValueError(f"rb={rb} does not divide {N}")
-        lv.rb, lv.sweep = int(rb), bool(sweep)
+        lv.rb, lv.sweep, lv.sweep_rank = int(rb), bool(sweep), int(rank)
         lv.ws = L.workspace(L.level_workspace_size(self.dl, lv.device, N, rb))
 
     def estimates(self):
@@ -493,20 +498,34 @@ class AdaptiveLevel:
     seconds: float
 
 
+def check_rule(level: int):
+    """(first, every) of a level's check points (check_points)."""
+    if level == 0:
+        return 2, 1
+    if level == 1:
+        return 3, 3
+    return 6, 3
+
+
 def run_to_tolerance(run: LatticeRun, eps: float, first_batch: int = 32,
-                     max_samples: int = 1 << 20, probe_last: bool = False) -> List[AdaptiveLevel]:
+                     max_samples: int = 1 << 20, probe_last: bool = False, graphs: bool = False,
+                     lookahead: int = 1) -> List[AdaptiveLevel]:
     """The multilevel Monte Carlo of Sec. 5 step 3 on the GPU: levels top
     first, each drawing batches of Z4 samples until its standard error falls
     to its share of eps (level_targets, given the errors of the levels before
-    it) at one of its check points.  Batches start at first_batch and double
-    up to the level's configured batch (a solve level always draws its full
-    batch).  The estimate of a level uses exactly the samples up to its
-    stopping point, as a one-at-a-time draw would; the rest of the last batch
-    is discarded.  With probe_last, the last level Tr p_d(A) is computed
-    exactly by probing with a distance-d colouring (Sec. 5 step 3d; its
-    standard error is 0) and eps is split over the Monte Carlo levels only.
-    Returns one AdaptiveLevel per level."""
-    from . import probing
+    it) at one of its check points.  The check runs on the device after every
+    batch (mpmc_level_stop_check: one sample at a time, so the estimate uses
+    exactly the samples up to the stopping point, as the paper's loop would);
+    the host reads back 128 bytes per batch, `lookahead` batches behind the
+    device (a batch enqueued after the stop is wasted work, not a wrong
+    result).  Batches start at first_batch and double up to the level's
+    configured batch (a solve level always draws its full batch).  With
+    graphs, each batch of a polynomial level is one launch of a step
+    recorded by the library (mpmc_batch_build: the level, its stopping check
+    and its sample counter).  With probe_last, the last level Tr p_d(A) is
+    computed exactly by probing with a distance-d colouring (Sec. 5 step 3d;
+    its standard error is 0) and eps is split over the Monte Carlo levels
+    only.  Returns one AdaptiveLevel per level."""
     out: List[AdaptiveLevel] = []
     errs: List[float] = []
     nl = len(run.levels)
@@ -515,6 +534,7 @@ def run_to_tolerance(run: LatticeRun, eps: float, first_batch: int = 32,
         raise ValueError("probing needs a last level Tr p_d(A) of a single polynomial")
     nmc = nl - 1 if probe_last else nl
     run.reset()
+    host = torch.zeros((lookahead + 1, 16), dtype=torch.float64, pin_memory=True)
     for li, lv in enumerate(run.levels):
         if li == nmc:
             t0 = time.perf_counter()
@@ -523,29 +543,90 @@ def run_to_tolerance(run: LatticeRun, eps: float, first_batch: int = 32,
             out.append(AdaptiveLevel(pr.probes, pr.probes, pr.trace, 0.0, 0.0, time.perf_counter() - t0))
             break
         target = level_targets(eps, errs + [0.0] * (nmc - len(errs)))[li]
+        first, every = check_rule(li)
         N = lv.batch
         rb = run.level_rb(li)
         batch = N if lv.solver is not None else max(rb, min(N, (first_batch // rb) * rb or rb))
-        chunks: List[np.ndarray] = []
-        have = 0
-        stop = None
+        state = run.adaptive.setdefault(("state", li), torch.zeros(16, dtype=torch.float64, device="cuda"))
+        state.zero_()
+        state[7] = float(target)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        while stop is None and have < max_samples:
-            run.draw(li, batch)
-            S = lv.samples[:batch].cpu().numpy()
-            chunks.append(S[:, 0] + 1j * S[:, 1])
-            allv = np.concatenate(chunks)
-            stop = stopping_index(allv, target, li, start=0 if have == 0 else have)
-            have += batch
-            if lv.solver is None and batch < N:
-                batch = min(N, 2 * batch)
-        allv = np.concatenate(chunks)
-        n = stop if stop is not None else len(allv)
-        sv = allv[:n]
-        mean = complex(sv.mean())
-        var = float(np.sum(np.abs(sv - mean) ** 2) / (n - 1)) if n > 1 else float("inf")
+        pending: List[tuple] = []
+        have, k, stopped = 0, 0, False
+        while True:
+            if have < max_samples:
+                if graphs and lv.solver is None:
+                    key = ("step", li, batch, first, every)
+                    if key not in run.adaptive:
+                        run.adaptive[key] = _stop_step(run, li, batch, state, first, every)
+                    h, ctr = run.adaptive[key]
+                    ctr.fill_(have)
+                    L.batch_launch(h)
+                    lv.drawn += batch
+                else:
+                    run.draw(li, batch)
+                    L.level_stop_check(lv.samples, batch, first, every, state)
+                slot = host[k % (lookahead + 1)]
+                slot.copy_(state, non_blocking=True)
+                ev = torch.cuda.Event()
+                ev.record()
+                pending.append((ev, slot))
+                have += batch
+                k += 1
+                if lv.solver is None and batch < N:
+                    batch = min(N, 2 * batch)
+            if not pending:
+                break
+            if len(pending) > lookahead or have >= max_samples:
+                ev, slot = pending.pop(0)
+                ev.synchronize()
+                if slot[4].item() != 0.0:
+                    stopped = True
+                    break
+        torch.cuda.synchronize()
+        st = state.cpu().numpy()
+        if stopped or st[4] != 0.0:
+            n, mean, m2 = int(st[5]), complex(st[8], st[9]), float(st[10])
+        else:
+            n, mean, m2 = int(st[0]), complex(st[1], st[2]), float(st[3])
         corr = complex(np.sum(lv.c)) if lv.c is not None else 0.0
-        se = float(np.sqrt(var / n))
+        se = float(np.sqrt(m2 / (n - 1) / n)) if n > 1 else float("inf")
         errs.append(se)
         out.append(AdaptiveLevel(n, have, mean + corr, se, float(target), time.perf_counter() - t0))
     return out
+
+
+def prepare_adaptive(run: LatticeRun, first_batch: int = 32):
+    """Record, ahead of a timed run_to_tolerance(graphs=True), every
+    one-batch step the adaptive loop can launch (batch sizes first_batch
+    doubling to each polynomial level's batch): recording is set-up."""
+    for li, lv in enumerate(run.levels):
+        if lv.solver is not None:
+            continue
+        state = run.adaptive.setdefault(("state", li), torch.zeros(16, dtype=torch.float64, device="cuda"))
+        first, every = check_rule(li)
+        rb, N = run.level_rb(li), lv.batch
+        batch = max(rb, min(N, (first_batch // rb) * rb or rb))
+        while True:
+            key = ("step", li, batch, first, every)
+            if key not in run.adaptive:
+                run.adaptive[key] = _stop_step(run, li, batch, state, first, every)
+            if batch >= N:
+                break
+            batch = min(N, 2 * batch)
+
+
+def _stop_step(run: LatticeRun, level: int, batch: int, state: torch.Tensor, first: int, every: int):
+    """A recorded one-level step for the adaptive loop: one batch of `batch`
+    samples starting at the sample counter, its stopping check, the counter
+    advanced (mpmc_batch_build)."""
+    lv = run.levels[level]
+    ctr = torch.zeros(1, dtype=torch.int64, device="cuda")
+    h = L.Handle()
+    item = L.BatchItem(run.dl, lv.device, batch, run.level_rb(level),
+                       L.Noise(run.cfg.seed_noise, run.cfg.lattice_id, lv.index, 0), ctr, 1, lv.samples[:batch],
+                       lv.acc, lv.ws, 0, int(lv.sweep), int(lv.sweep_rank), state, first, every)
+    L.batch_build(h, [item])
+    return h, ctr
+

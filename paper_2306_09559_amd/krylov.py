@@ -367,7 +367,7 @@ def pp_arnoldi_deflation(dl: L.DeviceLattice, pin: L.DevicePoly, start: np.ndarr
     UAV = torch.empty((ka, kpa), dtype=torch.complex128, device="cuda")
     L.deflate_project(dl, defl, L.DEFL_COEFF, kpa, kpa, AV, None, None, UAV, None, None, wsc)
     Hm = UAV.cpu().numpy()[:, :ka]
-    defl.hinv = _c(np.linalg.inv(Hm))
+    defl.hinv = _c(L.small_inverse(Hm))       # MpmcError(ESINGULAR) for a singular U^H A V
     torch.cuda.synchronize()
     ritz = None
     if keep_candidates:

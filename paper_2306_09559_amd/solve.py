@@ -42,12 +42,16 @@ class SolveStats:
     tol: float = 0.0
 
 
-class SolveNotConverged(RuntimeError):
-    """A top-level solve ended above its tolerance (its samples would be biased)."""
+class SolveNotConverged(L.MpmcError):
+    """A top-level solve ended above its tolerance (its samples would be
+    biased); status MPMC_ENOTCONVERGED."""
 
     def __init__(self, stats: "SolveStats"):
-        super().__init__(f"PP-GMRES did not converge: max relative residual {float(np.max(stats.rel_res)):.3e} "
-                         f"> tolerance {stats.tol:.1e} after {stats.outer} refinement steps, {stats.cycles} cycles")
+        RuntimeError.__init__(self, f"PP-GMRES did not converge: max relative residual "
+                                    f"{float(np.max(stats.rel_res)):.3e} > tolerance {stats.tol:.1e} after "
+                                    f"{stats.outer} refinement steps, {stats.cycles} cycles "
+                                    f"({L.status_string(L.ENOTCONVERGED)})")
+        self.status = L.ENOTCONVERGED
         self.stats = stats
 
 

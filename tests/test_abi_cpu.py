@@ -33,8 +33,9 @@ def test_exports_every_declared_symbol(L):
 
 
 def test_status_strings(L):
-    for st in (L.OK, L.EINVAL, L.EUNSUPPORTED, L.EWORKSPACE, L.EHIP):
-        assert L.status_string(st)
+    texts = [L.status_string(st) for st in (L.OK, L.EINVAL, L.EUNSUPPORTED, L.EWORKSPACE, L.EHIP, L.ESINGULAR,
+                                            L.ENOTCONVERGED)]
+    assert len(set(texts)) == len(texts) and "unknown" not in " ".join(texts)
     assert "gfx950" in L.build_info()
 
 
@@ -143,3 +144,33 @@ def test_workspace_too_small_is_rejected_on_the_host(L):
     st = lib.mpmc_poly_apply(ctypes.byref(lat), ctypes.byref(poly), sh, None, ctypes.byref(nz), y, None, ws, need,
                              None)
     assert st == L.EUNSUPPORTED
+
+
+def test_small_inverse(L):
+    """mpmc_small_inverse (host): the inverse of a random complex matrix, a
+    pivot that needs row exchanges, and ESINGULAR for a rank-deficient one."""
+    import numpy as np
+    rng = np.random.default_rng(4)
+    a = rng.standard_normal((20, 20)) + 1j * rng.standard_normal((20, 20))
+    assert np.max(np.abs(L.small_inverse(a) @ a - np.eye(20))) < 1e-12
+    p = np.array([[0, 1j], [2.0, 0]])
+    assert np.allclose(L.small_inverse(p) @ p, np.eye(2), atol=1e-15)
+    s = a.copy()
+    s[3] = 2.0 * s[7]
+    with pytest.raises(L.MpmcError) as e:
+        L.small_inverse(s)
+    assert e.value.status == L.ESINGULAR
+
+
+def test_batch_and_tuner_reject_on_host(L):
+    """mpmc_batch_build, mpmc_batch_launch and mpmc_autotune validate their
+    arguments before any device work."""
+    h = L.Handle()
+    assert L._lib.mpmc_batch_launch(h.ptr, None) == L.EINVAL
+    assert L._lib.mpmc_batch_build(h.ptr, None, 1) == L.EINVAL
+    items = (L.mpmc_batch_item * 1)()
+    assert L._lib.mpmc_batch_build(h.ptr, items, 1) == L.EINVAL          # no lattice
+    assert L._lib.mpmc_batch_build(None, items, 1) == L.EINVAL
+    assert L._lib.mpmc_autotune(None, None, None, 1, None, 1, 0.0, None, 0, None, None, None, None, 0, None,
+                                None) == L.EINVAL
+    h.close()

@@ -1,0 +1,120 @@
+"""The adaptive multilevel loop of Sec. 5 step 3 on the device against the
+oracle's stopping rule and estimator.
+
+* mpmc_level_stop_check on given samples, fed in batches of uneven size:
+  the stopping point is the oracle's first check point (estimator.check_points)
+  at which the standard error of estimator.level_estimate is at most the
+  target, and the recorded mean and M2 are those of exactly the samples up to
+  it.
+* driver.run_to_tolerance on a three-level 4^4 workload, eagerly and with
+  every batch a recorded step (mpmc_batch_build): both give the same stopping
+  points and estimates bit for bit, and they are the oracle's -- its own
+  samples b^H p_hi(A) b - b^H p_lo(A) b of the same Z4 vectors and roots, its
+  level tolerances (eps/sqrt(3), sqrt(eps^2 - e^2)/sqrt(2), sqrt(eps^2 - e^2)),
+  check points and level estimates.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import estimator
+
+from gpu_helpers import lib
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _oracle_stop(s, target, level):
+    """Oracle stopping point (1-based count) and estimate, or (None, None)."""
+    for n in estimator.check_points(level, len(s)):
+        est = estimator.level_estimate(s[:n])
+        if est.stderr <= target:
+            return n, est
+    return None, None
+
+
+@pytest.mark.parametrize("level,first,every", [(1, 2, 1), (2, 3, 3), (3, 6, 3)])
+def test_stop_check_is_the_oracle_rule(level, first, every):
+    L = lib()
+    rng = np.random.default_rng(10 + level)
+    total = 600
+    s = (rng.standard_normal(total) * 3.0 + 5.0) + 1j * (rng.standard_normal(total) + 1.0)
+    # a target the running error crosses inside the stream
+    target = float(np.sqrt(np.var(s) * 1.0 / 240))
+    n_ora, est = _oracle_stop(s, target, level)
+    assert n_ora is not None and 6 < n_ora < total
+    state = torch.zeros(16, dtype=torch.float64, device="cuda")
+    state[7] = target
+    pos = 0
+    for b in [7, 64, 1, 33, 128, 200, 167]:             # uneven batches
+        S = np.zeros((b, 6))
+        S[:, 0], S[:, 1] = s[pos:pos + b].real, s[pos:pos + b].imag
+        L.level_stop_check(torch.from_numpy(S).cuda(), b, first, every, state)
+        pos += b
+    torch.cuda.synchronize()
+    st = state.cpu().numpy()
+    assert pos == total and st[4] == 1.0
+    assert int(st[5]) == n_ora
+    assert abs(complex(st[8], st[9]) - est.mean) <= 1e-13 * abs(est.mean)
+    assert abs(st[10] - est.var * (n_ora - 1)) <= 1e-11 * est.var * (n_ora - 1)
+    # the state froze at the stop: later batches change nothing
+    assert int(st[0]) == n_ora
+
+
+def _three_levels():
+    from synth.configs import C1, Level
+    return dataclasses.replace(C1, name="C1a", levels=(Level(20, 10, 64), Level(10, 4, 64), Level(4, None, 64)))
+
+
+def test_adaptive_driver_matches_the_oracle():
+    L = lib()
+    from paper_2306_09559_amd import driver
+    cfg = _three_levels()
+    run = driver.build(cfg, prec=L.F64, rb=16)
+    ol = oracle.Lattice(cfg.dims, cfg.kappa, synth.gauge_links(cfg.dims, cfg.eps, cfg.seed_links),
+                        cfg.antiperiodic_t)
+    roots = run.roots.inv_roots
+    nmax = 4096
+
+    def ora_samples(li, n):
+        lv = cfg.levels[li]
+        B = oracle.z4(cfg.seed_noise, cfg.lattice_id, run.levels[li].index, 0, n, ol.V)
+        _, h = ol.poly_apply(roots[lv.hi], B)
+        lo = ol.poly_apply(roots[lv.lo], B)[1] if lv.lo is not None else 0.0
+        return h - lo
+
+    # eps such that the level of largest variance needs about a thousand samples
+    var = []
+    for li in range(3):
+        pilot = ora_samples(li, 256)
+        var.append(float(np.sum(np.abs(pilot - pilot.mean()) ** 2) / 255))
+    eps = float(np.sqrt(3.0 * max(var) / 1000.0))
+    res_e = driver.run_to_tolerance(run, eps, max_samples=nmax)
+    driver.prepare_adaptive(run)
+    res_g = driver.run_to_tolerance(run, eps, max_samples=nmax, graphs=True)
+    errs = []
+    for li in range(3):
+        a, g = res_e[li], res_g[li]
+        print(f"level {li}: n {a.n} of {a.drawn} drawn, target {a.target:.4g}, stderr {a.stderr:.4g}")
+        assert (a.n, a.estimate, a.stderr, a.target) == (g.n, g.estimate, g.stderr, g.target)
+        assert a.n < a.drawn <= nmax                      # stopped inside the drawn batches
+        s = ora_samples(li, a.drawn)
+        tol = estimator.level_tolerances(eps, errs)[li]
+        assert abs(tol - a.target) <= 1e-12 * tol
+        n, est = _oracle_stop(s, tol, li + 1)
+        assert n == a.n, (li, n, a.n)
+        scale = float(np.mean(np.abs(s[:n])))
+        assert abs(a.estimate - est.estimate) <= 1e-11 * scale
+        assert abs(a.stderr - est.stderr) <= 1e-10 * est.stderr
+        errs.append(est.stderr)
+    assert np.sqrt(sum(e * e for e in errs)) <= eps * (1 + 1e-12)

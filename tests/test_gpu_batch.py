@@ -106,23 +106,60 @@ def test_autotune_keeps_values(tmp_path):
 
 def test_autotune_offers_the_blocked_sweep(tmp_path):
     """On an FP32 lattice whose xyz-plane exceeds one workgroup (16^3 planes:
-    the t-sweep cuts them into blocks with a halo), the candidates include
-    the blocked t-sweep, and the tuner keeps it when it is the faster shape."""
+    the t-sweep cuts them into blocks with a halo), mpmc_autotune times the
+    blocked t-sweep with its best-ranked blocks next to the streaming kernel,
+    and keeps the sweep when it is the faster shape; the chosen block rank
+    changes the plan's block and leaves the level's values alone."""
     from paper_2306_09559_amd import driver
-    from paper_2306_09559_amd.batch import _candidates, autotune
+    from paper_2306_09559_amd.batch import autotune
     from synth.configs import Level
     L = lib()
     cfg = dataclasses.replace(_small_cfgs()[0], name="C1p", dims=(16, 16, 16, 4), kappa=0.14,
                               levels=(Level(12, None, 64),), seed_links=121, lattice_id=12)
     run = driver.build(cfg, prec=L.F32, rb=16)
     assert L.sweep_plan(run.dl, 64, 16)["halo"]
-    cands = _candidates(run, 0)
-    assert (16, True) in cands and (16, False) in cands
+    L.set_option(L.OPT_SWEEP_RANK, 1)
+    second = L.sweep_plan(run.dl, 64, 16)
+    L.set_option(L.OPT_SWEEP_RANK, 0)
+    assert second["ok"] and second["block"] != L.sweep_plan(run.dl, 64, 16)["block"]
+    run.step()
+    torch.cuda.synchronize()
+    ref = run.levels[0].samples.cpu().numpy().copy()
     res = autotune(run, reps=3, use_cache=False, cache_path=str(tmp_path / "t.json"))
     t = res.timings[0]
     print(t)
-    best_sweep = min(v for k, v in t.items() if k.endswith("-sweep"))
-    best_stream = min(v for k, v in t.items() if not k.endswith("-sweep"))
+    assert {"rb16", "rb16-sweep", "rb16-sweep1"} <= set(t)
+    best_sweep = min(v for k, v in t.items() if "-sweep" in k)
+    best_stream = min(v for k, v in t.items() if "-sweep" not in k)
     # the blocked sweep moves ~1.7x the streaming kernel's bytes per second on these planes
     assert best_sweep < best_stream
     assert res.choice[0][1]
+    run.step()
+    torch.cuda.synchronize()
+    got = run.levels[0].samples.cpu().numpy()
+    assert np.max(np.abs(got - ref)) <= 1e-6 * np.max(np.abs(ref))
+
+
+def test_batch_entry_points_validate(tmp_path):
+    """mpmc_batch_build rejects a solve level, a missing counter and a short
+    workspace before recording anything; mpmc_batch_launch needs a built step."""
+    from paper_2306_09559_amd import driver
+    L = lib()
+    run = driver.build(_small_cfgs()[1], prec=0, rb=8)
+    lv = run.levels[0]
+    h = L.Handle()
+    with pytest.raises(L.MpmcError) as e:
+        L.batch_launch(h)
+    assert e.value.status == L.EINVAL
+    ctr = torch.zeros(1, dtype=torch.int64, device="cuda")
+    good = dict(lat=run.dl, level=lv.device, nrhs=lv.batch, rb=8, noise=L.Noise(1, 2, 3, 0), counter=ctr,
+                batches=1, samples=lv.samples, acc=lv.acc, ws=lv.ws)
+    with pytest.raises(L.MpmcError) as e:
+        L.batch_build(h, [L.BatchItem(**dict(good, ws=lv.ws[:16]))])
+    assert e.value.status == L.EWORKSPACE
+    solve = L.DeviceLevel(L.OP_SOLVE, None, solve_x=lv.samples)
+    with pytest.raises(L.MpmcError) as e:
+        L.batch_build(h, [L.BatchItem(**dict(good, level=solve))])
+    assert e.value.status == L.EUNSUPPORTED
+    L.batch_build(h, [L.BatchItem(**good)])
+    h.close()
