@@ -473,6 +473,22 @@ int mpmc_autotune(mpmc_handle h, const mpmc_lattice *lat, const mpmc_level *leve
  * written to out then); a and out may not overlap. */
 int mpmc_small_inverse(int32_t k, const double *a, double tiny, double *out);
 
+/* ---- a level entry point that allocates nothing -------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, semantics and results (bit for bit) as mpmc_mlmc_level_estimate
+ * without ws/ws_bytes: the workspace is a static device array of
+ * mpmc_noalloc_scratch_bytes() bytes (64 MiB) that the library holds on
+ * every GPU it runs on until the process ends.  A level whose
+ * mpmc_level_workspace_size exceeds it returns MPMC_EWORKSPACE before
+ * anything is enqueued.  The call allocates nothing (no hipMalloc, no
+ * allocating library routine).  Every call on one GPU shares that GPU's
+ * array: calls that may overlap on one GPU (different streams or threads)
+ * race on it; serialise them.  Nothing in the array has to start at zero. */
+size_t mpmc_noalloc_scratch_bytes(void);
+int mpmc_mlmc_level_estimate_noalloc(const mpmc_lattice *lat, const mpmc_level *level, mpmc_shape shape,
+                                     const mpmc_noise *noise, double *samples, double *acc, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -120,6 +120,9 @@ _sig = {
                                      P(c_i32), c_vp]),
     "mpmc_small_inverse": (ctypes.c_int, [c_i32, c_vp, c_f64, c_vp]),
     "mpmc_level_stop_check": (ctypes.c_int, [c_vp, c_i32, c_i32, c_i32, c_vp, c_vp]),
+    "mpmc_noalloc_scratch_bytes": (c_size, []),
+    "mpmc_mlmc_level_estimate_noalloc": (ctypes.c_int, [P(mpmc_lattice), P(mpmc_level), mpmc_shape, P(mpmc_noise),
+                                                        c_vp, c_vp, c_vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -430,6 +433,22 @@ def deflate_project(lat: DeviceLattice, defl: DeviceDefl, mode: int, nrhs: int, 
     _check("mpmc_deflate_project", _lib.mpmc_deflate_project(
         ctypes.byref(L), ctypes.byref(D), int(mode), mpmc_shape(nrhs, rb), _ptr(b),
         ctypes.byref(nz) if nz else None, _ptr(zeta), _ptr(omega), _ptr(d), _ptr(X), _ptr(ws), ws.numel(),
+        _stream()))
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(_lib.mpmc_noalloc_scratch_bytes())
+
+
+def mlmc_level_estimate_noalloc(lat: DeviceLattice, level: DeviceLevel, nrhs: int, rb: int, noise: Noise,
+                                samples: torch.Tensor, acc: torch.Tensor):
+    """mpmc_mlmc_level_estimate with the library's static device scratch as
+    the workspace (no allocation; calls on one GPU must not overlap)."""
+    L = lat.c()
+    lv, _keep = level.cstruct()
+    nz = noise.c()
+    _check("mpmc_mlmc_level_estimate_noalloc", _lib.mpmc_mlmc_level_estimate_noalloc(
+        ctypes.byref(L), ctypes.byref(lv), mpmc_shape(nrhs, rb), ctypes.byref(nz), _ptr(samples), _ptr(acc),
         _stream()))
 
 

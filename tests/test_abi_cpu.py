@@ -174,3 +174,20 @@ def test_batch_and_tuner_reject_on_host(L):
     assert L._lib.mpmc_autotune(None, None, None, 1, None, 1, 0.0, None, 0, None, None, None, None, 0, None,
                                 None) == L.EINVAL
     h.close()
+
+
+def test_noalloc_rejects_a_level_beyond_its_scratch(L):
+    """The no-allocation level entry point refuses, on the host, a level whose
+    workspace exceeds its static scratch (8^4 x 256 vectors in FP64)."""
+    c_i32 = ctypes.c_int32
+    fake = ctypes.c_void_p(256)                      # never dereferenced: the size check comes first
+    lat = L.mpmc_lattice((c_i32 * 4)(8, 8, 8, 8), 0, L.F64, 0.13, fake, 3)
+    poly = L.mpmc_poly(3, 0, fake, None)
+    lv = L.mpmc_level(L.OP_POLY, L.OP_NONE, poly, L.mpmc_poly(0, 0, None, None), None, 0, None, None)
+    shape = L.mpmc_shape(256, 16)
+    need = L._lib.mpmc_level_workspace_size(ctypes.byref(lat), ctypes.byref(lv), shape)
+    assert need > L.noalloc_scratch_bytes() == 64 << 20
+    nz = L.mpmc_noise(1, 1, 1, 0, None, None)
+    st = L._lib.mpmc_mlmc_level_estimate_noalloc(ctypes.byref(lat), ctypes.byref(lv), shape, ctypes.byref(nz),
+                                                 fake, fake, None)
+    assert st == L.EWORKSPACE
