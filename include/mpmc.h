@@ -161,9 +161,12 @@ const char *mpmc_build_info(void);
  *     one workgroup, the t-sweep cuts the plane into xyz-blocks with a halo
  *     in LDS; the candidate blocks are ranked by the bytes each moves per
  *     site, and this option picks the rank-th (clamped to the last).
+ *   MPMC_OPT_HOP_SLAB     1 (default): the streaming kernel hands each XCD a
+ *     z-slab of the lattice swept along t (neighbours stay in its L2);
+ *     0: each XCD takes a contiguous range of tiles in site order.
  * Every choice computes the same values up to the order of floating-point
- * sums. */
-enum { MPMC_OPT_PLANE_SWEEP = 1, MPMC_OPT_SWEEP_RANK = 2 };
+ * sums (the work order changes no value at all). */
+enum { MPMC_OPT_PLANE_SWEEP = 1, MPMC_OPT_SWEEP_RANK = 2, MPMC_OPT_HOP_SLAB = 3 };
 int mpmc_set_option(int32_t option, int32_t value);
 
 /* Which t-sweep a scalar-mode polynomial on this lattice and batch would

@@ -25,7 +25,10 @@ namespace mpmc {
 template <typename T> struct HopArgs {
     Geo g;
     int rb, spw, nblk;
-    unsigned G;                 // logical workgroups
+    unsigned G;                 // workgroups of the launch
+    // work order (see hop_tile): slab = 1 when each XCD sweeps t over its own
+    // z-slab of the xyz-plane: tps tiles per xyz-plane, chunk of them per XCD
+    int slab, tps, chunk;
     const cplx_t<T> *in;        // input field; unused when the input is noise
     cplx_t<T> *out;
     const cplx_t<T> *gauge;     // [mu][9][V]
@@ -266,12 +269,41 @@ __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
 
 }  // namespace
 
+// The tile (RHS block nbk, site tile sblk) of hardware workgroup h, and
+// whether h has one.  A tile is spw consecutive sites of one RHS block.
+// Workgroups are dispatched round-robin over the 8 XCDs, and each XCD works
+// through its own ones in order.  With slab = 1 the tiles of each xyz-plane
+// are cut into 8 chunks (a z-slab each) and XCD x walks t = 0, 1, .. over its
+// chunk, so the +-t neighbours of the sites it runs were read just before (or
+// are read just after) by the same XCD and hit its L2; only the slab's two
+// z-faces come from another XCD.  (A plain range of tiles in site order per
+// XCD, the order without slab, evicts the t-neighbours: they are a whole
+// xyz-plane of reads apart.)
+template <typename T>
+__device__ __forceinline__ bool hop_tile(const HopArgs<T> &a, unsigned h, int &nbk, int &sblk) {
+    if (!a.slab) {
+        const unsigned L = xcd_remap(h, a.G);
+        nbk = (int)(L / (unsigned)a.nblk);
+        sblk = (int)(L % (unsigned)a.nblk);
+        return true;
+    }
+    const unsigned x = h % kXcds, k = h / kXcds;
+    const unsigned per_t = (unsigned)a.chunk, per_blk = (unsigned)a.g.L[3] * per_t;
+    nbk = (int)(k / per_blk);
+    const unsigned rem = k % per_blk;
+    const int t = (int)(rem / per_t);
+    const int tile = (int)(x * per_t + rem % per_t);
+    sblk = t * a.tps + tile;
+    return tile < a.tps;
+}
+
 template <typename T, bool IN_Z4, bool DOT, bool YACC, bool OUTER, bool ADDB>
 __global__ void __launch_bounds__(kBlock) k_hop(HopArgs<T> a) {
     using C = cplx_t<T>;
     __shared__ double2 red[DOT ? kBlock : 1];
-    const unsigned L = xcd_remap(blockIdx.x, a.G);
-    const int nbk = (int)(L / (unsigned)a.nblk), sblk = (int)(L % (unsigned)a.nblk);
+    int nbk, sblk;
+    if (!hop_tile<T>(a, blockIdx.x, nbk, sblk)) return;    // a padding workgroup (uniform)
+    const unsigned L = (unsigned)nbk * (unsigned)a.nblk + (unsigned)sblk;
     const int lane = (int)threadIdx.x;
     const int jr = lane & (a.rb - 1), ls = lane / a.rb;
     const int s = sblk * a.spw + ls;
@@ -401,8 +433,9 @@ template <typename T, bool IN_Z4>
 __global__ void __launch_bounds__(kBlock) k_scale_dot(HopArgs<T> a) {
     using C = cplx_t<T>;
     __shared__ double2 red[kBlock];
-    const unsigned L = xcd_remap(blockIdx.x, a.G);
-    const int nbk = (int)(L / (unsigned)a.nblk), sblk = (int)(L % (unsigned)a.nblk);
+    int nbk, sblk;
+    if (!hop_tile<T>(a, blockIdx.x, nbk, sblk)) return;    // a padding workgroup (uniform)
+    const unsigned L = (unsigned)nbk * (unsigned)a.nblk + (unsigned)sblk;
     const int lane = (int)threadIdx.x;
     const int jr = lane & (a.rb - 1), ls = lane / a.rb;
     const int s = sblk * a.spw + ls;
@@ -462,6 +495,14 @@ template <typename T> static HopArgs<T> base_args(const mpmc_lattice &lat, mpmc_
     a.spw = t.spw;
     a.nblk = t.nblk;
     a.G = t.groups();
+    // slab order when whole tiles cover an xyz-plane at least once per XCD
+    const int P = lat.dims[0] * lat.dims[1] * lat.dims[2];
+    if (g_opt_hop_slab && P % t.spw == 0 && P / t.spw >= kXcds) {
+        a.slab = 1;
+        a.tps = P / t.spw;
+        a.chunk = (a.tps + kXcds - 1) / kXcds;
+        a.G = (unsigned)kXcds * (unsigned)t.nb * (unsigned)lat.dims[3] * (unsigned)a.chunk;
+    }
     a.gauge = (const cplx_t<T> *)lat.gauge;
     a.two_rows = lat.link_rows == 2;
     a.kappa = lat.kappa;

@@ -60,6 +60,7 @@ int sweep_chain_t(const mpmc_lattice &lat, mpmc_shape sh, const SweepPlan &plan,
 // and the autotuner set them around each enqueue and restore them after
 extern int g_opt_sweep;
 extern int g_opt_sweep_rank;
+extern int g_opt_hop_slab;
 
 template <typename T>
 int poly_apply_t(const mpmc_lattice &, const mpmc_poly &, mpmc_shape, const void *x, const mpmc_noise *noise, void *y,

@@ -636,3 +636,45 @@ def test_vector_mode_sweep(dims, prec, nrhs, field_in, dot):
         assert err < (1e-12 if prec == 0 else 8 * deg * newton_amplification(ol.apply, t, x[None, :]) * U32)
         if dot:
             assert abs(bs[1][r] - np.vdot(x, want)) <= 1e-12 * abs(np.vdot(x, want))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_streaming_work_order_changes_no_value(prec):
+    """The streaming kernel's slab work order (each XCD a z-slab swept along
+    t) only reorders workgroups: A x, scalar-mode and vector-mode polynomials
+    and the double polynomial are bit-identical to the plain order, and
+    match the oracle."""
+    L = lib()
+    # 16 tiles per xyz-plane (the slab order applies), 9 RHS blocks
+    dims, N, rb = (8, 8, 8, 6), 72, 8
+    dl, ol = device_lattice(dims, 0.14, 0.4, 81, True, prec=prec)
+    V = dl.V
+    X = synth.random_fields(N, V, 82).reshape(N, -1)
+    x = pack(dims, X, rb, prec)
+    t = krylov.gmres_polys(ol.apply, synth.gaussian_start(ol.n, 83), [5]).inv_roots[5]
+    t_out = np.array([0.7, 0.5 + 0.1j, 0.9])
+    single, comp = L.DevicePoly(dev_c128(t)), L.DevicePoly(dev_c128(t), dev_c128(t_out))
+    L.set_option(L.OPT_PLANE_SWEEP, 0)
+    got = {}
+    for slab in (0, 1):
+        L.set_option(L.OPT_HOP_SLAB, slab)
+        y = L.empty_field(V, N, rb, prec)
+        L.wilson_apply(dl, x, y)
+        ys, bs, bc = L.empty_field(V, N, rb, prec), [], []
+        for poly, out in ((single, bs), (comp, bc)):
+            ws = L.workspace(L.poly_workspace_size(dl, poly, N, rb))
+            bhy = torch.empty(N, dtype=torch.complex128, device="cuda")
+            L.poly_apply(dl, poly, N, rb, None, L.Noise(8, 1, 2, 0), ys if poly is single else None, bhy, ws)
+            torch.cuda.synchronize()
+            out.append(bhy.cpu().numpy())
+        got[slab] = (unpack(dims, y, prec), unpack(dims, ys, prec), bs[0], bc[0])
+    L.set_option(L.OPT_HOP_SLAB, 1)
+    L.set_option(L.OPT_PLANE_SWEEP, 1)
+    for a, b in zip(got[0], got[1]):
+        assert np.array_equal(a, b)
+    R = ol.apply(X)
+    for r in (0, N - 1):
+        assert rel(got[1][0][r], R[r]) < (1e-13 if prec == 0 else 1e-6)
+    _, ref = ol.poly_apply(t, oracle.z4(8, 1, 2, 0, N, V))
+    bound = 1e-12 if prec == 0 else 8 * 5 * newton_amplification(ol.apply, t, oracle.z4(8, 1, 2, 0, 2, V)) * U32
+    assert np.max(np.abs(got[1][2] - ref) / np.abs(ref)) < bound
