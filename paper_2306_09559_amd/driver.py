@@ -516,9 +516,11 @@ def run_to_tolerance(run: LatticeRun, eps: float, first_batch: int = 32,
     it) at one of its check points.  The check runs on the device after every
     batch (mpmc_level_stop_check: one sample at a time, so the estimate uses
     exactly the samples up to the stopping point, as the paper's loop would);
-    the host reads back 128 bytes per batch, `lookahead` batches behind the
-    device (a batch enqueued after the stop is wasted work, not a wrong
-    result).  Batches start at first_batch and double up to the level's
+    the host reads back 128 bytes per batch.  Up to `lookahead` further
+    batches are enqueued before a batch's check is read, but only while the
+    running error predicts that the samples already enqueued fall short of
+    the target (a batch enqueued after the stop would be wasted work, not a
+    wrong result).  Batches start at first_batch and double up to the level's
     configured batch (a solve level always draws its full batch).  With
     graphs, each batch of a polynomial level is one launch of a step
     recorded by the library (mpmc_batch_build: the level, its stopping check
@@ -554,8 +556,13 @@ def run_to_tolerance(run: LatticeRun, eps: float, first_batch: int = 32,
         t0 = time.perf_counter()
         pending: List[tuple] = []
         have, k, stopped = 0, 0, False
+        need = None             # samples the running error predicts, from the last state read
         while True:
-            if have < max_samples:
+            # enqueue when nothing is in flight, or (pipelined) when the samples already enqueued
+            # are predicted not to reach the target, so the next batch is not wasted work
+            more = have < max_samples and (not pending or (len(pending) <= lookahead and need is not None
+                                                            and need > have))
+            if more:
                 if graphs and lv.solver is None:
                     key = ("step", li, batch, first, every)
                     if key not in run.adaptive:
@@ -576,14 +583,17 @@ def run_to_tolerance(run: LatticeRun, eps: float, first_batch: int = 32,
                 k += 1
                 if lv.solver is None and batch < N:
                     batch = min(N, 2 * batch)
+                continue
             if not pending:
                 break
-            if len(pending) > lookahead or have >= max_samples:
-                ev, slot = pending.pop(0)
-                ev.synchronize()
-                if slot[4].item() != 0.0:
-                    stopped = True
-                    break
+            ev, slot = pending.pop(0)
+            ev.synchronize()
+            if slot[4].item() != 0.0:
+                stopped = True
+                break
+            n_read, m2 = float(slot[0].item()), float(slot[3].item())
+            if n_read >= 2 and target > 0:
+                need = int(np.ceil(m2 / (n_read - 1) / target ** 2))     # n with stderr^2 = var / n = target^2
         torch.cuda.synchronize()
         st = state.cpu().numpy()
         if stopped or st[4] != 0.0:
