@@ -49,10 +49,11 @@ def parse():
                     help="skip the 24^3x48 four-level workload (set-up ~20 s, ~190 GiB of HBM)")
     ap.add_argument("--cpu-baseline-only", action="store_true",
                     help="print only the oracle's CPU rate (used for the one-thread figure)")
-    ap.add_argument("--probe", choices=["gemm", "hop"], default=None,
+    ap.add_argument("--probe", choices=["gemm", "hop", "sweep"], default=None,
                     help="measurement helper for profiling runs: time the deflation GEMMs at the 8^4 and "
-                         "24^3x48 workloads' sizes (gemm), or the streaming kernel on the 16^4 / 12^3x24 / "
-                         "24^3x48 lattices (hop), then exit")
+                         "24^3x48 workloads' sizes (gemm), the streaming kernel on the 16^4 / 12^3x24 / "
+                         "24^3x48 lattices (hop), or the blocked FP32 t-sweep on 24^3x48 and 16^4 (sweep), "
+                         "then exit")
     ap.add_argument("--reps", type=int, default=10, help="repetitions of each probe call")
     ap.add_argument("--hop-orders", default="0,1",
                     help="work orders (MPMC_OPT_HOP_SLAB values) the hop probe times, comma-separated")
@@ -256,6 +257,51 @@ def probe_hop(reps: int, orders=(0, 1)):
         torch.cuda.empty_cache()
     L.set_option(L.OPT_HOP_SLAB, 1)
     L.set_option(L.OPT_PLANE_SWEEP, 1)
+    return out
+
+
+def probe_sweep(reps: int):
+    """The blocked FP32 t-sweep (scalar-mode Newton steps of a degree-10
+    polynomial) on the 24^3x48 lattice at 256 and 32 vectors and on 16^4 x
+    16 vectors, for each of the first three ranked blocks
+    (MPMC_OPT_SWEEP_RANK).  Algorithmic bytes as for the streaming probe."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2306_09559_amd import _lib as L
+    cases = [((24, 24, 24, 48), 256, 16), ((24, 24, 24, 48), 32, 16), ((16, 16, 16, 16), 16, 16)]
+    out = []
+    for dims, N, rb in cases:
+        V = int(np.prod(dims))
+        csz = 8
+        U = synth.gauge_links(dims, 0.5, 7)
+        g = torch.empty(36 * V, dtype=L.complex_dtype(L.F32), device="cuda")
+        L.pack_gauge(dims, L.F32, torch.from_numpy(U).cuda(), g)
+        del U
+        dl = L.DeviceLattice(dims, 0.14, True, L.F32, g, 2)
+        poly = L.DevicePoly(torch.from_numpy(np.linspace(0.3, 0.9, 11) + 0.05j).cuda())
+        ws = L.workspace(L.poly_workspace_size(dl, poly, N, rb))
+        bhy = torch.empty(N, dtype=torch.complex128, device="cuda")
+        nz = L.Noise(1, 2, 3, 0)
+        byts = (9 * V * N * 24 * csz + V * N * 12 * csz) // 10 + V * 24 * csz
+        for rank in (0, 1, 2):
+            L.set_option(L.OPT_SWEEP_RANK, rank)
+            plan = L.sweep_plan(dl, N, rb)
+            L.poly_apply(dl, poly, N, rb, None, nz, None, bhy, ws)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                L.poly_apply(dl, poly, N, rb, None, nz, None, bhy, ws)
+            e1.record()
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / (reps * 10)
+            out.append({"dims": list(dims), "N": N, "rb": rb, "rank": rank, "plan": plan,
+                        "bytes_per_launch": byts, "us_per_launch": round(us, 2), "GBps": round(byts / us / 1e3, 1)})
+            print(json.dumps(out[-1]), file=sys.stderr, flush=True)
+        del ws, g
+        torch.cuda.empty_cache()
+    L.set_option(L.OPT_SWEEP_RANK, 0)
     return out
 
 
@@ -534,8 +580,12 @@ def main():
     if args.probe:
         import torch
         torch.cuda.set_device(0)
-        res = probe_gemm(args.reps) if args.probe == "gemm" else \
-            probe_hop(args.reps, tuple(int(v) for v in args.hop_orders.split(",")))
+        if args.probe == "gemm":
+            res = probe_gemm(args.reps)
+        elif args.probe == "sweep":
+            res = probe_sweep(args.reps)
+        else:
+            res = probe_hop(args.reps, tuple(int(v) for v in args.hop_orders.split(",")))
         print(json.dumps({"probe": args.probe, "results": res}), flush=True)
         if args.calibrate_copy:
             calibrate_copy()
