@@ -93,6 +93,60 @@ __device__ __forceinline__ void load_su3(const char *gl, size_t estride, uint32_
     }
 }
 
+// Buffer loads of the links: a resource over the whole link array (4 scalar
+// registers for the launch), each element's byte offset (mu, e) in a scalar
+// register and the site's 32-bit offset in the lane: one load instruction
+// per element.  Flat loads from a 64-bit base put every element's address in
+// a register pair instead: a chain of 64-bit vector adds, or with scalar
+// bases per element, spilled scalar registers.  Needs the link array below
+// 4 GiB (36 V sizeof(complex) bytes).  The streaming kernel takes them; the
+// t-sweeps keep flat loads, measured faster there (FP32 whole planes 60.8
+// against 64.5 us per launch at 8^4 x 256 vectors, blocked 4%, FP64 even).
+constexpr int kBufWord3 = 0x00020000;    // raw buffer access (gfx9 descriptor word 3)
+
+template <typename T>
+__device__ __forceinline__ cplx_t<T> buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(cplx_t<T>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    } else {
+        return __builtin_bit_cast(cplx_t<T>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    }
+}
+
+// the links of direction mu: element e of a site at base + e * es + site * sizeof(complex)
+template <typename T> struct LinkBuf {
+    __amdgpu_buffer_rsrc_t r;
+    uint32_t base, es;
+};
+template <typename T> __device__ __forceinline__ LinkBuf<T> link_buf(const void *gauge, int V, int mu) {
+    LinkBuf<T> l;
+    l.es = (uint32_t)V * (uint32_t)sizeof(cplx_t<T>);
+    l.r = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(gauge), (short)0, (int)(36u * l.es), kBufWord3);
+    l.base = (uint32_t)mu * 9u * l.es;
+    return l;
+}
+template <typename T> __device__ __forceinline__ cplx_t<T> link_el(const LinkBuf<T> &l, int e, int site) {
+    return buf_ld<T>(l.r, (uint32_t)site * (uint32_t)sizeof(cplx_t<T>), l.base + (uint32_t)e * l.es);
+}
+
+// load_su3 through a LinkBuf
+template <typename T>
+__device__ __forceinline__ void load_su3_buf(const LinkBuf<T> &l, int site, bool two_rows, cplx_t<T> (&U)[9]) {
+#pragma unroll
+    for (int e = 0; e < 6; ++e) U[e] = link_el<T>(l, e, site);
+    if (two_rows) {
+        const cplx_t<T> c0 = csub<T>(cmul<T>(U[1], U[5]), cmul<T>(U[2], U[4]));
+        const cplx_t<T> c1 = csub<T>(cmul<T>(U[2], U[3]), cmul<T>(U[0], U[5]));
+        const cplx_t<T> c2 = csub<T>(cmul<T>(U[0], U[4]), cmul<T>(U[1], U[3]));
+        U[6] = mk<T>(c0.x, -c0.y);
+        U[7] = mk<T>(c1.x, -c1.y);
+        U[8] = mk<T>(c2.x, -c2.y);
+    } else {
+#pragma unroll
+        for (int e = 6; e < 9; ++e) U[e] = link_el<T>(l, e, site);
+    }
+}
+
 // ---------------------------------------------------------------- geometry
 struct Geo {
     int L[4];      // Lx, Ly, Lz, Lt
