@@ -122,8 +122,8 @@ C4 = LatticeConfig(
     levels=(Level((20, 15), 60, 32, deflated=True), Level(60, 15, 128, deflated=True),
             Level(15, 4, 512, deflated=True), Level(4, None, 2048)),
     k_defl=128, seed_links=401, seed_start=402, seed_noise=403, lattice_id=4,
-    description="24^3x48, n=7.96M complex64, 4 levels 299/60/15/4, 128 eigvecs, 32/128/512/2048 samples",
-    extra={"arnoldi_m": 200, "nev": 160},
+    description="24^3x48, n=7.96M complex64, 4 levels 299/60/15/4, at most 128 eigvecs, 32/128/512/2048 samples",
+    extra={"arnoldi_m": 255, "nev": 240},
 )
 
 C5 = tuple(
