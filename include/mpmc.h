@@ -164,9 +164,12 @@ const char *mpmc_build_info(void);
  *   MPMC_OPT_HOP_SLAB     1 (default): the streaming kernel hands each XCD a
  *     z-slab of the lattice swept along t (neighbours stay in its L2);
  *     0: each XCD takes a contiguous range of tiles in site order.
+ *   MPMC_OPT_LINK_BUF     1 (default): the streaming kernel reads the links
+ *     through buffer loads when the link array is below 4 GiB; 0: always
+ *     through 64-bit flat addresses (the path of larger arrays).
  * Every choice computes the same values up to the order of floating-point
  * sums (the work order changes no value at all). */
-enum { MPMC_OPT_PLANE_SWEEP = 1, MPMC_OPT_SWEEP_RANK = 2, MPMC_OPT_HOP_SLAB = 3 };
+enum { MPMC_OPT_PLANE_SWEEP = 1, MPMC_OPT_SWEEP_RANK = 2, MPMC_OPT_HOP_SLAB = 3, MPMC_OPT_LINK_BUF = 4 };
 int mpmc_set_option(int32_t option, int32_t value);
 
 /* Which t-sweep a scalar-mode polynomial on this lattice and batch would

@@ -29,7 +29,7 @@ OK, EINVAL, EUNSUPPORTED, EWORKSPACE, EHIP, ESINGULAR, ENOTCONVERGED = 0, -1, -2
 F64, F32 = 0, 1
 DEFL_COEFF, DEFL_RECON, DEFL_PROJECT = 0, 1, 2
 OP_NONE, OP_POLY, OP_DEFLATED_POLY, OP_SOLVE = 0, 1, 2, 3
-OPT_PLANE_SWEEP, OPT_SWEEP_RANK, OPT_HOP_SLAB = 1, 2, 3
+OPT_PLANE_SWEEP, OPT_SWEEP_RANK, OPT_HOP_SLAB, OPT_LINK_BUF = 1, 2, 3, 4
 
 c_i32, c_u64, c_f64, c_vp, c_size = ctypes.c_int32, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 

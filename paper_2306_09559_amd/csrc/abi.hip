@@ -10,6 +10,7 @@ namespace mpmc {
 int g_opt_sweep = 1;
 int g_opt_sweep_rank = 0;
 int g_opt_hop_slab = 1;
+int g_opt_link_buf = 1;
 
 size_t poly_ws_bytes(const int32_t dims[4], int32_t prec, const mpmc_poly &poly, mpmc_shape sh) {
     const size_t fb = align256(field_bytes(dims, prec, sh.nrhs));
@@ -126,6 +127,10 @@ int mpmc_set_option(int32_t option, int32_t value) {
     case MPMC_OPT_HOP_SLAB:
         if (value != 0 && value != 1) return MPMC_EINVAL;
         g_opt_hop_slab = value;
+        return MPMC_OK;
+    case MPMC_OPT_LINK_BUF:
+        if (value != 0 && value != 1) return MPMC_EINVAL;
+        g_opt_link_buf = value;
         return MPMC_OK;
     default: return MPMC_EUNSUPPORTED;
     }

@@ -513,7 +513,7 @@ template <typename T> static HopArgs<T> base_args(const mpmc_lattice &lat, mpmc_
     }
     a.gauge = (const cplx_t<T> *)lat.gauge;
     a.two_rows = lat.link_rows == 2;
-    a.gbuf = 36ull * (unsigned long long)a.g.V * sizeof(cplx_t<T>) < (1ull << 32);
+    a.gbuf = g_opt_link_buf && 36ull * (unsigned long long)a.g.V * sizeof(cplx_t<T>) < (1ull << 32);
     a.kappa = lat.kappa;
     return a;
 }

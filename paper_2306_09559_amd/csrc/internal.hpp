@@ -61,6 +61,7 @@ int sweep_chain_t(const mpmc_lattice &lat, mpmc_shape sh, const SweepPlan &plan,
 extern int g_opt_sweep;
 extern int g_opt_sweep_rank;
 extern int g_opt_hop_slab;
+extern int g_opt_link_buf;
 
 template <typename T>
 int poly_apply_t(const mpmc_lattice &, const mpmc_poly &, mpmc_shape, const void *x, const mpmc_noise *noise, void *y,

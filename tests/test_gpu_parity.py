@@ -639,6 +639,43 @@ def test_vector_mode_sweep(dims, prec, nrhs, field_in, dot):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_streaming_link_load_paths(prec):
+    """The streaming kernel's two ways of reading the links (buffer loads
+    below 4 GiB, 64-bit flat addresses otherwise): A x and a scalar-mode
+    polynomial agree with the oracle on both, and with each other to the
+    rounding the FMA contraction of each path allows."""
+    L = lib()
+    dims, N, rb = (8, 8, 8, 6), 32, 16
+    dl, ol = device_lattice(dims, 0.14, 0.4, 91, True, prec=prec)
+    V = dl.V
+    X = synth.random_fields(N, V, 92).reshape(N, -1)
+    x = pack(dims, X, rb, prec)
+    t = krylov.gmres_polys(ol.apply, synth.gaussian_start(ol.n, 93), [6]).inv_roots[6]
+    poly = L.DevicePoly(dev_c128(t))
+    L.set_option(L.OPT_PLANE_SWEEP, 0)
+    got = {}
+    for buf in (1, 0):
+        L.set_option(L.OPT_LINK_BUF, buf)
+        y = L.empty_field(V, N, rb, prec)
+        L.wilson_apply(dl, x, y)
+        ws = L.workspace(L.poly_workspace_size(dl, poly, N, rb))
+        bhy = torch.empty(N, dtype=torch.complex128, device="cuda")
+        L.poly_apply(dl, poly, N, rb, None, L.Noise(9, 1, 2, 0), None, bhy, ws)
+        torch.cuda.synchronize()
+        got[buf] = (unpack(dims, y, prec), bhy.cpu().numpy())
+    L.set_option(L.OPT_LINK_BUF, 1)
+    L.set_option(L.OPT_PLANE_SWEEP, 1)
+    R = ol.apply(X)
+    _, ref = ol.poly_apply(t, oracle.z4(9, 1, 2, 0, N, V))
+    bound = 1e-12 if prec == 0 else 8 * 6 * newton_amplification(ol.apply, t, oracle.z4(9, 1, 2, 0, 2, V)) * U32
+    for buf in (1, 0):
+        for r in (0, N // 2, N - 1):
+            assert rel(got[buf][0][r], R[r]) < (1e-13 if prec == 0 else 1e-6)
+        assert np.max(np.abs(got[buf][1] - ref) / np.abs(ref)) < bound
+    assert np.max(np.abs(got[1][1] - got[0][1]) / np.abs(got[0][1])) < bound
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 def test_streaming_work_order_changes_no_value(prec):
     """The streaming kernel's slab work order (each XCD a z-slab swept along
     t) only reorders workgroups: A x, scalar-mode and vector-mode polynomials
