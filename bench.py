@@ -537,7 +537,9 @@ def c4_step(steps: int = 2):
     t0 = time.perf_counter()
     run = driver.build(C4, prec=L.F32, rb=16, max_batch=256)
     setup = time.perf_counter() - t0
-    gs = GraphStep([run], parallel=False)
+    # one graph branch per level: launches of different levels fill each other's tails
+    # (2.32 -> 2.22 s per step, same estimates)
+    gs = GraphStep([run], level_branches=True)
     gs.replay()
     torch.cuda.synchronize()
     gs.reset()
@@ -684,7 +686,7 @@ def main():
         # the adaptive loop is then one launch of a step the library recorded as a HIP graph
         tune = autotune(run32, reps=4, use_cache=False)
         gps = graph_level_seconds(run32, args.steps)
-        gs = GraphStep([run32], parallel=False)
+        gs = GraphStep([run32], level_branches=True)
         gs.replay()
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -46,12 +46,14 @@ class GraphStep:
 
     def __init__(self, runs: Sequence[LatticeRun], batch: Optional[Dict[Tuple[int, int], int]] = None,
                  parallel: bool = True, only: Optional[Sequence[Tuple[int, int]]] = None,
-                 keep_state: bool = False):
+                 keep_state: bool = False, level_branches: bool = False):
         """runs: the lattices; batch: samples per (run, level), default the
         configured batch; parallel: one graph branch per lattice (else one
-        branch in order); only: restrict to these (run, level) pairs;
-        keep_state: continue the levels' accumulators and sample counts (a
-        run resumed from a checkpoint) instead of starting from zero."""
+        branch in order); level_branches: one branch per level of every
+        lattice (the levels hold separate buffers, so their launches may
+        overlap); only: restrict to these (run, level) pairs; keep_state:
+        continue the levels' accumulators and sample counts (a run resumed
+        from a checkpoint) instead of starting from zero."""
         self.runs = list(runs)
         self.parallel = parallel
         self.items: List[List[_Item]] = []
@@ -70,15 +72,21 @@ class GraphStep:
         self.replays = 0
         self.handle = L.Handle()
         citems = []
+        nb = 0
         for ri, row in enumerate(self.items):
             for it in row:
+                if level_branches:
+                    branch = nb
+                    nb += 1
+                else:
+                    branch = ri if parallel else 0
                 run, lv = it.run, it.run.levels[it.level]
                 cfg = run.cfg
                 # the sample index is the counter alone: replay k draws samples k*N .. k*N+N-1
                 cfg_noise = L.Noise(cfg.seed_noise, cfg.lattice_id, lv.index, 0)
                 citems.append(L.BatchItem(run.dl, lv.device, it.nsamples, run.level_rb(it.level), cfg_noise,
                                           it.counter, it.repeats, lv.samples[: it.nsamples], lv.acc, lv.ws,
-                                          branch=ri if parallel else 0, plane_sweep=int(lv.sweep),
+                                          branch=branch, plane_sweep=int(lv.sweep),
                                           sweep_rank=int(lv.sweep_rank)))
         L.batch_build(self.handle, citems)
         if keep_state:

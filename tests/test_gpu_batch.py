@@ -70,19 +70,22 @@ def test_graph_replays_match_eager(prec):
 
 
 def test_graph_serial_equals_parallel():
+    """One branch in order, one per lattice and one per level give the same
+    accumulators bit for bit."""
     from paper_2306_09559_amd import driver
     from paper_2306_09559_amd.batch import GraphStep
     ca, cb = _small_cfgs()
     runs = [driver.build(ca, prec=0, rb=4), driver.build(cb, prec=0, rb=8)]
     res = []
-    for par in (False, True):
-        gs = GraphStep(runs, parallel=par)
+    for kw in (dict(parallel=False), dict(parallel=True), dict(level_branches=True)):
+        gs = GraphStep(runs, **kw)
         gs.replay(2)
         torch.cuda.synchronize()
         res.append([[lv.acc.cpu().numpy().copy() for lv in r.levels] for r in runs])
-    for a, b in zip(res[0], res[1]):
-        for x, y in zip(a, b):
-            assert np.array_equal(x, y)
+    for other in res[1:]:
+        for a, b in zip(res[0], other):
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y)
 
 
 def test_autotune_keeps_values(tmp_path):
