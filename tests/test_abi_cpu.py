@@ -191,3 +191,20 @@ def test_noalloc_rejects_a_level_beyond_its_scratch(L):
     st = L._lib.mpmc_mlmc_level_estimate_noalloc(ctypes.byref(lat), ctypes.byref(lv), shape, ctypes.byref(nz),
                                                  fake, fake, None)
     assert st == L.EWORKSPACE
+
+
+def test_set_option_checks_its_arguments(L):
+    """Every kernel-selection option takes its documented values, rejects
+    others with EINVAL, and an unknown option is EUNSUPPORTED; the defaults
+    are restored afterwards (the options are process-wide)."""
+    lib = L._lib
+    ranges = {L.OPT_PLANE_SWEEP: (0, 1, 1), L.OPT_SWEEP_RANK: (0, 63, 0), L.OPT_HOP_SLAB: (0, 1, 1),
+              L.OPT_LINK_BUF: (0, 1, 1)}
+    for opt, (lo, hi, default) in ranges.items():
+        assert lib.mpmc_set_option(opt, lo) == L.OK
+        assert lib.mpmc_set_option(opt, hi) == L.OK
+        assert lib.mpmc_set_option(opt, lo - 1) == L.EINVAL
+        assert lib.mpmc_set_option(opt, hi + 1) == L.EINVAL
+        assert lib.mpmc_set_option(opt, default) == L.OK
+    assert lib.mpmc_set_option(0, 1) == L.EUNSUPPORTED
+    assert lib.mpmc_set_option(max(ranges) + 1, 1) == L.EUNSUPPORTED
