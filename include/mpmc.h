@@ -153,10 +153,16 @@ const char *mpmc_build_info(void);
 
 /* Process-wide kernel-selection options (set them before enqueueing work;
  * not synchronised with concurrent calls).
- *   MPMC_OPT_PLANE_SWEEP  1 (default): scalar-mode single polynomials on a
+ *   MPMC_OPT_PLANE_SWEEP  2 (default): scalar-mode single polynomials on a
  *     lattice whose xyz-plane (Lx*Ly*Lz a multiple of 64, at most 512 sites
  *     and 160 KiB of LDS at the field precision) run as a t-sweep with one
- *     workgroup per vector; 0: always use the streaming site-parallel kernel.
+ *     workgroup per vector when the batch has at least half as many vectors
+ *     as the GPU has CUs (below that the streaming kernel is faster: the
+ *     sweep's launch time does not shrink with the batch); larger planes
+ *     take the blocked t-sweep when the batch fills the GPU; probe vectors
+ *     always take the t-sweep.  1: the t-sweep whenever the lattice admits
+ *     one (mpmc_sweep_plan ok), whatever the batch.  0: always the
+ *     streaming site-parallel kernel (probe vectors: unsupported).
  *   MPMC_OPT_SWEEP_RANK   0 (default) .. 63: on FP32 planes too large for
  *     one workgroup, the t-sweep cuts the plane into xyz-blocks with a halo
  *     in LDS; the candidate blocks are ranked by the bytes each moves per

@@ -30,6 +30,8 @@ F64, F32 = 0, 1
 DEFL_COEFF, DEFL_RECON, DEFL_PROJECT = 0, 1, 2
 OP_NONE, OP_POLY, OP_DEFLATED_POLY, OP_SOLVE = 0, 1, 2, 3
 OPT_PLANE_SWEEP, OPT_SWEEP_RANK, OPT_HOP_SLAB, OPT_LINK_BUF = 1, 2, 3, 4
+# MPMC_OPT_PLANE_SWEEP values: never, whenever the lattice admits one, when the batch keeps half the CUs busy
+SWEEP_OFF, SWEEP_ALWAYS, SWEEP_AUTO = 0, 1, 2
 
 c_i32, c_u64, c_f64, c_vp, c_size = ctypes.c_int32, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 
@@ -509,7 +511,7 @@ class BatchItem:
     acc: torch.Tensor
     ws: torch.Tensor
     branch: int = 0
-    plane_sweep: int = 1
+    plane_sweep: int = SWEEP_AUTO
     sweep_rank: int = 0
     stop_state: Optional[torch.Tensor] = None    # device float64 (16,): mpmc_level_stop_check after each batch
     stop_first: int = 2

@@ -86,7 +86,8 @@ class GraphStep:
                 cfg_noise = L.Noise(cfg.seed_noise, cfg.lattice_id, lv.index, 0)
                 citems.append(L.BatchItem(run.dl, lv.device, it.nsamples, run.level_rb(it.level), cfg_noise,
                                           it.counter, it.repeats, lv.samples[: it.nsamples], lv.acc, lv.ws,
-                                          branch=branch, plane_sweep=int(lv.sweep),
+                                          branch=branch,
+                                          plane_sweep=L.SWEEP_AUTO if lv.sweep else L.SWEEP_OFF,
                                           sweep_rank=int(lv.sweep_rank)))
         L.batch_build(self.handle, citems)
         if keep_state:

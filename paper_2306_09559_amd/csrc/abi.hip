@@ -7,7 +7,7 @@
 
 namespace mpmc {
 
-int g_opt_sweep = 1;
+int g_opt_sweep = 2;
 int g_opt_sweep_rank = 0;
 int g_opt_hop_slab = 1;
 int g_opt_link_buf = 1;
@@ -117,7 +117,7 @@ const char *mpmc_build_info(void) { return "libmpmc 0.1 gfx950"; }
 int mpmc_set_option(int32_t option, int32_t value) {
     switch (option) {
     case MPMC_OPT_PLANE_SWEEP:
-        if (value != 0 && value != 1) return MPMC_EINVAL;
+        if (value < 0 || value > 2) return MPMC_EINVAL;
         g_opt_sweep = value;
         return MPMC_OK;
     case MPMC_OPT_SWEEP_RANK:

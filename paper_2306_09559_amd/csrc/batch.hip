@@ -111,7 +111,7 @@ int mpmc_batch_build(mpmc_handle h, const mpmc_batch_item *items, int32_t n_item
         const mpmc_batch_item &it = items[i];
         if (!it.lat || !it.counter || it.batches < 1 || it.branch < 0 || it.branch > 255) return MPMC_EINVAL;
         if (!polynomial_level(it.level)) return MPMC_EUNSUPPORTED;
-        if (it.plane_sweep != 0 && it.plane_sweep != 1) return MPMC_EINVAL;
+        if (it.plane_sweep < 0 || it.plane_sweep > 2) return MPMC_EINVAL;
         if (it.sweep_rank < 0 || it.sweep_rank > 63) return MPMC_EINVAL;
         if (it.stop_state && (it.stop_first < 2 || it.stop_every < 1)) return MPMC_EINVAL;
         // descriptor, shape and workspace (the level call validates the rest while it is recorded,

@@ -666,8 +666,10 @@ int poly_apply_t(const mpmc_lattice &lat, const mpmc_poly &poly, mpmc_shape sh, 
     const int32_t *colour = noise ? noise->probe_colour : nullptr;
     if (poly.n_out == 0 && y == nullptr && bhy != nullptr && poly.n_in >= 2 && (g_opt_sweep || colour)) {
         // scalar mode: t-sweep over xyz-blocks when the lattice admits one
+        // (option 2: and the batch keeps half the CUs busy; probe vectors
+        // are generated only by the sweep and always take it)
         const SweepPlan plan = sweep_plan(lat, sh);
-        if (plan.ok)
+        if (plan.ok && (plan.busy || g_opt_sweep == 1 || colour))
             return sweep_newton_t<T>(lat, sh, plan, poly.n_in, poly.inv_roots_in, x, x_noise, bvec, key, first, off,
                                      part, (double2 *)bhy, ws.f[0], ws.f[1], nullptr, stream, colour);
     }
@@ -689,7 +691,7 @@ int poly_apply_t(const mpmc_lattice &lat, const mpmc_poly &poly, mpmc_shape sh, 
         // fused outer update on the streaming kernel, all at block width 1
         const mpmc_shape sh1{sh.nrhs, 1};
         const SweepPlan plan = sweep_plan(lat, sh1);
-        if (plan.ok) return composite_sweep_t<T>(lat, poly, sh, sh1, plan, x, key, first, off, bhy, ws, stream);
+        if (plan.ok && (plan.busy || g_opt_sweep == 1)) return composite_sweep_t<T>(lat, poly, sh, sh1, plan, x, key, first, off, bhy, ws, stream);
     }
     if (poly.n_out == 0) {
         st = newton_t<T>(lat, sh, poly.n_in, poly.inv_roots_in, x, x_noise, bvec, key, first, off, y, part, ws.f[0],

@@ -39,6 +39,7 @@ struct SweepPlan {
     int nbp = 1;           // blocks per plane
     size_t lds = 0;        // dynamic LDS bytes
     bool fills = false;    // the batch gives every CU a full workgroup's worth of threads
+    bool busy = false;     // the batch keeps at least half the CUs busy (a whole plane: nrhs >= CUs / 2)
     int nranked = 1;       // blocked planes: candidate blocks ranked by the plan's cost (rank option)
 };
 SweepPlan sweep_plan(const mpmc_lattice &lat, mpmc_shape sh);

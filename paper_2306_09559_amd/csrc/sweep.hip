@@ -868,6 +868,13 @@ SweepPlan sweep_plan(const mpmc_lattice &lat, mpmc_shape sh) {
         return p;
     const size_t min_threads = (size_t)cus[dev] * 512;
     p.fills = (size_t)sh.nrhs * (size_t)P >= min_threads;
+    // A whole-plane sweep runs one workgroup per vector for the whole launch,
+    // so its launch takes about as long for 16 vectors as for 256; the
+    // streaming kernel's time grows with the vectors.  Measured on 8^4 per
+    // launch (sweep / streaming): FP64 72 / 27 us at 32 vectors, 74 / 51 at
+    // 64, 77 / 92 at 128, 102 / 170 at 256; FP32 55 / 19, 56 / 32, 57 / 54,
+    // 64 / 99.  Half the CUs is where the two meet.
+    p.busy = 2 * (size_t)sh.nrhs >= (size_t)cus[dev];
     const size_t whole = (lat.prec == MPMC_F32 ? 36 : 18) * (size_t)P * csz;
     if (P >= 64 && P <= 512 && P % 64 == 0 && whole <= kLds) {
         // the whole xyz-plane in one workgroup (neighbours wrap inside it)
@@ -939,6 +946,7 @@ SweepPlan sweep_plan(const mpmc_lattice &lat, mpmc_shape sh) {
     const Cand &c = cands[g_opt_sweep_rank < nc ? g_opt_sweep_rank : nc - 1];
     p.ok = true;
     p.halo = true;
+    p.busy = true;    // blocked planes take the sweep only when the batch fills the GPU (above)
     p.B[0] = c.bx;
     p.B[1] = c.by;
     p.B[2] = c.bz;

@@ -83,7 +83,7 @@ class LatticeRun:
         descriptor (used by graph capture, where the sample index comes from a
         device counter)."""
         lv = self.levels[level]
-        L.set_option(L.OPT_PLANE_SWEEP, int(lv.sweep))
+        L.set_option(L.OPT_PLANE_SWEEP, L.SWEEP_AUTO if lv.sweep else L.SWEEP_OFF)
         L.set_option(L.OPT_SWEEP_RANK, int(lv.sweep_rank))
         L.mlmc_level_estimate(self.dl, lv.device, nsamples, self.level_rb(level), nz, lv.samples[:nsamples],
                               lv.acc, lv.ws)
@@ -636,7 +636,8 @@ def _stop_step(run: LatticeRun, level: int, batch: int, state: torch.Tensor, fir
     h = L.Handle()
     item = L.BatchItem(run.dl, lv.device, batch, run.level_rb(level),
                        L.Noise(run.cfg.seed_noise, run.cfg.lattice_id, lv.index, 0), ctr, 1, lv.samples[:batch],
-                       lv.acc, lv.ws, 0, int(lv.sweep), int(lv.sweep_rank), state, first, every)
+                       lv.acc, lv.ws, 0, L.SWEEP_AUTO if lv.sweep else L.SWEEP_OFF, int(lv.sweep_rank),
+                       state, first, every)
     L.batch_build(h, [item])
     return h, ctr
 

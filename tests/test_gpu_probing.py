@@ -84,8 +84,13 @@ def test_probes_in_kernel_equal_filled_probes(prec):
     t = krylov.gmres_polys(ol.apply, synth.gaussian_start(ol.n, 3), [deg]).inv_roots[deg]
     poly = L.DevicePoly(dev_c128(t))
     col = probing.colouring(dims, deg)
-    a = probing.probe_trace(dl, poly, col, nrhs=64, in_kernel=True)
-    b = probing.probe_trace(dl, poly, col, nrhs=64, in_kernel=False)
+    # the filled probes on the same kernel (at 64 vectors the automatic choice streams them)
+    L.set_option(L.OPT_PLANE_SWEEP, L.SWEEP_ALWAYS)
+    try:
+        a = probing.probe_trace(dl, poly, col, nrhs=64, in_kernel=True)
+        b = probing.probe_trace(dl, poly, col, nrhs=64, in_kernel=False)
+    finally:
+        L.set_option(L.OPT_PLANE_SWEEP, L.SWEEP_AUTO)
     print(f"prec {prec}: in kernel {a.trace}, filled {b.trace}, equal {a.trace == b.trace}")
     assert abs(a.trace - b.trace) <= 1e-14 * abs(b.trace)
     if prec == 0:
