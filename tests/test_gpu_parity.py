@@ -284,6 +284,58 @@ def test_deflate_coeff_large_random():
     assert np.max(np.abs(omega.cpu().numpy() - ro) / scale) < 1e-13
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_deflate_at_the_largest_width(prec):
+    """The deflation GEMMs at their largest width, kpad = 256 with a ragged
+    k = 250 (pairs swapped, left vectors g5 z_pair / 2), on 4^4 x 12 rows:
+    V^H b and U^H b for 48 Z4 vectors and X = V d, against the oracle's
+    dense products (FP64 1e-13 of the terms' scale; FP32 operands and
+    accumulation: the summation bound 4 m u32 sum|products|, m the number of
+    complex terms, 12 V for the coefficients and k + 2 for X, d rounded
+    once)."""
+    L = lib()
+    dims = (4, 4, 4, 4)
+    dl, ol = device_lattice(dims, 0.15, 0.5, 5, True, prec=prec)
+    k, kpad, n = 250, 256, 12 * dl.V
+    rng = np.random.default_rng(11)
+    Z = rng.standard_normal((k, n)) + 1j * rng.standard_normal((k, n))
+    if prec == 1:
+        Z = Z.astype(np.complex64).astype(np.complex128)     # the field-precision eigenvectors
+    pair = np.arange(k)
+    pair[0:2] = [1, 0]
+    U = np.stack([ol.gamma5(Z[pair[i]]) for i in range(k)]) * 0.5
+    D = device_defl(dims, Z, pair, U, None, prec, kpad)
+    nrhs, rb = 48, 16
+    nz = L.Noise(8, 1, 3, 7)
+    B = oracle.z4(8, 1, 3, 7, nrhs, dl.V)
+    zeta = torch.empty((k, nrhs), dtype=torch.complex128, device="cuda")
+    omega = torch.empty_like(zeta)
+    ws = L.workspace(L.deflate_workspace_size(dl, D, nrhs, rb))
+    L.deflate_project(dl, D, L.DEFL_COEFF, nrhs, rb, None, nz, zeta, omega, None, None, ws)
+    rz, ro = deflation.projection_coefficients(Z, U, B)
+    if prec == 0:
+        scale = np.linalg.norm(Z, axis=1)[:, None] * np.linalg.norm(B, axis=1)[None, :]
+        assert np.max(np.abs(zeta.cpu().numpy() - rz) / scale) < 1e-13
+        assert np.max(np.abs(omega.cpu().numpy() - ro) / scale) < 1e-13
+    else:
+        # a complex product is two real ones in each of Re and Im (2n real terms per sum):
+        # |zeta - zeta*| <= gamma_2n (|Re| + |Im| parts) <= 4 n u32 sum|z||b|
+        bz = 4 * n * U32 * (np.abs(Z) @ np.abs(B).T)
+        assert np.all(np.abs(zeta.cpu().numpy() - rz) <= bz)
+        assert np.all(np.abs(omega.cpu().numpy() - ro) <= 0.5 * bz[pair])
+    d = rng.standard_normal((k, nrhs)) + 1j * rng.standard_normal((k, nrhs))
+    X = L.empty_field(dl.V, nrhs, rb, prec)
+    L.deflate_project(dl, D, L.DEFL_RECON, nrhs, rb, None, None, None, None, dev_c128(d), X, ws)
+    ref = (Z.T @ d).T
+    got = unpack(dims, X, prec)
+    for r in (0, nrhs // 2, nrhs - 1):
+        if prec == 0:
+            assert rel(got[r], ref[r]) < 1e-13
+        else:
+            bx = 4 * (k + 2) * U32 * (np.abs(Z).T @ np.abs(d[:, r]))   # d rounded to FP32, k products summed
+            assert np.all(np.abs(got[r] - ref[r]) <= bx)
+
+
 def test_deflate_recon_and_project(small_defl):
     L = lib()
     dims, dl, ol, lam, Z, pair, U, H = small_defl
