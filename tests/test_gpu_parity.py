@@ -77,6 +77,7 @@ def test_pack_roundtrip(prec):
     ((3, 2, 2, 5), 8, 2, True),        # odd extents, ragged last workgroup
     ((2, 4, 2, 2), 3, 1, True),
     ((8, 4, 4, 4), 64, 64, True),      # one site per workgroup quarter
+    ((4, 4, 2, 2), 256, 256, True),    # the largest block width: one site per workgroup
 ])
 def test_wilson_apply_f64(dims, nrhs, rb, ap):
     L = lib()
@@ -129,7 +130,8 @@ def _roots(ol, degs, seed=3):
 
 
 @pytest.mark.parametrize("deg,nrhs,rb,z4", [(0, 4, 4, True), (1, 4, 2, False), (5, 12, 4, True),
-                                            (20, 16, 16, True), (20, 6, 2, False)])
+                                            (20, 16, 16, True), (20, 6, 2, False),
+                                            (5, 256, 256, False)])      # the largest block width
 def test_poly_apply_f64(deg, nrhs, rb, z4):
     L = lib()
     dims = (4, 4, 4, 4)
