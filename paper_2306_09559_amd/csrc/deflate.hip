@@ -186,6 +186,7 @@ __global__ void k_small_gemm(const double2 *hinv, const double2 *omega, int k, i
 
 template <typename T> struct ReconArgs {
     int Vol, kpad, k, nrhs, rb, ntr, nts;   // nts: 16-site tiles
+    int kact;                               // columns summed: k rounded up to the MFMA depth 4
     const cplx_t<T> *V;
     const double2 *d;                       // k x nrhs
     cplx_t<T> *X;                           // field
@@ -206,7 +207,7 @@ __global__ void __launch_bounds__(kWaves * 64) k_recon(ReconArgs<T> a) {
     const int r = tr * 16 + m;                 // vector column of the B operand
     acc_t xr, xi;
     for (int v = 0; v < 4; ++v) xr[v] = xi[v] = T(0);
-    for (int i0 = 0; i0 < a.kpad; i0 += 4) {
+    for (int i0 = 0; i0 < a.kact; i0 += 4) {
         const int i = i0 + kk;
         T vr = T(0), vi = T(0), dr = T(0), di = T(0);
         if (s < a.Vol) {
@@ -239,14 +240,20 @@ __global__ void __launch_bounds__(kWaves * 64) k_recon(ReconArgs<T> a) {
 namespace {
 
 struct CoeffPlan {
-    int ntr, nti, nsplit, sites_per_split, ldr;
+    int ntr, nti, nti_run, nsplit, sites_per_split, ldr;
     size_t part_bytes;
 };
 
-CoeffPlan plan_coeff(int Vol, int kpad, int nrhs) {
+// kpad: the row length of V (and of the partial sums); k: the columns in use.
+// The split over the lattice (and so the workspace) follows kpad; only the
+// eigenvector tiles holding columns below k are launched, so a basis filled
+// column by column (the Arnoldi runs) is read only as far as it is filled;
+// the finish reads rows below k.
+CoeffPlan plan_coeff(int Vol, int kpad, int k, int nrhs) {
     CoeffPlan p;
     p.ntr = (nrhs + 15) / 16;
     p.nti = kpad / 16;
+    p.nti_run = (k + 15) / 16;
     p.ldr = p.ntr * 16;
     const int tiles = p.ntr * p.nti;
     int want = (2048 + tiles - 1) / tiles;
@@ -263,7 +270,7 @@ template <typename T>
 int coeff_t(const mpmc_lattice &lat, const mpmc_defl &df, mpmc_shape sh, const void *b, const mpmc_noise *noise,
             double *zeta, double *omega, void *ws, void *stream) {
     const int Vol = lat.dims[0] * lat.dims[1] * lat.dims[2] * lat.dims[3];
-    const CoeffPlan p = plan_coeff(Vol, df.kpad, sh.nrhs);
+    const CoeffPlan p = plan_coeff(Vol, df.kpad, df.k, sh.nrhs);
     CoeffArgs<T> a;
     a.Vol = Vol;
     a.kpad = df.kpad;
@@ -277,7 +284,7 @@ int coeff_t(const mpmc_lattice &lat, const mpmc_defl &df, mpmc_shape sh, const v
     a.first = noise ? noise->first_sample : 0ull;
     a.off = noise ? noise->sample_offset : nullptr;
     a.part = (double2 *)ws;
-    hipLaunchKernelGGL(k_coeff<T>, dim3(p.nti * p.ntr, p.nsplit), dim3(kWaves * 64), 0, (hipStream_t)stream, a);
+    hipLaunchKernelGGL(k_coeff<T>, dim3(p.nti_run * p.ntr, p.nsplit), dim3(kWaves * 64), 0, (hipStream_t)stream, a);
     if (hipGetLastError() != hipSuccess) return MPMC_EHIP;
     const int tot = df.k * sh.nrhs;
     hipLaunchKernelGGL(k_coeff_finish, dim3((unsigned)tot), dim3(kSumLanes), 0, (hipStream_t)stream,
@@ -292,6 +299,7 @@ int recon_t(const mpmc_lattice &lat, const mpmc_defl &df, mpmc_shape sh, const d
     a.Vol = lat.dims[0] * lat.dims[1] * lat.dims[2] * lat.dims[3];
     a.kpad = df.kpad;
     a.k = df.k;
+    a.kact = (df.k + 3) / 4 * 4;
     a.nrhs = sh.nrhs;
     a.rb = sh.rb;
     a.ntr = (sh.nrhs + 15) / 16;
@@ -308,7 +316,7 @@ int recon_t(const mpmc_lattice &lat, const mpmc_defl &df, mpmc_shape sh, const d
 
 size_t defl_ws_bytes(const mpmc_lattice &lat, const mpmc_defl &df, mpmc_shape sh) {
     const int Vol = lat.dims[0] * lat.dims[1] * lat.dims[2] * lat.dims[3];
-    const CoeffPlan p = plan_coeff(Vol, df.kpad, sh.nrhs);
+    const CoeffPlan p = plan_coeff(Vol, df.kpad, df.k, sh.nrhs);
     // partials, then (PROJECT) omega/zeta scratch and the field V d
     return align256(p.part_bytes) + 2 * align256((size_t)df.k * sh.nrhs * sizeof(double2)) +
            align256(field_bytes(lat.dims, lat.prec, sh.nrhs));
@@ -317,7 +325,7 @@ size_t defl_ws_bytes(const mpmc_lattice &lat, const mpmc_defl &df, mpmc_shape sh
 int deflate_impl(const mpmc_lattice &lat, const mpmc_defl &df, int32_t mode, mpmc_shape sh, const void *b,
                  const mpmc_noise *noise, double *zeta, double *omega, double *d, void *X, void *ws, void *stream) {
     const int Vol = lat.dims[0] * lat.dims[1] * lat.dims[2] * lat.dims[3];
-    const CoeffPlan p = plan_coeff(Vol, df.kpad, sh.nrhs);
+    const CoeffPlan p = plan_coeff(Vol, df.kpad, df.k, sh.nrhs);
     char *w = (char *)ws;
     void *part = w;
     w += align256(p.part_bytes);
