@@ -14,32 +14,66 @@ __device__ __forceinline__ size_t fidx(int r, int c, int s, int V, int rb) {
     return ((size_t)(r / rb) * 12 + (size_t)c) * (size_t)V * (size_t)rb + (size_t)s * (size_t)rb + (size_t)(r % rb);
 }
 
+// Element-wise kernels run on a grid (element of a component plane, component
+// c, RHS block nbk): a plane of one RHS block holds V * rb elements (fewer
+// than 2^29, the byte offsets of a plane fit 32 bits), rb is a power of two,
+// so every index is formed without division (a 64-bit division per element,
+// emulated in software, held a one-vector FP64 axpby on 24^3x48 to 0.2 TB/s).
+struct PlaneIdx {
+    size_t e;      // element index in the batch
+    int r;         // vector
+    unsigned i;    // element within the plane: site i >> lrb, lane i & (rb - 1)
+    bool ok;
+};
+__device__ __forceinline__ PlaneIdx plane_idx(int V, int lrb) {
+    PlaneIdx p;
+    const unsigned per = (unsigned)V << lrb;
+    p.i = blockIdx.x * blockDim.x + threadIdx.x;
+    p.ok = p.i < per;
+    const unsigned c = blockIdx.y, nbk = blockIdx.z;
+    p.e = ((size_t)nbk * 12 + c) * (size_t)per + p.i;
+    p.r = (int)((nbk << lrb) + (p.i & ((1u << lrb) - 1u)));
+    return p;
+}
+// (at most 65535 RHS blocks: the launches check it)
+inline dim3 plane_grid(int V, int rb, int nrhs) {
+    return dim3((unsigned)(((size_t)V * rb + 255) / 256), 12u, (unsigned)(nrhs / rb));
+}
+inline int log2_pow2(int rb) {
+    int l = 0;
+    while ((1 << l) < rb) ++l;
+    return l;
+}
+
 template <typename T>
-__global__ void k_axpby(const double2 *alpha, const cplx_t<T> *x, const double2 *beta, cplx_t<T> *y, int V, int rb,
-                        int nrhs) {
-    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t total = (size_t)nrhs * 12 * (size_t)V;
-    if (e >= total) return;
-    const int j = (int)(e % (size_t)rb);
-    const int nbk = (int)(e / ((size_t)rb * 12 * (size_t)V));
-    const int r = nbk * rb + j;
+__global__ void k_axpby(const double2 *alpha, const cplx_t<T> *x, const double2 *beta, cplx_t<T> *y, int V, int lrb) {
+    const PlaneIdx q = plane_idx(V, lrb);
+    if (!q.ok) return;
+    const size_t e = q.e;
+    const int r = q.r;
     const double2 a = alpha[r];
     const cplx_t<T> xv = x[e];
     y[e] = beta != nullptr ? lin2_d<T>(a, xv, beta[r], y[e]) : cmul_d<T>(a, xv);
 }
 
-// partial inner products: workgroup covers 256/rb sites of one RHS block
+constexpr int kDotRun = 4096;
+
+// partial inner products: workgroup b of an RHS block covers the site tiles
+// b, b + nrun, .. (256/rb sites each), so that an RHS block leaves at most
+// nrun partials per vector (at block width 256 one site per tile: a partial
+// per site made the finish read V strided values per vector)
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_dot_part(const cplx_t<T> *x, const cplx_t<T> *y, int V, int rb, int spw,
-                                                     int nblk, double2 *part) {
+                                                     int nblk, int nrun, double2 *part) {
     __shared__ double2 red[kBlock];
     const int L = (int)blockIdx.x;
-    const int nbk = L / nblk, sblk = L % nblk;
+    const int nbk = L / nrun, b0 = L % nrun;
     const int lane = (int)threadIdx.x, jr = lane & (rb - 1), ls = lane / rb;
-    const int s = sblk * spw + ls;
+    const int r = nbk * rb + jr;
     double re = 0.0, im = 0.0;
-    if (s < V) {
-        const int r = nbk * rb + jr;
+    for (int sblk = b0; sblk < nblk; sblk += nrun) {
+        const int s = sblk * spw + ls;
+        if (s >= V) break;
         for (int c = 0; c < 12; ++c) {
             const size_t ix = fidx(r, c, s, V, rb);
             const double xr = (double)x[ix].x, xi = (double)x[ix].y, yr = (double)y[ix].x, yi = (double)y[ix].y;
@@ -80,27 +114,24 @@ __global__ void k_copy_vector(const cplx_t<T> *src, int src_rb, int src_r, cplx_
 
 // a whole batch from block width src_rb to dst_rb, one thread per destination element
 template <typename T>
-__global__ void k_relayout(const cplx_t<T> *src, int src_rb, cplx_t<T> *dst, int dst_rb, int V, int nrhs) {
-    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (size_t)nrhs * 12 * (size_t)V) return;
-    const int j = (int)(e % (size_t)dst_rb);
-    size_t rest = e / (size_t)dst_rb;
-    const int s = (int)(rest % (size_t)V);
-    rest /= (size_t)V;
-    const int c = (int)(rest % 12);
-    const int r = (int)(rest / 12) * dst_rb + j;
-    dst[e] = src[fidx(r, c, s, V, src_rb)];
+__global__ void k_relayout(const cplx_t<T> *src, int lsrc, cplx_t<T> *dst, int ldst, int V) {
+    const PlaneIdx q = plane_idx(V, ldst);
+    if (!q.ok) return;
+    const int s = (int)(q.i >> ldst), c = (int)blockIdx.y;
+    const size_t per = (size_t)V << lsrc;
+    const size_t from = ((size_t)(q.r >> lsrc) * 12 + (size_t)c) * per + ((size_t)s << lsrc) +
+                        (size_t)(q.r & ((1 << lsrc) - 1));
+    dst[q.e] = src[from];
 }
 
 // y = alpha x + beta y across precisions, coefficients applied in FP64
 template <typename TX, typename TY>
 __global__ void k_axpby_mixed(const double2 *alpha, const cplx_t<TX> *x, const double2 *beta, cplx_t<TY> *y, int V,
-                              int rb, int nrhs) {
-    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t total = (size_t)nrhs * 12 * (size_t)V;
-    if (e >= total) return;
-    const int j = (int)(e % (size_t)rb);
-    const int r = (int)(e / ((size_t)rb * 12 * (size_t)V)) * rb + j;
+                              int lrb) {
+    const PlaneIdx q = plane_idx(V, lrb);
+    if (!q.ok) return;
+    const size_t e = q.e;
+    const int r = q.r;
     const double2 a = alpha[r];
     const double xr = (double)x[e].x, xi = (double)x[e].y;
     double re = a.x * xr - a.y * xi, im = a.x * xi + a.y * xr;
@@ -187,11 +218,11 @@ __global__ void __launch_bounds__(kSumLanes) k_block_dot_finish(const double2 *p
 // y = [y +] sum_i coeff[i][r] (v_i)_r, in FP64, rounded once
 template <typename T>
 __global__ void k_block_axpy(const cplx_t<T> *basis, size_t F, int k, const double2 *coeff, int accumulate,
-                             cplx_t<T> *y, int V, int rb, int nrhs) {
-    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= F) return;
-    const int j = (int)(e % (size_t)rb);
-    const int r = (int)(e / ((size_t)rb * 12 * (size_t)V)) * rb + j;
+                             cplx_t<T> *y, int V, int lrb, int nrhs) {
+    const PlaneIdx q = plane_idx(V, lrb);
+    if (!q.ok) return;
+    const size_t e = q.e;
+    const int r = q.r;
     double re = 0.0, im = 0.0;
     if (accumulate) {
         re = (double)y[e].x;
@@ -226,58 +257,65 @@ inline int st() { return hipGetLastError() == hipSuccess ? MPMC_OK : MPMC_EHIP; 
 int field_axpby_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, const double *alpha, const void *x,
                      const double *beta, void *y, void *stream) {
     const int V = dims[0] * dims[1] * dims[2] * dims[3];
-    const size_t total = (size_t)sh.nrhs * 12 * V;
-    const unsigned g = (unsigned)((total + 255) / 256);
+    if (sh.nrhs / sh.rb > 65535) return MPMC_EUNSUPPORTED;
+    const dim3 g = plane_grid(V, sh.rb, sh.nrhs);
+    const int lrb = log2_pow2(sh.rb);
     if (prec == MPMC_F64)
-        hipLaunchKernelGGL(k_axpby<double>, dim3(g), dim3(256), 0, (hipStream_t)stream, (const double2 *)alpha,
-                           (const double2 *)x, (const double2 *)beta, (double2 *)y, V, sh.rb, sh.nrhs);
+        hipLaunchKernelGGL(k_axpby<double>, g, dim3(256), 0, (hipStream_t)stream, (const double2 *)alpha,
+                           (const double2 *)x, (const double2 *)beta, (double2 *)y, V, lrb);
     else
-        hipLaunchKernelGGL(k_axpby<float>, dim3(g), dim3(256), 0, (hipStream_t)stream, (const double2 *)alpha,
-                           (const float2 *)x, (const double2 *)beta, (float2 *)y, V, sh.rb, sh.nrhs);
+        hipLaunchKernelGGL(k_axpby<float>, g, dim3(256), 0, (hipStream_t)stream, (const double2 *)alpha,
+                           (const float2 *)x, (const double2 *)beta, (float2 *)y, V, lrb);
     return st();
 }
+
+// workgroups per RHS block of the inner products (and partials per vector)
+static int dot_nrun(const FieldTiling &t) { return t.nblk < kDotRun ? t.nblk : kDotRun; }
 
 size_t field_dot_ws_bytes(const int32_t dims[4], mpmc_shape sh) {
     const int V = dims[0] * dims[1] * dims[2] * dims[3];
     const FieldTiling t = make_tiling(V, sh.nrhs, sh.rb);
-    return align256((size_t)t.groups() * sh.rb * sizeof(double2));
+    return align256((size_t)t.nb * dot_nrun(t) * sh.rb * sizeof(double2));
 }
 
 int field_dot_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, const void *x, const void *y, double *out,
                    void *ws, void *stream) {
     const int V = dims[0] * dims[1] * dims[2] * dims[3];
     const FieldTiling t = make_tiling(V, sh.nrhs, sh.rb);
+    const int nrun = dot_nrun(t);
+    const dim3 grid((unsigned)(t.nb * nrun));
     if (prec == MPMC_F64)
-        hipLaunchKernelGGL(k_dot_part<double>, dim3(t.groups()), dim3(kBlock), 0, (hipStream_t)stream,
-                           (const double2 *)x, (const double2 *)y, V, sh.rb, t.spw, t.nblk, (double2 *)ws);
+        hipLaunchKernelGGL(k_dot_part<double>, grid, dim3(kBlock), 0, (hipStream_t)stream, (const double2 *)x,
+                           (const double2 *)y, V, sh.rb, t.spw, t.nblk, nrun, (double2 *)ws);
     else
-        hipLaunchKernelGGL(k_dot_part<float>, dim3(t.groups()), dim3(kBlock), 0, (hipStream_t)stream,
-                           (const float2 *)x, (const float2 *)y, V, sh.rb, t.spw, t.nblk, (double2 *)ws);
+        hipLaunchKernelGGL(k_dot_part<float>, grid, dim3(kBlock), 0, (hipStream_t)stream, (const float2 *)x,
+                           (const float2 *)y, V, sh.rb, t.spw, t.nblk, nrun, (double2 *)ws);
     if (hipGetLastError() != hipSuccess) return MPMC_EHIP;
     hipLaunchKernelGGL(k_dot_finish, dim3(sh.nrhs), dim3(kSumLanes), 0, (hipStream_t)stream, (const double2 *)ws,
-                       t.nblk, sh.rb, (double2 *)out);
+                       nrun, sh.rb, (double2 *)out);
     return st();
 }
 
 int field_axpby_mixed_impl(const int32_t dims[4], mpmc_shape sh, int32_t xp, const double *alpha, const void *x,
                            int32_t yp, const double *beta, void *y, void *stream) {
     const int V = dims[0] * dims[1] * dims[2] * dims[3];
-    const size_t total = (size_t)sh.nrhs * 12 * V;
-    const unsigned g = (unsigned)((total + 255) / 256);
+    if (sh.nrhs / sh.rb > 65535) return MPMC_EUNSUPPORTED;
+    const dim3 g = plane_grid(V, sh.rb, sh.nrhs);
+    const int lrb = log2_pow2(sh.rb);
     const double2 *a = (const double2 *)alpha, *b = (const double2 *)beta;
     hipStream_t s = (hipStream_t)stream;
     if (xp == MPMC_F64 && yp == MPMC_F64)
-        hipLaunchKernelGGL((k_axpby_mixed<double, double>), dim3(g), dim3(256), 0, s, a, (const double2 *)x, b,
-                           (double2 *)y, V, sh.rb, sh.nrhs);
+        hipLaunchKernelGGL((k_axpby_mixed<double, double>), g, dim3(256), 0, s, a, (const double2 *)x, b,
+                           (double2 *)y, V, lrb);
     else if (xp == MPMC_F64)
-        hipLaunchKernelGGL((k_axpby_mixed<double, float>), dim3(g), dim3(256), 0, s, a, (const double2 *)x, b,
-                           (float2 *)y, V, sh.rb, sh.nrhs);
+        hipLaunchKernelGGL((k_axpby_mixed<double, float>), g, dim3(256), 0, s, a, (const double2 *)x, b,
+                           (float2 *)y, V, lrb);
     else if (yp == MPMC_F64)
-        hipLaunchKernelGGL((k_axpby_mixed<float, double>), dim3(g), dim3(256), 0, s, a, (const float2 *)x, b,
-                           (double2 *)y, V, sh.rb, sh.nrhs);
+        hipLaunchKernelGGL((k_axpby_mixed<float, double>), g, dim3(256), 0, s, a, (const float2 *)x, b,
+                           (double2 *)y, V, lrb);
     else
-        hipLaunchKernelGGL((k_axpby_mixed<float, float>), dim3(g), dim3(256), 0, s, a, (const float2 *)x, b,
-                           (float2 *)y, V, sh.rb, sh.nrhs);
+        hipLaunchKernelGGL((k_axpby_mixed<float, float>), g, dim3(256), 0, s, a, (const float2 *)x, b,
+                           (float2 *)y, V, lrb);
     return st();
 }
 
@@ -310,27 +348,31 @@ int field_block_axpy_impl(const int32_t dims[4], int32_t prec, mpmc_shape sh, in
                           const double *coeff, int accumulate, void *y, void *stream) {
     const int V = dims[0] * dims[1] * dims[2] * dims[3];
     const size_t F = (size_t)sh.nrhs * 12 * (size_t)V;
-    const unsigned g = (unsigned)((F + 255) / 256);
+    if (sh.nrhs / sh.rb > 65535) return MPMC_EUNSUPPORTED;
+    const dim3 g = plane_grid(V, sh.rb, sh.nrhs);
+    const int lrb = log2_pow2(sh.rb);
     hipStream_t s = (hipStream_t)stream;
     if (prec == MPMC_F64)
-        hipLaunchKernelGGL(k_block_axpy<double>, dim3(g), dim3(256), 0, s, (const double2 *)basis, F, k,
-                           (const double2 *)coeff, accumulate, (double2 *)y, V, sh.rb, sh.nrhs);
+        hipLaunchKernelGGL(k_block_axpy<double>, g, dim3(256), 0, s, (const double2 *)basis, F, k,
+                           (const double2 *)coeff, accumulate, (double2 *)y, V, lrb, sh.nrhs);
     else
-        hipLaunchKernelGGL(k_block_axpy<float>, dim3(g), dim3(256), 0, s, (const float2 *)basis, F, k,
-                           (const double2 *)coeff, accumulate, (float2 *)y, V, sh.rb, sh.nrhs);
+        hipLaunchKernelGGL(k_block_axpy<float>, g, dim3(256), 0, s, (const float2 *)basis, F, k,
+                           (const double2 *)coeff, accumulate, (float2 *)y, V, lrb, sh.nrhs);
     return st();
 }
 
 int field_relayout_impl(const int32_t dims[4], int32_t prec, int32_t nrhs, const void *src, int32_t src_rb, void *dst,
                         int32_t dst_rb, void *stream) {
     const int V = dims[0] * dims[1] * dims[2] * dims[3];
-    const unsigned g = (unsigned)(((size_t)nrhs * 12 * (size_t)V + 255) / 256);
+    if (nrhs / dst_rb > 65535) return MPMC_EUNSUPPORTED;
+    const dim3 g = plane_grid(V, dst_rb, nrhs);
+    const int ls = log2_pow2(src_rb), ld = log2_pow2(dst_rb);
     if (prec == MPMC_F64)
-        hipLaunchKernelGGL(k_relayout<double>, dim3(g), dim3(256), 0, (hipStream_t)stream, (const double2 *)src, src_rb,
-                           (double2 *)dst, dst_rb, V, nrhs);
+        hipLaunchKernelGGL(k_relayout<double>, g, dim3(256), 0, (hipStream_t)stream, (const double2 *)src, ls,
+                           (double2 *)dst, ld, V);
     else
-        hipLaunchKernelGGL(k_relayout<float>, dim3(g), dim3(256), 0, (hipStream_t)stream, (const float2 *)src, src_rb,
-                           (float2 *)dst, dst_rb, V, nrhs);
+        hipLaunchKernelGGL(k_relayout<float>, g, dim3(256), 0, (hipStream_t)stream, (const float2 *)src, ls,
+                           (float2 *)dst, ld, V);
     return st();
 }
 

@@ -86,10 +86,12 @@ class DeviceArnoldi:
         beta = self._norm(self.w)
         L.field_axpby(dims, F64, _c([1.0 / beta]), self.w, None, self.w)
         L.field_copy_vector(dims, F64, self.w, 0, self.Q, 0)
+        # v holds the newest basis vector as its own contiguous field (the
+        # basis column it equals is strided by the basis width)
+        self.v, self.w = self.w, self.v
         H = np.zeros((m + 1, m), dtype=np.complex128)
         taken, broke = m, False
         for j in range(m):
-            L.field_copy_vector(dims, F64, self.Q, j, self.v, 0)
             apply_op(self.v, self.w)
             basis = self._basis(j + 1)
             hcol = np.zeros(j + 1, dtype=np.complex128)
@@ -107,6 +109,7 @@ class DeviceArnoldi:
                 break
             L.field_axpby(dims, F64, _c([1.0 / hn]), self.w, None, self.w)
             L.field_copy_vector(dims, F64, self.w, 0, self.Q, j + 1)
+            self.v, self.w = self.w, self.v
             if stop is not None and stop(j, H[: j + 2, : j + 1], beta):
                 taken = j + 1
                 break
@@ -314,17 +317,25 @@ def pp_arnoldi_deflation(dl: L.DeviceLattice, pin: L.DevicePoly, start: np.ndarr
     lam_all = zaz.cpu().numpy()[: len(idx)]
     order = np.argsort(np.abs(lam_all), kind="stable")
 
+    one = (L.empty_field(V, 1, 1, F64), L.empty_field(V, 1, 1, F64))   # the single-candidate residuals
+
     def resid(coef: np.ndarray, src_perm: np.ndarray) -> np.ndarray:
-        """|| A z_p - coef_i z_p || for p = src_perm[i]."""
-        R = torch.empty_like(Zb)
-        P = torch.empty_like(Zb)
+        """|| A z_p - coef_i z_p || for p = src_perm[i] (a batch of the
+        candidates' width, or single-vector fields for one candidate)."""
+        if len(src_perm) == 1:
+            P, R = one
+            w = 1
+        else:
+            R = torch.empty_like(Zb)
+            P = torch.empty_like(Zb)
+            w = kp
         for i, p in enumerate(src_perm):
             L.field_copy_vector(dims, F64, Zb, int(p), P, i)
             L.field_copy_vector(dims, F64, AZ, int(p), R, i)
-        cpad = np.zeros(kp, dtype=np.complex128)
+        cpad = np.zeros(w, dtype=np.complex128)
         cpad[: len(coef)] = -np.asarray(coef)
-        L.field_axpby(dims, F64, _c(cpad), P, _c(np.ones(kp)), R)
-        out = torch.empty(kp, dtype=torch.complex128, device="cuda")
+        L.field_axpby(dims, F64, _c(cpad), P, _c(np.ones(w)), R)
+        out = torch.empty(w, dtype=torch.complex128, device="cuda")
         L.field_dot(dims, F64, R, R, out, wsd)
         return np.sqrt(np.maximum(out.cpu().numpy().real[: len(coef)], 0.0))
 
