@@ -23,13 +23,26 @@ import numpy as np
 import torch
 
 import synth
-from synth.configs import LatticeConfig, poly_mvps
+from synth.configs import LatticeConfig
 
 from synth.configs import SOLVE
 
 from . import _lib as L
 from . import krylov, probing
 from .solve import MixedPPGMRES, SolveNotConverged, SolveStats
+
+
+def poly_mvps(p) -> int:
+    """Operator applications of one polynomial application (Sec. 3.1, Sec. 3.2):
+    d for a single polynomial of degree d, n_in n_out - 1 for a double one
+    given as (n_in, n_out), none for a level without a polynomial or a solve
+    (whose cost depends on its convergence and is counted by the solver)."""
+    if p is None or p == SOLVE:
+        return 0
+    if isinstance(p, tuple):
+        n_in, n_out = p
+        return n_in * n_out - 1
+    return int(p)
 
 
 @dataclass

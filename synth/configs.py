@@ -56,16 +56,6 @@ class LatticeConfig:
         return 12 * self.volume
 
 
-def poly_mvps(p: Optional[Poly]) -> int:
-    """Matrix-vector products per application (Sec. 3.1, Sec. 3.2)."""
-    if p is None or p == SOLVE:
-        return 0          # a solve's cost depends on its convergence; counted by the solver
-    if isinstance(p, tuple):
-        n_in, n_out = p
-        return n_in * n_out - 1
-    return int(p)
-
-
 C1 = LatticeConfig(
     name="C1", dims=(4, 4, 4, 4), eps=0.5, kappa=0.150,
     levels=(Level(20, 5, 100), Level(5, None, 100)),

@@ -10,7 +10,6 @@ import oracle
 import synth
 from oracle import dense, krylov
 from oracle.deflation import composite_eval, poly_eval, residual_poly_eval
-from synth.configs import poly_mvps
 
 
 def _lat(dims, kappa=0.15, eps=0.5, seed=7):
@@ -136,13 +135,6 @@ def test_composite_reproduces_pp_gmres():
     assert np.linalg.norm(x - xd) <= 1e-9 * np.linalg.norm(x)
 
 
-def test_degree_arithmetic():
-    # (dp_in + 1)(dp_out + 1) - 1 with the examples quoted in Sec. 3.2 and Sec. 5
-    assert poly_mvps((30, 31)) == 929
-    assert poly_mvps((30, 12)) == 359
-    assert poly_mvps((50, 33)) == 1649
-    assert poly_mvps((20, 15)) == 299
-    assert 615 ** 2 == 378225 and 30 ** 2 + 31 ** 2 == 1861
 
 
 @pytest.mark.parametrize("rtol", [1e-3, 1e-6])

@@ -24,6 +24,18 @@ def pk():
     return krylov
 
 
+def test_degree_arithmetic(pk):
+    # operator applications per polynomial application, against the counts the
+    # paper states for its double polynomials (Sec. 3.2, Sec. 5):
+    # (d_in + 1)(d_out + 1) - 1 for (n_in, n_out) = (d_in + 1, d_out + 1)
+    from paper_2306_09559_amd.driver import poly_mvps
+    assert poly_mvps((30, 31)) == 929
+    assert poly_mvps((30, 12)) == 359
+    assert poly_mvps((50, 33)) == 1649
+    assert poly_mvps((20, 15)) == 299
+    assert poly_mvps(150) == 150 and poly_mvps(None) == 0
+
+
 def _hess(n, seed):
     rng = np.random.default_rng(seed)
     H = np.triu(rng.standard_normal((n + 1, n)) + 1j * rng.standard_normal((n + 1, n)), -1)
