@@ -156,13 +156,15 @@ const char *mpmc_build_info(void);
  *   MPMC_OPT_PLANE_SWEEP  2 (default): scalar-mode single polynomials on a
  *     lattice whose xyz-plane (Lx*Ly*Lz a multiple of 64, at most 512 sites
  *     and 160 KiB of LDS at the field precision) run as a t-sweep with one
- *     workgroup per vector when the batch has at least half as many vectors
- *     as the GPU has CUs (below that the streaming kernel is faster: the
- *     sweep's launch time does not shrink with the batch); larger planes
- *     take the blocked t-sweep when the batch fills the GPU; probe vectors
- *     always take the t-sweep.  1: the t-sweep whenever the lattice admits
- *     one (mpmc_sweep_plan ok), whatever the batch.  0: always the
- *     streaming site-parallel kernel (probe vectors: unsupported).
+ *     workgroup per (vector, t-chunk) when those workgroups cover the GPU's
+ *     CUs (below that the streaming kernel is faster: the sweep's launch time
+ *     does not shrink with the batch); larger FP32 planes take the blocked
+ *     t-sweep when its workgroups, in t-chunks of at least 4 planes, cover
+ *     the CUs; vector mode at block width 1 takes the sweep when its threads
+ *     fill the GPU; probe vectors always take the t-sweep.  1: the t-sweep
+ *     whenever the lattice admits one (mpmc_sweep_plan ok), whatever the
+ *     batch.  0: always the streaming site-parallel kernel (probe vectors:
+ *     unsupported).
  *   MPMC_OPT_SWEEP_RANK   0 (default) .. 63: on FP32 planes too large for
  *     one workgroup, the t-sweep cuts the plane into xyz-blocks with a halo
  *     in LDS; the candidate blocks are ranked by the bytes each moves per
@@ -173,17 +175,28 @@ const char *mpmc_build_info(void);
  *   MPMC_OPT_LINK_BUF     1 (default): the streaming kernel reads the links
  *     through buffer loads when the link array is below 4 GiB; 0: always
  *     through 64-bit flat addresses (the path of larger arrays).
+ *   MPMC_OPT_SWEEP_CHUNKS 0 (default): the plan chooses how many t-chunks a
+ *     t-sweep's planes are cut into (each workgroup walks Lt / k planes,
+ *     starting from its chunk's previous plane, so that small batches still
+ *     occupy the GPU); k = 1 .. 1024: k chunks when k divides Lt and the
+ *     partial sums fit the polynomial workspace, else 1.
  * Every choice computes the same values up to the order of floating-point
  * sums (the work order changes no value at all). */
-enum { MPMC_OPT_PLANE_SWEEP = 1, MPMC_OPT_SWEEP_RANK = 2, MPMC_OPT_HOP_SLAB = 3, MPMC_OPT_LINK_BUF = 4 };
+enum {
+    MPMC_OPT_PLANE_SWEEP = 1,
+    MPMC_OPT_SWEEP_RANK = 2,
+    MPMC_OPT_HOP_SLAB = 3,
+    MPMC_OPT_LINK_BUF = 4,
+    MPMC_OPT_SWEEP_CHUNKS = 5
+};
 int mpmc_set_option(int32_t option, int32_t value);
 
 /* Which t-sweep a scalar-mode polynomial on this lattice and batch would
- * use (host only, enqueues nothing).  out (host, 8 int32): [0] 1 if a sweep
+ * use (host only, enqueues nothing).  out (host, 9 int32): [0] 1 if a sweep
  * applies, [1] 1 if the xyz-plane is cut into blocks with a halo in LDS (FP32
  * lattices whose plane exceeds one workgroup), [2..4] block extents in x, y,
  * z, [5] sites per block (= workgroup size), [6] halo sites, [7] blocks per
- * plane. */
+ * plane, [8] t-chunks (each workgroup walks Lt / [8] planes). */
 int mpmc_sweep_plan(const mpmc_lattice *lat, mpmc_shape shape, int32_t *out);
 
 /* *counter += increment, enqueued on `stream` as a one-thread kernel (plain

@@ -29,7 +29,7 @@ OK, EINVAL, EUNSUPPORTED, EWORKSPACE, EHIP, ESINGULAR, ENOTCONVERGED = 0, -1, -2
 F64, F32 = 0, 1
 DEFL_COEFF, DEFL_RECON, DEFL_PROJECT = 0, 1, 2
 OP_NONE, OP_POLY, OP_DEFLATED_POLY, OP_SOLVE = 0, 1, 2, 3
-OPT_PLANE_SWEEP, OPT_SWEEP_RANK, OPT_HOP_SLAB, OPT_LINK_BUF = 1, 2, 3, 4
+OPT_PLANE_SWEEP, OPT_SWEEP_RANK, OPT_HOP_SLAB, OPT_LINK_BUF, OPT_SWEEP_CHUNKS = 1, 2, 3, 4, 5
 # MPMC_OPT_PLANE_SWEEP values: never, whenever the lattice admits one, when the batch keeps half the CUs busy
 SWEEP_OFF, SWEEP_ALWAYS, SWEEP_AUTO = 0, 1, 2
 
@@ -281,11 +281,12 @@ def workspace(nbytes: int, device="cuda") -> torch.Tensor:
 # ------------------------------------------------------------------ entry points
 def sweep_plan(lat: "DeviceLattice", nrhs: int, rb: int) -> dict:
     """The t-sweep a scalar-mode polynomial would use on this lattice and batch."""
-    out = (c_i32 * 8)()
+    out = (c_i32 * 9)()
     L = lat.c()
     _check("mpmc_sweep_plan", _lib.mpmc_sweep_plan(ctypes.byref(L), mpmc_shape(nrhs, rb), out))
     v = list(out)
-    return dict(ok=bool(v[0]), halo=bool(v[1]), block=tuple(v[2:5]), sites=v[5], halo_sites=v[6], blocks=v[7])
+    return dict(ok=bool(v[0]), halo=bool(v[1]), block=tuple(v[2:5]), sites=v[5], halo_sites=v[6], blocks=v[7],
+                chunks=v[8])
 
 
 def probe_fill(dims, prec: int, colour: torch.Tensor, first_probe: int, field: torch.Tensor):

@@ -9,14 +9,14 @@ namespace mpmc {
 
 int g_opt_sweep = 2;
 int g_opt_sweep_rank = 0;
+int g_opt_sweep_chunks = 0;
 int g_opt_hop_slab = 1;
 int g_opt_link_buf = 1;
 
 size_t poly_ws_bytes(const int32_t dims[4], int32_t prec, const mpmc_poly &poly, mpmc_shape sh) {
     const size_t fb = align256(field_bytes(dims, prec, sh.nrhs));
     const int V = dims[0] * dims[1] * dims[2] * dims[3];
-    const FieldTiling t = make_tiling(V, sh.nrhs, sh.rb);
-    const size_t part = align256((size_t)t.groups() * (size_t)sh.rb * sizeof(double2));
+    const size_t part = align256(poly_part_count((size_t)V, sh.nrhs, sh.rb) * sizeof(double2));
     const int nf = poly.n_out > 0 ? 5 : (poly.n_in > 1 ? 2 : 0);
     return (size_t)nf * fb + part;
 }
@@ -132,6 +132,10 @@ int mpmc_set_option(int32_t option, int32_t value) {
         if (value != 0 && value != 1) return MPMC_EINVAL;
         g_opt_link_buf = value;
         return MPMC_OK;
+    case MPMC_OPT_SWEEP_CHUNKS:
+        if (value < 0 || value > 1024) return MPMC_EINVAL;
+        g_opt_sweep_chunks = value;
+        return MPMC_OK;
     default: return MPMC_EUNSUPPORTED;
     }
 }
@@ -151,8 +155,8 @@ int mpmc_sweep_plan(const mpmc_lattice *lat, mpmc_shape shape, int32_t *out) {
     MPMC_TRY(check_lattice(lat));
     if (!valid_shape(shape) || !out) return MPMC_EINVAL;
     const SweepPlan p = sweep_plan(*lat, shape);
-    const int32_t v[8] = {p.ok ? 1 : 0, p.halo ? 1 : 0, p.B[0], p.B[1], p.B[2], p.Pb, p.Hb, p.nbp};
-    for (int i = 0; i < 8; ++i) out[i] = v[i];
+    const int32_t v[9] = {p.ok ? 1 : 0, p.halo ? 1 : 0, p.B[0], p.B[1], p.B[2], p.Pb, p.Hb, p.nbp, p.nch};
+    for (int i = 0; i < 9; ++i) out[i] = v[i];
     return MPMC_OK;
 }
 

@@ -677,10 +677,11 @@ int poly_apply_t(const mpmc_lattice &lat, const mpmc_poly &poly, mpmc_shape sh, 
     if (poly.n_out == 0 && poly.n_in >= 2 && y != nullptr && sh.rb == 1 && (noise != nullptr || bhy == nullptr) &&
         g_opt_sweep) {
         // vector mode on the t-sweep: y (block width 1, like the sweep's own
-        // outputs) accumulates t_j w_j in the same launches; only when the
-        // batch fills the GPU (the sweep walks all planes per workgroup)
+        // outputs) accumulates t_j w_j in the same launches; when the batch,
+        // chunked in t, fills the GPU (option 1: whenever the lattice admits a
+        // sweep)
         const SweepPlan plan = sweep_plan(lat, sh);
-        if (plan.ok && plan.fills)
+        if (plan.ok && (plan.fills || g_opt_sweep == 1))
             return sweep_newton_t<T>(lat, sh, plan, poly.n_in, poly.inv_roots_in, x, x_noise, bhy ? bvec : nullptr,
                                      key, first, off, bhy ? part : nullptr, (double2 *)bhy, ws.f[0], ws.f[1], y,
                                      stream);

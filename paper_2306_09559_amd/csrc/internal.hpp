@@ -21,6 +21,15 @@ inline size_t field_bytes(const int32_t dims[4], int32_t prec, int32_t nrhs) {
     return V * 12 * (size_t)nrhs * (prec == MPMC_F64 ? 16 : 8);
 }
 
+// FP64 complex partial sums the polynomial workspace holds: one per (site
+// block of 256 / rb sites, vector) for the field kernels, and at least one per
+// (64 sites, vector), which covers every (t-chunk, xyz-block) of a t-sweep
+// (blocks of at least 64 sites, at most Lt chunks)
+inline size_t poly_part_count(size_t V, int nrhs, int rb) {
+    const size_t spw = 256 / (size_t)rb;
+    const size_t a = (V + spw - 1) / spw, b = (V + 63) / 64;
+    return (a > b ? a : b) * (size_t)nrhs;
+}
 size_t poly_ws_bytes(const int32_t dims[4], int32_t prec, const mpmc_poly &poly, mpmc_shape sh);
 PolyWs carve_poly_ws(const int32_t dims[4], int32_t prec, const mpmc_poly &poly, mpmc_shape sh, void *ws);
 
@@ -39,8 +48,9 @@ struct SweepPlan {
     int nbp = 1;           // blocks per plane
     size_t lds = 0;        // dynamic LDS bytes
     bool fills = false;    // the batch gives every CU a full workgroup's worth of threads
-    bool busy = false;     // the batch keeps at least half the CUs busy (a whole plane: nrhs >= CUs / 2)
+    bool busy = false;     // the workgroups, in t-chunks, cover the CUs (the sweep beats streaming)
     int nranked = 1;       // blocked planes: candidate blocks ranked by the plan's cost (rank option)
+    int nch = 1;           // t-chunks: each workgroup walks Lt / nch planes
 };
 SweepPlan sweep_plan(const mpmc_lattice &lat, mpmc_shape sh);
 int sweep_prepare_kernels();
@@ -61,6 +71,7 @@ int sweep_chain_t(const mpmc_lattice &lat, mpmc_shape sh, const SweepPlan &plan,
 // and the autotuner set them around each enqueue and restore them after
 extern int g_opt_sweep;
 extern int g_opt_sweep_rank;
+extern int g_opt_sweep_chunks;
 extern int g_opt_hop_slab;
 extern int g_opt_link_buf;
 

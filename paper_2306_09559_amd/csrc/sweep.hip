@@ -16,6 +16,7 @@
 // Newton recurrence, exactly as the streaming kernel does; only the order of
 // the floating-point sums inside a site differs.
 #include "common.hpp"
+#include <algorithm>
 #include <cmath>
 #include "internal.hpp"
 
@@ -38,12 +39,14 @@ template <typename T> struct SweepArgs {
     const int32_t *colour;     // probe vectors of this colouring instead of Z4 noise, or nullptr
     const cplx_t<T> *bvec;     // dot vector field (layout rb_b), or nullptr
     int rb_b;
-    double2 *part;             // N partial sums, one per vector
-    double2 *bhy;              // final sums (last step, whole-plane blocks only), or nullptr
+    double2 *part;             // partial sums, one per (vector, t-chunk, block)
+    double2 *bhy;              // final sums (last step, whole planes in one t-chunk only), or nullptr
     int dot_first;
     // xyz-blocks (HALO): block extents, sites, halo sites, blocks per plane
     int B[3];
     int Pb, Hb, nbp;
+    // t-chunks: a workgroup walks Lt / nch planes (nch divides Lt)
+    int nch;
     // vector mode (YACC): y (block width 1) accumulates t_j w_j, zeroed first, + t_{j+1} w_{j+1} last
     cplx_t<T> *y;
     int y_first, y_last;
@@ -366,7 +369,7 @@ __device__ __forceinline__ void dot_acc(const cplx_t<T> (&b)[12], const cplx_t<T
 // fixed-order tree (LDS plane buffer reused) and added to the vector's (or
 // block's) running partial.
 template <typename T, bool FIRST, bool HALO>
-__device__ __forceinline__ void sweep_dot_finish(const SweepArgs<T> &a, int r, int blk, int q, int Pb, double2 tj,
+__device__ __forceinline__ void sweep_dot_finish(const SweepArgs<T> &a, int r, size_t pi, int q, int Pb, double2 tj,
                                                  double dre, double dim, double d0re, double d0im,
                                                  unsigned char *smem) {
     double2 *red = reinterpret_cast<double2 *>(smem);
@@ -389,8 +392,8 @@ __device__ __forceinline__ void sweep_dot_finish(const SweepArgs<T> &a, int r, i
         n = h;
     }
     if (q == 0) {
-        // one partial per (vector, block); whole-plane blocks also write b^H y at the end
-        const size_t pi = HALO ? (size_t)r * (size_t)a.nbp + (size_t)blk : (size_t)r;
+        // one partial per (vector, t-chunk, block); a whole plane in one
+        // t-chunk also writes b^H y at the end
         double2 tot = red[0];
         if (!FIRST) {
             tot.x += a.part[pi].x;
@@ -410,16 +413,17 @@ __device__ __forceinline__ void sweep_dot_finish(const SweepArgs<T> &a, int r, i
 // the step's epilogue instead, the same update cost 2% per FP64 launch at
 // 8^4 x 256 vectors; as an out-of-line call it made every variant spill).
 template <typename T, bool IN_Z4, bool DOT, bool FIRST, bool BFIELD, bool HALO, bool YACC, bool PROBE>
-__device__ __forceinline__ void sweep_step_no_hop(const SweepArgs<T> &a, int r, int blk, int q, int Pb, int gq,
+__device__ __forceinline__ void sweep_step_no_hop(const SweepArgs<T> &a, int r, size_t pi, int t0, int t1, int q,
+                                                  int Pb, int gq,
                                                NoiseSrc S, unsigned char *smem) {
     using C = cplx_t<T>;
-    const int P = a.P, Lt = a.L[3];
+    const int P = a.P;
     const double2 tj = a.troots[a.j];
     const double2 alpha = make_double2(1.0 - tj.x, -tj.y);
     const Plane<T> inp = plane_of<T>(a.in, r, a.V, a.rb_in);
     const Plane<T> outp = plane_of<T>(a.out, r, a.V, 1);
     double dre = 0.0, dim = 0.0, d0re = 0.0, d0im = 0.0;
-    for (int t = 0; t < Lt; ++t) {
+    for (int t = t0; t < t1; ++t) {
         const int s = gq + t * P;
         C w[12], o[12];
         load_plane_site<T, PROBE>(inp, IN_Z4, S, s, w);
@@ -452,7 +456,7 @@ __device__ __forceinline__ void sweep_step_no_hop(const SweepArgs<T> &a, int r, 
             }
         }
     }
-    if (DOT) sweep_dot_finish<T, FIRST, HALO>(a, r, blk, q, Pb, tj, dre, dim, d0re, d0im, smem);
+    if (DOT) sweep_dot_finish<T, FIRST, HALO>(a, r, pi, q, Pb, tj, dre, dim, d0re, d0im, smem);
 }
 
 }  // namespace
@@ -474,13 +478,16 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
     const int P = a.P, Lt = a.L[3];
     const int Lx = a.L[0], Ly = a.L[1], Lz = a.L[2];
     const int q = (int)threadIdx.x;               // site within the block
-    int r, blk = 0;
+    int r, blk = 0, ch;
     int x, y, z, bx, by, bz, Pb, Hb;
     if (HALO) {
-        // blocks of one vector are consecutive logical ids: one XCD, shared halos in its L2
+        // the blocks of one (vector, t-chunk) are consecutive logical ids: one
+        // XCD, shared halos in its L2
         const unsigned lg = xcd_remap(blockIdx.x, gridDim.x);
-        r = (int)(lg / (unsigned)a.nbp);
         blk = (int)(lg % (unsigned)a.nbp);
+        const unsigned rc = lg / (unsigned)a.nbp;
+        r = (int)(rc / (unsigned)a.nch);
+        ch = (int)(rc % (unsigned)a.nch);
         bx = a.B[0];
         by = a.B[1];
         bz = a.B[2];
@@ -491,7 +498,8 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
         y = ((blk / nbx) % nby) * by + (q / bx) % by;
         z = (blk / (nbx * nby)) * bz + q / (bx * by);
     } else {
-        r = (int)blockIdx.x;
+        r = (int)(blockIdx.x / (unsigned)a.nch);
+        ch = (int)(blockIdx.x % (unsigned)a.nch);
         bx = Lx;
         by = Ly;
         bz = Lz;
@@ -555,8 +563,11 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
     const double2 beta = make_double2(a.kappa * tj.x, a.kappa * tj.y);   // kappa t_j
     const uint64_t g = sample_base(a.first, a.off) + (uint64_t)r;      // global sample (or probe) index
     const NoiseSrc S{PROBE ? 0ull : sample_state(a.key, g), a.colour, (long long)(g / 12u), (int)(g % 12u)};
+    // this workgroup's planes t0 .. t1-1 and its partial sum
+    const int tc = Lt / a.nch, t0 = ch * tc, t1 = t0 + tc;
+    const size_t pidx = ((size_t)r * (size_t)a.nch + (size_t)ch) * (size_t)a.nbp + (size_t)blk;
     if (a.kappa * (tj.x * tj.x + tj.y * tj.y) == 0.0) {   // kappa t_j = 0 (uniform over the launch)
-        sweep_step_no_hop<T, IN_Z4, DOT, FIRST, BFIELD, HALO, YACC, PROBE>(a, r, blk, q, Pb, gq, S, smem);
+        sweep_step_no_hop<T, IN_Z4, DOT, FIRST, BFIELD, HALO, YACC, PROBE>(a, r, pidx, t0, t1, q, Pb, gq, S, smem);
         return;
     }
     const Plane<T> inp = plane_of<T>(a.in, r, a.V, a.rb_in);
@@ -577,16 +588,18 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
     constexpr bool OWN = sizeof(T) == 4 && !HALO && !FIRST;
     constexpr bool TWOL = OWN ? false : TWO;
     C *bwl = stl + 6 * Pb;
-    // prologue: -t term of plane 0 from plane Lt-1; cur (and halo) = plane 0
+    // prologue: -t term of plane t0 from plane t0-1 (Lt-1 for t0 = 0, across
+    // the boundary); cur (and halo) = plane t0
     C stash[2][3];
     {
         C p[12];
-        load_plane_site<T, PROBE>(inp, IN_Z4, S, gq + (Lt - 1) * P, p);
+        const int tp = t0 == 0 ? Lt - 1 : t0 - 1;
+        load_plane_site<T, PROBE>(inp, IN_Z4, S, gq + tp * P, p);
         proj<T, 3, false>(p, stash);
         C U[9];
-        load_link<T>(gt, estride, gq + (Lt - 1) * P, two, U);
+        load_link<T>(gt, estride, gq + tp * P, two, U);
         mul_link<T, true>(U, stash);
-        const T sg = a.apbc ? T(-1) : T(1);
+        const T sg = (t0 == 0 && a.apbc) ? T(-1) : T(1);
 #pragma unroll
         for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
@@ -600,12 +613,12 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
     // 8^4 x 256 vectors FP64, with the hops unrolled: 112 -> 106 us per launch;
     // at 64 vectors 83 -> 75 us).
     C Ust[9];
-    link_raw<T, TWOL>(gt, estride, gq, Ust);
+    link_raw<T, TWOL>(gt, estride, gq + t0 * P, Ust);
     C cur[12];
-    load_plane_site<T, PROBE>(inp, IN_Z4, S, gq, cur);
+    load_plane_site<T, PROBE>(inp, IN_Z4, S, gq + t0 * P, cur);
     C hcur[12];
     if constexpr (HALO) {
-        if (q < Hb) load_plane_site<T, PROBE>(inp, IN_Z4, S, ghq, hcur);
+        if (q < Hb) load_plane_site<T, PROBE>(inp, IN_Z4, S, ghq + t0 * P, hcur);
     }
 
     // out = alpha w + beta D w is formed as beta * ((alpha/beta) w + D w): the
@@ -621,7 +634,7 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
     }
 
     double dre = 0.0, dim = 0.0, d0re = 0.0, d0im = 0.0;
-    for (int t = 0; t < Lt; ++t) {
+    for (int t = t0; t < t1; ++t) {
         const int s = gq + t * P;
         const T sg = (t + 1 == Lt && a.apbc) ? T(-1) : T(1);
 #pragma unroll
@@ -836,10 +849,11 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs<T> a) {
         }
     }
 
-    if (DOT) sweep_dot_finish<T, FIRST, HALO>(a, r, blk, q, Pb, tj, dre, dim, d0re, d0im, smem);
+    if (DOT) sweep_dot_finish<T, FIRST, HALO>(a, r, pidx, q, Pb, tj, dre, dim, d0re, d0im, smem);
 }
 
-// b^H y of a blocked sweep: the blocks' partials of each vector in a fixed order
+// b^H y of a blocked or t-chunked sweep: the (t-chunk, block) partials of each
+// vector in a fixed order
 __global__ void k_sweep_sum(const double2 *part, int nbp, int nrhs, double2 *bhy) {
     const int r = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (r >= nrhs) return;
@@ -867,17 +881,61 @@ SweepPlan sweep_plan(const mpmc_lattice &lat, mpmc_shape sh) {
     if (!cus[dev] && hipDeviceGetAttribute(&cus[dev], hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return p;
     const size_t min_threads = (size_t)cus[dev] * 512;
-    p.fills = (size_t)sh.nrhs * (size_t)P >= min_threads;
-    // A whole-plane sweep runs one workgroup per vector for the whole launch,
-    // so its launch takes about as long for 16 vectors as for 256; the
-    // streaming kernel's time grows with the vectors.  Measured on 8^4 per
-    // launch (sweep / streaming): FP64 72 / 27 us at 32 vectors, 74 / 51 at
-    // 64, 77 / 92 at 128, 102 / 170 at 256; FP32 55 / 19, 56 / 32, 57 / 54,
-    // 64 / 99.  Half the CUs is where the two meet.
-    p.busy = 2 * (size_t)sh.nrhs >= (size_t)cus[dev];
+    // partial sums the polynomial workspace holds
+    const size_t avail = poly_part_count(V, sh.nrhs, sh.rb);
+    // t-chunks.  A workgroup walks the Lt / k planes of its chunk, starting
+    // from a prologue that forms the -t term of its first plane from the
+    // plane before, so k chunks give k times the workgroups for one more plane
+    // read per chunk.  Of the k that divide Lt (chunks of at least min_len
+    // planes, partial sums within the workspace), the plan takes the one with
+    // the least modelled time, rounds of workgroups (C at a time) times
+    // (planes per chunk + 2), among those whose launch gives every CU a
+    // workgroup; if none does, the sweep is not worth its launch (`fill`
+    // false) and the cheapest k is kept for callers that force it.  Measured
+    // per launch (FP32 unless noted; sweep with k chunks against streaming):
+    // 8^4 x 64 vectors k = 1 / 2 / 4: 56.7 / 33.6 / 23.7 us, streaming 32.5
+    // (FP64 74.9 / 45.0 / 36.1, streaming 52.6); 16^4 x 16 k = 2 / 4 / 8:
+    // 86.3 / 96.0 / 112.4, streaming 112.2; 24^3x48 x 32 k = 1 / 2 / 4:
+    // 2059 / 1916 / 1970, streaming 2032; 8^4 x 256 k = 1 / 2 / 4: 67.1 /
+    // 73.2 / 82.1, streaming 109.9.
+    struct Chunks {
+        int k;
+        bool fill;
+    };
+    auto chunks = [&](size_t W, size_t C, int min_len) {
+        if (g_opt_sweep_chunks > 0) {
+            const size_t f = (size_t)g_opt_sweep_chunks;
+            const size_t k = (Lt % g_opt_sweep_chunks == 0 && W * f <= avail) ? f : 1;
+            return Chunks{(int)k, W * k >= C};
+        }
+        Chunks best{1, W >= C}, any{1, W >= C};
+        double tbest = 1e300, tany = 1e300;
+        for (int k = 1; k <= Lt; ++k) {
+            if (Lt % k || (k > 1 && Lt / k < min_len) || W * (size_t)k > avail) continue;
+            const double t = (double)((W * (size_t)k + C - 1) / C) * (double)(Lt / k + 2);
+            if (t < tany) {
+                tany = t;
+                any = Chunks{k, W * (size_t)k >= C};
+            }
+            if (W * (size_t)k >= C && t < tbest) {
+                tbest = t;
+                best = Chunks{k, true};
+            }
+        }
+        return tbest < 1e300 ? best : any;
+    };
+    // A whole-plane sweep runs one workgroup per (vector, t-chunk) for the
+    // whole launch, so a launch that leaves CUs idle takes about as long as
+    // one that does not, while the streaming kernel's time grows with the
+    // vectors: the sweep applies when its workgroups, chunked, cover the CUs
+    // (one per CU: the LDS holds one plane).
     const size_t whole = (lat.prec == MPMC_F32 ? 36 : 18) * (size_t)P * csz;
     if (P >= 64 && P <= 512 && P % 64 == 0 && whole <= kLds) {
         // the whole xyz-plane in one workgroup (neighbours wrap inside it)
+        const Chunks c = chunks((size_t)sh.nrhs, (size_t)cus[dev], 2);
+        p.nch = c.k;
+        p.busy = c.fill;
+        p.fills = (size_t)sh.nrhs * (size_t)P * (size_t)c.k >= min_threads;
         p.ok = true;
         p.B[0] = Lx;
         p.B[1] = Ly;
@@ -887,13 +945,10 @@ SweepPlan sweep_plan(const mpmc_lattice &lat, mpmc_shape sh) {
         return p;
     }
     if (lat.prec != MPMC_F32) return p;                        // FP64 blocks + halo exceed the registers
-    // A blocked sweep walks all Lt planes inside each workgroup: it pays only
-    // when the launch still gives every CU a full workgroup's worth of
-    // threads; small batches on large planes stay on the streaming kernel.
-    if (!p.fills) return p;
-    // partial sums: one per (vector, block) in the polynomial workspace
-    const size_t spw = 256 / (size_t)sh.rb;
-    const size_t avail = ((V + spw - 1) / spw) * (size_t)sh.nrhs;
+    // A blocked sweep pays only when its launch, chunked in t (chunks of at
+    // least 4 planes), gives every CU a workgroup; small batches on large
+    // planes stay on the streaming kernel (12^3x24 x 8 vectors would need
+    // 2-plane chunks: 48.2 us per launch against 42.6 streaming).
     // Sites are x-fastest over the whole lattice, so a block reads and writes
     // its rows (and its halo rows, and its links) bx sites at a time: whole
     // 128-byte lines only when bx spans the x extent or a multiple of a line.
@@ -953,6 +1008,17 @@ SweepPlan sweep_plan(const mpmc_lattice &lat, mpmc_shape sh) {
     p.Pb = c.Pb;
     p.Hb = c.Hb;
     p.nbp = P / c.Pb;
+    // workgroups resident per CU: the LDS's limit and two waves per SIMD
+    // (the kernels take over 128 VGPRs)
+    const size_t wpc = std::max<size_t>(1, std::min<size_t>(kLds / c.lds, 512 / (size_t)c.Pb));
+    const Chunks ck = chunks((size_t)sh.nrhs * (size_t)p.nbp, (size_t)cus[dev] * wpc, 4);
+    if (!ck.fill) {
+        p.ok = false;
+        p.halo = false;
+        return p;
+    }
+    p.nch = ck.k;
+    p.fills = true;
     p.lds = c.lds;
     p.nranked = nc;
     return p;
@@ -1041,6 +1107,7 @@ static SweepArgs<T> sweep_args(const mpmc_lattice &lat, const SweepPlan &plan, c
     a.Pb = plan.Pb;
     a.Hb = plan.Hb;
     a.nbp = plan.nbp;
+    a.nch = plan.nch;
     return a;
 }
 
@@ -1062,7 +1129,9 @@ int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, const SweepPlan &plan
     const bool y = yacc != nullptr;
     if (!dot && !y) return MPMC_EINVAL;
     const int d = n - 1;
-    const dim3 grid((unsigned)(sh.nrhs * plan.nbp)), block((unsigned)plan.Pb);
+    const dim3 grid((unsigned)(sh.nrhs * plan.nbp * plan.nch)), block((unsigned)plan.Pb);
+    // b^H y straight from the kernel only when one workgroup covers a vector
+    const bool sum_after = plan.halo || plan.nch > 1;
     for (int j = 0; j < d; ++j) {
         a.j = j;
         const bool first_step = (j == 0);
@@ -1070,7 +1139,7 @@ int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, const SweepPlan &plan
         a.rb_in = first_step ? sh.rb : 1;
         a.out = (cplx_t<T> *)(j % 2 == 0 ? w0 : w1);
         a.dot_first = first_step;
-        a.bhy = (j == d - 1 && !plan.halo) ? bhy : nullptr;
+        a.bhy = (j == d - 1 && !sum_after) ? bhy : nullptr;
         a.y_first = first_step;
         a.y_last = (j == d - 1);
         const int v = first_step ? (x_is_noise ? 0 : 1) : 2;
@@ -1082,9 +1151,9 @@ int sweep_newton_t(const mpmc_lattice &lat, mpmc_shape sh, const SweepPlan &plan
         if (hipLaunchKernel(k, grid, block, args, plan.lds, (hipStream_t)stream) != hipSuccess) return MPMC_EHIP;
         if (hipGetLastError() != hipSuccess) return MPMC_EHIP;
     }
-    if (plan.halo && bhy) {
+    if (sum_after && bhy) {
         hipLaunchKernelGGL(k_sweep_sum, dim3((sh.nrhs + 255) / 256), dim3(256), 0, (hipStream_t)stream,
-                           (const double2 *)part, plan.nbp, sh.nrhs, bhy);
+                           (const double2 *)part, plan.nbp * plan.nch, sh.nrhs, bhy);
         if (hipGetLastError() != hipSuccess) return MPMC_EHIP;
     }
     return MPMC_OK;
@@ -1099,7 +1168,7 @@ int sweep_chain_t(const mpmc_lattice &lat, mpmc_shape sh, const SweepPlan &plan,
     const void *k = sweep_kernel<T>(false, false, false, lat.link_rows == 2, plan.halo, 2);
     if (!k) return MPMC_EUNSUPPORTED;
     if (ensure_lds_attr(k) != MPMC_OK) return MPMC_EHIP;
-    const dim3 grid((unsigned)(sh.nrhs * plan.nbp)), block((unsigned)plan.Pb);
+    const dim3 grid((unsigned)(sh.nrhs * plan.nbp * plan.nch)), block((unsigned)plan.Pb);
     const void *cur = in;
     for (int j = 0; j < count; ++j) {
         a.j = j;

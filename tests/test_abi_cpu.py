@@ -199,7 +199,7 @@ def test_set_option_checks_its_arguments(L):
     are restored afterwards (the options are process-wide)."""
     lib = L._lib
     ranges = {L.OPT_PLANE_SWEEP: (0, 2, 2), L.OPT_SWEEP_RANK: (0, 63, 0), L.OPT_HOP_SLAB: (0, 1, 1),
-              L.OPT_LINK_BUF: (0, 1, 1)}
+              L.OPT_LINK_BUF: (0, 1, 1), L.OPT_SWEEP_CHUNKS: (0, 1024, 0)}
     for opt, (lo, hi, default) in ranges.items():
         assert lib.mpmc_set_option(opt, lo) == L.OK
         assert lib.mpmc_set_option(opt, hi) == L.OK

@@ -692,6 +692,67 @@ def test_vector_mode_sweep(dims, prec, nrhs, field_in, dot):
             assert abs(bs[1][r] - np.vdot(x, want)) <= 1e-12 * abs(np.vdot(x, want))
 
 
+@pytest.mark.parametrize("dims,prec,nrhs,rb,chunks", [
+    ((8, 8, 8, 8), 0, 32, 8, (2, 4, 8)),        # whole plane, down to one plane per chunk
+    ((4, 4, 4, 6), 0, 5, 1, (2, 3, 6)),         # whole plane, odd chunk lengths, 5 vectors
+    ((8, 8, 8, 8), 1, 64, 16, (2, 4)),          # FP32 whole plane (own backward-hop products)
+    # blocked planes are offered only when the unchunked launch already
+    # covers the CUs: 32 x 8 workgroups of 512 sites, 64 x 9 of 192 (two per CU)
+    ((16, 16, 16, 8), 1, 32, 8, (2, 4, 8)),     # FP32 16 x 4 x 8 blocks with a halo
+    ((12, 12, 12, 4), 1, 64, 8, (2, 4)),        # FP32 12 x 4 x 4 blocks, cut in y and z
+])
+def test_sweep_t_chunks(dims, prec, nrhs, rb, chunks):
+    """The t-sweep cut into k t-chunks (each workgroup walks Lt / k planes,
+    starting from a prologue that forms the -t term of its first plane from
+    the plane before; the partial sums of every (chunk, block) are summed
+    after the launch), with an inverse root 0 among the roots (a step without
+    hops): scalar mode on Z4 noise and vector mode y = p(A) b with b^H y,
+    against the oracle and against the unchunked sweep, for every k."""
+    L = lib()
+    dl, ol = device_lattice(dims, 0.14, 0.4, 57, True, prec=prec)
+    deg = 7
+    t = krylov.gmres_polys(ol.apply, synth.gaussian_start(ol.n, 4), [deg]).inv_roots[deg]
+    t = np.insert(t, 3, 0.0)
+    poly = L.DevicePoly(dev_c128(t))
+    nz = L.Noise(8, 3, 0, 5)
+    B = oracle.z4(8, 3, 0, 5, nrhs, dl.V)
+    _, ref = ol.poly_apply(t, B)
+    kN = newton_amplification(ol.apply, t, B[:2])
+    tol = 1e-12 if prec == 0 else 8 * len(t) * kN * U32
+    ws = L.workspace(L.poly_workspace_size(dl, poly, nrhs, rb))
+    ws1 = L.workspace(L.poly_workspace_size(dl, poly, nrhs, 1))
+    L.set_option(L.OPT_PLANE_SWEEP, 1)
+    got = {}
+    try:
+        for k in (1,) + tuple(chunks):
+            L.set_option(L.OPT_SWEEP_CHUNKS, k)
+            plan = L.sweep_plan(dl, nrhs, rb)
+            assert plan["ok"] and plan["chunks"] == k and plan["halo"] == (dl.V // dims[3] > 512), plan
+            assert L.sweep_plan(dl, nrhs, 1)["chunks"] == k
+            bhy = torch.empty(nrhs, dtype=torch.complex128, device="cuda")
+            L.poly_apply(dl, poly, nrhs, rb, None, nz, None, bhy, ws)
+            y = L.empty_field(dl.V, nrhs, 1, prec)
+            bhy1 = torch.empty(nrhs, dtype=torch.complex128, device="cuda")
+            L.poly_apply(dl, poly, nrhs, 1, None, nz, y, bhy1, ws1)
+            torch.cuda.synchronize()
+            got[k] = (bhy.cpu().numpy(), unpack(dims, y, prec), bhy1.cpu().numpy())
+    finally:
+        L.set_option(L.OPT_SWEEP_CHUNKS, 0)
+    for k, (s, Y, s1) in got.items():
+        err = np.max(np.abs(s - ref) / np.abs(ref))
+        print(dims, "chunks", k, f"scalar rel err {err:.2e}")
+        assert err < tol, k
+        assert np.max(np.abs(s1 - ref) / np.abs(ref)) < tol, k
+        for r in (0, nrhs - 1):
+            want, _ = ol.poly_apply(t, B[r])
+            assert rel(Y[r], want) < tol, (k, r)
+        # against the unchunked sweep: the same site arithmetic, partial sums
+        # grouped differently
+        s0, Y0, _ = got[1]
+        assert np.max(np.abs(s - s0) / np.abs(s0)) < (1e-13 if prec == 0 else tol), k
+        assert np.max(np.abs(Y - Y0)) <= (1e-13 if prec == 0 else tol) * np.max(np.abs(Y0)), k
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_streaming_link_load_paths(prec):
     """The streaming kernel's two ways of reading the links (buffer loads
