@@ -433,7 +433,8 @@ def batched_c5(steps: int):
             "speedup": round(eager / graph, 3), "graph_GBps": round(byts / graph / 1e9, 1),
             "autotuned": {"tune_s": round(tune_s, 2), "graph_parallel_ms_per_step": round(tuned * 1e3, 3),
                           "graph_GBps": round(byts / tuned / 1e9, 1),
-                          "shapes": [{"rb": t.choice[0][0], "sweep": t.choice[0][1], "block_rank": t.choice[0][2]}
+                          "shapes": [{"rb": t.choice[0][0], "sweep": t.choice[0][1], "block_rank": t.choice[0][2],
+                                      "t_chunks": t.choice[0][3]}
                                      for t in tunes]}}
 
 
@@ -738,7 +739,8 @@ def main():
             "value": round(run32.bytes_per_step() / gstep / 1e9, 2), "unit": "GB/s",
             "time_to_eps_s": ad["mixed_batched"]["seconds"],
             "speedup_vs_f64": ad["speedup_mixed_batched_vs_f64"],
-            "shapes": {str(k): {"rb": v[0], "sweep": v[1], "block_rank": v[2]} for k, v in tune.choice.items()},
+            "shapes": {str(k): {"rb": v[0], "sweep": v[1], "block_rank": v[2], "t_chunks": v[3]}
+                       for k, v in tune.choice.items()},
         }
         # measured seconds to eps (the adaptive runs above); the MLMC-optimal cost formula with measured
         # per-sample times is kept beside them as a model

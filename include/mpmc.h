@@ -439,6 +439,7 @@ typedef struct {
     int32_t branch;              /* >= 0 */
     int32_t plane_sweep;         /* kernel selection for this item: MPMC_OPT_PLANE_SWEEP value */
     int32_t sweep_rank;          /* MPMC_OPT_SWEEP_RANK value */
+    int32_t sweep_chunks;        /* MPMC_OPT_SWEEP_CHUNKS value (0: the plan's choice) */
     double *stop_state;          /* device state of mpmc_level_stop_check, or NULL: when given, every
                                     batch is followed by the stopping check on its samples */
     int32_t stop_first, stop_every;  /* the level's check points (as mpmc_level_stop_check) */
@@ -455,12 +456,13 @@ int mpmc_batch_build(mpmc_handle h, const mpmc_batch_item *items, int32_t n_item
  * step was built. */
 int mpmc_batch_launch(mpmc_handle h, void *stream);
 
-/* A kernel shape for one level: RHS block width and the two kernel-selection
+/* A kernel shape for one level: RHS block width and the three t-sweep
  * options above. */
 typedef struct {
     int32_t rb;
     int32_t plane_sweep;
     int32_t sweep_rank;
+    int32_t sweep_chunks;
 } mpmc_tune_choice;
 
 typedef struct {
@@ -475,7 +477,8 @@ size_t mpmc_autotune_workspace_size(const mpmc_lattice *lat, const mpmc_level *l
 /* Time one level's batch of nrhs samples under every candidate shape and
  * pick the fastest: block widths rb = 1, 2, 4, .. 32 dividing nrhs on the
  * streaming kernel; rb >= 8 on the t-sweep where it applies; on FP32 planes
- * cut into blocks, the three best-ranked blocks.  `best` is in/out: on
+ * cut into blocks, the three best-ranked blocks; for each sweep, the plan's
+ * number of t-chunks and the divisors of Lt next to it.  `best` is in/out: on
  * entry the current shape, which is kept unless a candidate is faster by
  * more than keep_within (a fraction, e.g. 0.03); on exit the choice.  Each
  * candidate runs once untimed, then `reps` times between HIP events on

@@ -67,11 +67,12 @@ class mpmc_batch_item(ctypes.Structure):
     _fields_ = [("lat", ctypes.POINTER(mpmc_lattice)), ("level", ctypes.POINTER(mpmc_level)), ("shape", mpmc_shape),
                 ("noise", mpmc_noise), ("counter", c_vp), ("batches", c_i32), ("samples", c_vp), ("acc", c_vp),
                 ("ws", c_vp), ("ws_bytes", c_size), ("branch", c_i32), ("plane_sweep", c_i32),
-                ("sweep_rank", c_i32), ("stop_state", c_vp), ("stop_first", c_i32), ("stop_every", c_i32)]
+                ("sweep_rank", c_i32), ("sweep_chunks", c_i32), ("stop_state", c_vp), ("stop_first", c_i32),
+                ("stop_every", c_i32)]
 
 
 class mpmc_tune_choice(ctypes.Structure):
-    _fields_ = [("rb", c_i32), ("plane_sweep", c_i32), ("sweep_rank", c_i32)]
+    _fields_ = [("rb", c_i32), ("plane_sweep", c_i32), ("sweep_rank", c_i32), ("sweep_chunks", c_i32)]
 
 
 class mpmc_tune_result(ctypes.Structure):
@@ -514,6 +515,7 @@ class BatchItem:
     branch: int = 0
     plane_sweep: int = SWEEP_AUTO
     sweep_rank: int = 0
+    sweep_chunks: int = 0                        # t-chunks of the sweep (0: the plan's choice)
     stop_state: Optional[torch.Tensor] = None    # device float64 (16,): mpmc_level_stop_check after each batch
     stop_first: int = 2
     stop_every: int = 1
@@ -531,7 +533,8 @@ def batch_build(h: Handle, items: Sequence[BatchItem]):
         arr[i] = mpmc_batch_item(ctypes.pointer(L), ctypes.pointer(lv), mpmc_shape(it.nrhs, it.rb), it.noise.c(),
                                  it.counter.data_ptr(), int(it.batches), it.samples.data_ptr(), it.acc.data_ptr(),
                                  it.ws.data_ptr(), it.ws.numel(), int(it.branch), int(it.plane_sweep),
-                                 int(it.sweep_rank), None if it.stop_state is None else it.stop_state.data_ptr(),
+                                 int(it.sweep_rank), int(it.sweep_chunks),
+                                 None if it.stop_state is None else it.stop_state.data_ptr(),
                                  int(it.stop_first), int(it.stop_every))
     _check("mpmc_batch_build", _lib.mpmc_batch_build(h.ptr, arr, len(items)))
     h._keep = keep
@@ -549,7 +552,7 @@ def autotune_workspace_size(lat: DeviceLattice, level: DeviceLevel, nrhs: int) -
 
 def autotune_level(h: Handle, lat: DeviceLattice, level: DeviceLevel, nrhs: int, noise: Noise, current: tuple,
                    reps: int = 3, keep_within: float = 0.03, ws: Optional[torch.Tensor] = None):
-    """mpmc_autotune for one level.  current = (rb, plane_sweep, sweep_rank).
+    """mpmc_autotune for one level.  current = (rb, plane_sweep, sweep_rank, sweep_chunks).
     Returns (choice tuple, seconds per call, cached flag, [(choice, seconds)...])."""
     L = lat.c()
     lv, _keep = level.cstruct()
@@ -563,8 +566,9 @@ def autotune_level(h: Handle, lat: DeviceLattice, level: DeviceLevel, nrhs: int,
         h.ptr, ctypes.byref(L), ctypes.byref(lv), int(nrhs), ctypes.byref(nz), int(reps), float(keep_within),
         _ptr(ws), ws.numel(), ctypes.byref(best), ctypes.byref(secs), ctypes.byref(cached), res, 64,
         ctypes.byref(nres), _stream()))
-    table = [((r.choice.rb, r.choice.plane_sweep, r.choice.sweep_rank), r.seconds) for r in res[: nres.value]]
-    return (best.rb, best.plane_sweep, best.sweep_rank), secs.value, bool(cached.value), table
+    table = [((r.choice.rb, r.choice.plane_sweep, r.choice.sweep_rank, r.choice.sweep_chunks), r.seconds)
+             for r in res[: nres.value]]
+    return (best.rb, best.plane_sweep, best.sweep_rank, best.sweep_chunks), secs.value, bool(cached.value), table
 
 
 def level_stop_check(samples: torch.Tensor, nrhs: int, first: int, every: int, state: torch.Tensor):

@@ -88,7 +88,7 @@ class GraphStep:
                                           it.counter, it.repeats, lv.samples[: it.nsamples], lv.acc, lv.ws,
                                           branch=branch,
                                           plane_sweep=L.SWEEP_AUTO if lv.sweep else L.SWEEP_OFF,
-                                          sweep_rank=int(lv.sweep_rank)))
+                                          sweep_rank=int(lv.sweep_rank), sweep_chunks=int(lv.sweep_chunks)))
         L.batch_build(self.handle, citems)
         if keep_state:
             torch.cuda.synchronize()
@@ -146,19 +146,20 @@ def _key(run: LatticeRun, level: int) -> str:
 
 @dataclass
 class TuneResult:
-    choice: Dict[int, Tuple[int, bool, int]] = field(default_factory=dict)    # level -> (rb, sweep, rank)
+    # level -> (rb, sweep, block rank, t-chunks)
+    choice: Dict[int, Tuple[int, bool, int, int]] = field(default_factory=dict)
     timings: Dict[int, Dict[str, float]] = field(default_factory=dict)
     cached: Dict[int, bool] = field(default_factory=dict)
 
 
 def _label(choice) -> str:
-    rb, sw, rank = choice
-    return f"rb{rb}" + (f"-sweep{'' if rank == 0 else rank}" if sw else "")
+    rb, sw, rank, chunks = choice
+    return f"rb{rb}" + (f"-sweep{'' if rank == 0 else rank}{'' if chunks == 0 else f'-t{chunks}'}" if sw else "")
 
 
 def autotune(run: LatticeRun, reps: int = 3, use_cache: bool = True, cache_path: Optional[str] = None,
              keep_within: float = 0.03, handle: Optional[L.Handle] = None) -> TuneResult:
-    """Pick (rb, sweep, block rank) per polynomial level of `run` with
+    """Pick (rb, sweep, block rank, t-chunks) per polynomial level of `run` with
     mpmc_autotune; applies the choice to the run and resets its
     accumulators.  The level's current shape is kept unless another is
     faster by more than keep_within.  Choices persist in a JSON file."""
@@ -178,22 +179,23 @@ def autotune(run: LatticeRun, reps: int = 3, use_cache: bool = True, cache_path:
         key = _key(run, li)
         if use_cache and key in cache:
             c = cache[key]
-            rb, sw, rank = int(c["rb"]), bool(c["sweep"]), int(c.get("rank", 0))
-            run.set_level_shape(li, rb, sw, rank)
-            res.choice[li] = (rb, sw, rank)
+            rb, sw, rank, chunks = int(c["rb"]), bool(c["sweep"]), int(c.get("rank", 0)), int(c.get("chunks", 0))
+            run.set_level_shape(li, rb, sw, rank, chunks)
+            res.choice[li] = (rb, sw, rank, chunks)
             res.cached[li] = True
             continue
         N = lv.batch
-        cur = (run.level_rb(li), int(lv.sweep), int(lv.sweep_rank))
+        cur = (run.level_rb(li), int(lv.sweep), int(lv.sweep_rank), int(lv.sweep_chunks))
         nz = L.Noise(run.cfg.seed_noise, run.cfg.lattice_id, lv.index, 0)
         best, secs, _hit, table = L.autotune_level(h, run.dl, lv.device, N, nz, cur, reps=reps,
                                                    keep_within=keep_within)
-        rb, sw, rank = best
-        run.set_level_shape(li, rb, bool(sw), rank)
-        res.choice[li] = (rb, bool(sw), rank)
+        rb, sw, rank, chunks = best
+        run.set_level_shape(li, rb, bool(sw), rank, chunks)
+        res.choice[li] = (rb, bool(sw), rank, chunks)
         res.timings[li] = {_label(c): t for c, t in table}
         res.cached[li] = False
-        cache[key] = {"rb": rb, "sweep": bool(sw), "rank": rank, "seconds": secs, "when": time.strftime("%Y-%m-%d")}
+        cache[key] = {"rb": rb, "sweep": bool(sw), "rank": rank, "chunks": chunks, "seconds": secs,
+                      "when": time.strftime("%Y-%m-%d")}
     run.reset()
     if use_cache:
         try:

@@ -33,16 +33,23 @@ namespace {
 
 // the kernel-selection options of one enqueue, restored on scope exit
 struct OptionScope {
-    int sweep, rank;
-    OptionScope(int s, int r) : sweep(g_opt_sweep), rank(g_opt_sweep_rank) {
+    int sweep, rank, chunks;
+    OptionScope(int s, int r, int c) : sweep(g_opt_sweep), rank(g_opt_sweep_rank), chunks(g_opt_sweep_chunks) {
         g_opt_sweep = s;
         g_opt_sweep_rank = r;
+        g_opt_sweep_chunks = c;
     }
     ~OptionScope() {
         g_opt_sweep = sweep;
         g_opt_sweep_rank = rank;
+        g_opt_sweep_chunks = chunks;
     }
 };
+
+bool same_choice(const mpmc_tune_choice &a, const mpmc_tune_choice &b) {
+    return a.rb == b.rb && a.plane_sweep == b.plane_sweep && a.sweep_rank == b.sweep_rank &&
+           a.sweep_chunks == b.sweep_chunks;
+}
 
 void drop_graph(mpmc_handle h) {
     if (h->exec) (void)hipGraphExecDestroy(h->exec);
@@ -113,6 +120,7 @@ int mpmc_batch_build(mpmc_handle h, const mpmc_batch_item *items, int32_t n_item
         if (!polynomial_level(it.level)) return MPMC_EUNSUPPORTED;
         if (it.plane_sweep < 0 || it.plane_sweep > 2) return MPMC_EINVAL;
         if (it.sweep_rank < 0 || it.sweep_rank > 63) return MPMC_EINVAL;
+        if (it.sweep_chunks < 0 || it.sweep_chunks > 1024) return MPMC_EINVAL;
         if (it.stop_state && (it.stop_first < 2 || it.stop_every < 1)) return MPMC_EINVAL;
         // descriptor, shape and workspace (the level call validates the rest while it is recorded,
         // and any failure there abandons the recording: nothing has run)
@@ -144,7 +152,7 @@ int mpmc_batch_build(mpmc_handle h, const mpmc_batch_item *items, int32_t n_item
         for (int i = 0; i < n_items && st == MPMC_OK; ++i) {
             const mpmc_batch_item &it = items[i];
             if (it.branch != b) continue;
-            OptionScope opts(it.plane_sweep, it.sweep_rank);
+            OptionScope opts(it.plane_sweep, it.sweep_rank, it.sweep_chunks);
             mpmc_noise nz = it.noise;
             nz.sample_offset = it.counter;
             for (int rep = 0; rep < it.batches && st == MPMC_OK; ++rep) {
@@ -198,6 +206,9 @@ int mpmc_autotune(mpmc_handle h, const mpmc_lattice *lat, const mpmc_level *leve
                   mpmc_tune_choice *best, double *best_seconds, int32_t *cached, mpmc_tune_result *results,
                   int32_t max_results, int32_t *n_results, void *stream) {
     if (!h || !lat || !level || !noise || !best || nrhs < 1 || reps < 1 || keep_within < 0.0) return MPMC_EINVAL;
+    if (best->plane_sweep < 0 || best->plane_sweep > 2 || best->sweep_rank < 0 || best->sweep_rank > 63 ||
+        best->sweep_chunks < 0 || best->sweep_chunks > 1024)
+        return MPMC_EINVAL;
     if (!polynomial_level(level)) return MPMC_EUNSUPPORTED;
     const size_t need = mpmc_autotune_workspace_size(lat, level, nrhs);
     if (need == 0) return MPMC_EINVAL;
@@ -229,21 +240,37 @@ int mpmc_autotune(mpmc_handle h, const mpmc_lattice *lat, const mpmc_level *leve
     nz.sample_offset = nullptr;
     // candidates
     std::vector<mpmc_tune_choice> cand;
+    const int Lt = lat->dims[3];
     for (int rb = 1; rb <= 32 && rb <= nrhs; rb *= 2) {
         if (nrhs % rb) continue;
-        cand.push_back(mpmc_tune_choice{rb, 0, 0});
+        cand.push_back(mpmc_tune_choice{rb, 0, 0, 0});
         if (rb < 8) continue;
         for (int r = 0; r < 3; ++r) {
-            OptionScope o(1, r);
-            const SweepPlan p = sweep_plan(*lat, mpmc_shape{nrhs, rb});
-            if (!p.ok || r >= p.nranked) break;
-            cand.push_back(mpmc_tune_choice{rb, 1, r});
+            int k0 = 1;
+            {
+                OptionScope o(1, r, 0);
+                const SweepPlan p = sweep_plan(*lat, mpmc_shape{nrhs, rb});
+                if (!p.ok || r >= p.nranked) break;
+                k0 = p.nch;
+            }
+            cand.push_back(mpmc_tune_choice{rb, 1, r, 0});
+            // the divisors of Lt next to the plan's t-chunk count (chunks of at least 2 planes)
+            int lower = 0, upper = 0;
+            for (int k = 1; k < k0; ++k)
+                if (Lt % k == 0) lower = k;
+            for (int k = k0 + 1; k <= Lt / 2 && !upper; ++k)
+                if (Lt % k == 0) upper = k;
+            for (int k : {lower, upper}) {
+                if (k < 1) continue;
+                OptionScope o(1, r, k);
+                const SweepPlan p = sweep_plan(*lat, mpmc_shape{nrhs, rb});
+                if (p.ok && p.nch == k) cand.push_back(mpmc_tune_choice{rb, 1, r, k});
+            }
         }
     }
     bool have_current = false;
     for (const auto &c : cand)
-        if (c.rb == best->rb && c.plane_sweep == best->plane_sweep && c.sweep_rank == best->sweep_rank)
-            have_current = true;
+        if (same_choice(c, *best)) have_current = true;
     if (!have_current && best->rb >= 1 && nrhs % best->rb == 0 && best->rb <= 256 && (best->rb & (best->rb - 1)) == 0)
         cand.push_back(*best);
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -251,7 +278,7 @@ int mpmc_autotune(mpmc_handle h, const mpmc_lattice *lat, const mpmc_level *leve
     std::vector<double> secs(cand.size(), 0.0);
     int st = MPMC_OK;
     for (size_t c = 0; c < cand.size() && st == MPMC_OK; ++c) {
-        OptionScope opts(cand[c].plane_sweep, cand[c].sweep_rank);
+        OptionScope opts(cand[c].plane_sweep, cand[c].sweep_rank, cand[c].sweep_chunks);
         const mpmc_shape sh{nrhs, cand[c].rb};
         if (hipMemsetAsync(acc, 0, 8 * sizeof(double), (hipStream_t)stream) != hipSuccess) st = MPMC_EHIP;
         if (st == MPMC_OK)
@@ -271,8 +298,7 @@ int mpmc_autotune(mpmc_handle h, const mpmc_lattice *lat, const mpmc_level *leve
     size_t ib = 0, icur = cand.size();
     for (size_t c = 0; c < cand.size(); ++c) {
         if (secs[c] < secs[ib]) ib = c;
-        if (cand[c].rb == best->rb && cand[c].plane_sweep == best->plane_sweep && cand[c].sweep_rank == best->sweep_rank)
-            icur = c;
+        if (same_choice(cand[c], *best)) icur = c;
     }
     // keep the current shape unless another is faster by more than keep_within
     if (icur < cand.size() && secs[icur] <= secs[ib] * (1.0 + keep_within)) ib = icur;

@@ -66,6 +66,7 @@ class LevelState:
     batch: int = 0                          # vectors per batch (device buffers); samples per step / batch draws
     sweep: bool = True                      # allow the t-sweep kernel for this level
     sweep_rank: int = 0                     # block choice of a blocked t-sweep (MPMC_OPT_SWEEP_RANK)
+    sweep_chunks: int = 0                   # t-chunks of the sweep (MPMC_OPT_SWEEP_CHUNKS; 0: the plan's)
 
 
 @dataclass
@@ -98,6 +99,7 @@ class LatticeRun:
         lv = self.levels[level]
         L.set_option(L.OPT_PLANE_SWEEP, L.SWEEP_AUTO if lv.sweep else L.SWEEP_OFF)
         L.set_option(L.OPT_SWEEP_RANK, int(lv.sweep_rank))
+        L.set_option(L.OPT_SWEEP_CHUNKS, int(lv.sweep_chunks))
         L.mlmc_level_estimate(self.dl, lv.device, nsamples, self.level_rb(level), nz, lv.samples[:nsamples],
                               lv.acc, lv.ws)
 
@@ -137,17 +139,17 @@ class LatticeRun:
             lv.acc.zero_()
             lv.drawn = 0
 
-    def set_level_shape(self, level: int, rb: int, sweep: bool, rank: int = 0):
-        """Choose the RHS block width, kernel family and blocked-sweep block
-        rank of one level (the autotuner's knobs); resizes the level's
-        workspace."""
+    def set_level_shape(self, level: int, rb: int, sweep: bool, rank: int = 0, chunks: int = 0):
+        """Choose the RHS block width, kernel family, blocked-sweep block rank
+        and t-chunk count (0: the plan's) of one level (the autotuner's
+        knobs); resizes the level's workspace."""
         lv = self.levels[level]
         if lv.solver is not None:
             raise ValueError("the block width of a solve level is fixed by its solver")
         N = lv.batch
         if N % rb:
             raise ValueError(f"rb={rb} does not divide {N}")
-        lv.rb, lv.sweep, lv.sweep_rank = int(rb), bool(sweep), int(rank)
+        lv.rb, lv.sweep, lv.sweep_rank, lv.sweep_chunks = int(rb), bool(sweep), int(rank), int(chunks)
         lv.ws = L.workspace(L.level_workspace_size(self.dl, lv.device, N, rb))
 
     def estimates(self):
@@ -650,6 +652,7 @@ def _stop_step(run: LatticeRun, level: int, batch: int, state: torch.Tensor, fir
     item = L.BatchItem(run.dl, lv.device, batch, run.level_rb(level),
                        L.Noise(run.cfg.seed_noise, run.cfg.lattice_id, lv.index, 0), ctr, 1, lv.samples[:batch],
                        lv.acc, lv.ws, 0, L.SWEEP_AUTO if lv.sweep else L.SWEEP_OFF, int(lv.sweep_rank),
+                       int(lv.sweep_chunks),
                        state, first, every)
     L.batch_build(h, [item])
     return h, ctr

@@ -143,6 +143,42 @@ def test_autotune_offers_the_blocked_sweep(tmp_path):
     assert np.max(np.abs(got - ref)) <= 1e-6 * np.max(np.abs(ref))
 
 
+def test_autotune_offers_t_chunks(tmp_path):
+    """On 8^4 planes with 64 vectors the plan cuts the whole-plane t-sweep
+    into 4 t-chunks (64 workgroups would leave three CUs in four idle);
+    mpmc_autotune also times the neighbouring chunk count, 2.  A level forced
+    to 2 chunks gives the samples of the plan's 4 up to the order of FP64
+    sums, and the same level recorded as a HIP graph (the chunk count carried
+    by the batch item) replays the eager samples bit for bit."""
+    from paper_2306_09559_amd import driver
+    from paper_2306_09559_amd.batch import GraphStep, autotune
+    from synth.configs import Level
+    L = lib()
+    cfg = dataclasses.replace(_small_cfgs()[0], name="C1t", dims=(8, 8, 8, 8), kappa=0.14,
+                              levels=(Level(12, None, 64),), seed_links=131, lattice_id=13)
+    run = driver.build(cfg, prec=L.F64, rb=16)
+    L.set_option(L.OPT_PLANE_SWEEP, 1)
+    L.set_option(L.OPT_SWEEP_CHUNKS, 0)
+    assert L.sweep_plan(run.dl, 64, 16)["chunks"] == 4
+    L.set_option(L.OPT_PLANE_SWEEP, 2)
+    res = autotune(run, reps=2, use_cache=False, cache_path=str(tmp_path / "t.json"))
+    t = res.timings[0]
+    print(t)
+    assert {"rb16", "rb16-sweep", "rb16-sweep-t2"} <= set(t)
+    samples = {}
+    for chunks in (0, 2):
+        run.set_level_shape(0, 16, True, 0, chunks)
+        eager, _ = _eager_steps(run, 1)
+        samples[chunks] = eager[0][0]
+        gs = GraphStep([run])
+        gs.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(run.levels[0].samples[:64].cpu().numpy(), samples[chunks]), chunks
+    L.set_option(L.OPT_SWEEP_CHUNKS, 0)    # the eager steps left the level's option set
+    a, b = samples[0], samples[2]
+    assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(a))
+
+
 def test_batch_entry_points_validate(tmp_path):
     """mpmc_batch_build rejects a solve level, a missing counter and a short
     workspace before recording anything; mpmc_batch_launch needs a built step."""
