@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--hop-orders", default="0,1",
                     help="work orders (MPMC_OPT_HOP_SLAB values) the hop probe times, comma-separated")
     ap.add_argument("--c4-only", action="store_true", help="run only the 24^3x48 workload (profiling runs)")
+    ap.add_argument("--c5-only", action="store_true",
+                    help="run only the four independent lattices in one graph (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -579,6 +581,11 @@ def main():
         import torch
         torch.cuda.set_device(0)
         print(json.dumps({"c4": c4_step(max(1, args.steps))}), flush=True)
+        return
+    if args.c5_only:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps({"batched_lattices": batched_c5(max(1, args.steps))}), flush=True)
         return
     if args.probe:
         import torch
