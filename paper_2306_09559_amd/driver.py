@@ -97,11 +97,18 @@ class LatticeRun:
         descriptor (used by graph capture, where the sample index comes from a
         device counter)."""
         lv = self.levels[level]
+        # the level's kernel selection for this call only (the options are
+        # process-wide; mpmc_batch_build scopes them per item the same way)
         L.set_option(L.OPT_PLANE_SWEEP, L.SWEEP_AUTO if lv.sweep else L.SWEEP_OFF)
         L.set_option(L.OPT_SWEEP_RANK, int(lv.sweep_rank))
         L.set_option(L.OPT_SWEEP_CHUNKS, int(lv.sweep_chunks))
-        L.mlmc_level_estimate(self.dl, lv.device, nsamples, self.level_rb(level), nz, lv.samples[:nsamples],
-                              lv.acc, lv.ws)
+        try:
+            L.mlmc_level_estimate(self.dl, lv.device, nsamples, self.level_rb(level), nz, lv.samples[:nsamples],
+                                  lv.acc, lv.ws)
+        finally:
+            L.set_option(L.OPT_PLANE_SWEEP, L.SWEEP_AUTO)
+            L.set_option(L.OPT_SWEEP_RANK, 0)
+            L.set_option(L.OPT_SWEEP_CHUNKS, 0)
 
     def draw(self, level: int, nsamples: int):
         """Enqueue nsamples more samples of one level (one batch)."""

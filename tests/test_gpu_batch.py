@@ -174,7 +174,7 @@ def test_autotune_offers_t_chunks(tmp_path):
         gs.replay()
         torch.cuda.synchronize()
         assert np.array_equal(run.levels[0].samples[:64].cpu().numpy(), samples[chunks]), chunks
-    L.set_option(L.OPT_SWEEP_CHUNKS, 0)    # the eager steps left the level's option set
+    assert L.sweep_plan(run.dl, 64, 16)["chunks"] == 4     # eager steps leave the options as they found them
     a, b = samples[0], samples[2]
     assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(a))
 
