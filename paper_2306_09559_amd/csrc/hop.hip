@@ -210,12 +210,61 @@ __device__ __forceinline__ void hop_one(const HopArgs<T> &a, const Blk<T> &in, i
     reconstruct<T, MU, FWD>(h.h, acc);
 }
 
-// acc = D psi at site s: the 8 hops run as a rolled loop so that only one
-// neighbour's loads and products are live at a time (bounded registers,
-// occupancy >= 3 waves per SIMD in FP64); acc is carried in registers.
+// both hops of direction MU, the two neighbours' loads issued before either
+// is used (FP64, see hop_all)
+template <typename T, int MU>
+__device__ __forceinline__ void hop_pair(const HopArgs<T> &a, const Blk<T> &in, int jr, bool z4, uint64_t S, int s,
+                                         const int (&x)[4], cplx_t<T> (&acc)[12]) {
+    const bool wf = x[MU] == a.g.L[MU] - 1, wb = x[MU] == 0;
+    const int st = a.g.st[MU];
+    const int nf = wf ? s - (a.g.L[MU] - 1) * st : s + st;
+    const int nb = wb ? s + (a.g.L[MU] - 1) * st : s - st;
+    const T sf = (MU == 3 && wf && a.g.apbc) ? T(-1) : T(1);
+    const T sb = (MU == 3 && wb && a.g.apbc) ? T(-1) : T(1);
+    cplx_t<T> pf[12], pb[12];
+    load_site<T>(in, a.rb, jr, z4, S, nf, sf, pf);
+    load_site<T>(in, a.rb, jr, z4, S, nb, sb, pb);
+    {
+        Half<T> h;
+        project<T, MU, true>(pf, h.h);
+        su3_mul<T, true>(a, MU, s, h.h);
+        reconstruct<T, MU, true>(h.h, acc);
+    }
+    {
+        Half<T> h;
+        project<T, MU, false>(pb, h.h);
+        su3_mul<T, false>(a, MU, nb, h.h);
+        reconstruct<T, MU, false>(h.h, acc);
+    }
+}
+
+// acc = D psi at site s: the hops run as a rolled loop so that only one
+// neighbour's (FP32) or one direction's (FP64) loads and products are live at
+// a time (bounded registers); acc is carried in registers.  FP64 takes the
+// two hops of a direction per iteration, both neighbours requested together:
+// 159 -> 243 VGPRs (3 -> 2 waves per SIMD) and faster all the same (24^3x48 x
+// 1 vector 176 -> 159 us per launch, 8^4 x 64 even); FP32 kept one hop per
+// iteration (103 -> 144 VGPRs with pairs, 4-8% slower).
 template <typename T>
 __device__ __forceinline__ void hop_all(const HopArgs<T> &a, const Blk<T> &in, int jr, bool z4, uint64_t S, int s,
                                         const int (&x)[4], cplx_t<T> (&acc)[12]) {
+    if constexpr (sizeof(T) == 8) {
+#pragma nounroll
+        for (int d = 0; d < 4; ++d) {
+            // opaque copies of the loop-invariant inputs (see below)
+            int sl = s, xl[4] = {x[0], x[1], x[2], x[3]};
+            asm volatile("" : "+v"(sl), "+v"(xl[0]), "+v"(xl[1]), "+v"(xl[2]), "+v"(xl[3]));
+            Blk<T> il = in;
+            il.base = opaque_ptr(il.base);
+            switch (d) {
+            case 0: hop_pair<T, 0>(a, il, jr, z4, S, sl, xl, acc); break;
+            case 1: hop_pair<T, 1>(a, il, jr, z4, S, sl, xl, acc); break;
+            case 2: hop_pair<T, 2>(a, il, jr, z4, S, sl, xl, acc); break;
+            default: hop_pair<T, 3>(a, il, jr, z4, S, sl, xl, acc); break;
+            }
+        }
+        return;
+    }
 #pragma nounroll
     for (int d = 0; d < 8; ++d) {
         // Opaque copies of the loop-invariant inputs: without them the
