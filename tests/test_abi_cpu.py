@@ -173,6 +173,22 @@ def test_batch_and_tuner_reject_on_host(L):
     assert L._lib.mpmc_batch_build(None, items, 1) == L.EINVAL
     assert L._lib.mpmc_autotune(None, None, None, 1, None, 1, 0.0, None, 0, None, None, None, None, 0, None,
                                 None) == L.EINVAL
+    # a current shape outside the options' ranges (t-chunks above 1024, a kernel selection above 2)
+    fake = ctypes.c_void_p(256)                      # never dereferenced: the argument checks come first
+    lat = L.mpmc_lattice((ctypes.c_int32 * 4)(8, 8, 8, 8), 0, L.F64, 0.13, fake, 3)
+    lv = L.mpmc_level(L.OP_POLY, L.OP_NONE, L.mpmc_poly(3, 0, fake, None), L.mpmc_poly(0, 0, None, None), None,
+                      0, None, None)
+    nz = L.mpmc_noise(1, 1, 1, 0, None, None)
+    for bad in (L.mpmc_tune_choice(16, 2, 0, 1025), L.mpmc_tune_choice(16, 3, 0, 0), L.mpmc_tune_choice(16, 1, 64, 0)):
+        assert L._lib.mpmc_autotune(h.ptr, ctypes.byref(lat), ctypes.byref(lv), 64, ctypes.byref(nz), 1, 0.0,
+                                    fake, 1 << 30, ctypes.byref(bad), None, None, None, 0, None, None) == L.EINVAL
+    # a batch item with t-chunks out of range
+    item = L.mpmc_batch_item()
+    item.lat, item.level, item.counter, item.batches = ctypes.pointer(lat), ctypes.pointer(lv), fake, 1
+    item.plane_sweep, item.sweep_chunks = 2, 2000
+    assert L._lib.mpmc_batch_build(h.ptr, ctypes.byref(item), 1) == L.EINVAL
+    item.sweep_chunks = 0                            # in range: the next check is the (missing) workspace
+    assert L._lib.mpmc_batch_build(h.ptr, ctypes.byref(item), 1) == L.EWORKSPACE
     h.close()
 
 
