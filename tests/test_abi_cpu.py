@@ -185,6 +185,7 @@ def test_batch_and_tuner_reject_on_host(L):
     # a batch item with t-chunks out of range
     item = L.mpmc_batch_item()
     item.lat, item.level, item.counter, item.batches = ctypes.pointer(lat), ctypes.pointer(lv), fake, 1
+    item.shape = L.mpmc_shape(64, 16)
     item.plane_sweep, item.sweep_chunks = 2, 2000
     assert L._lib.mpmc_batch_build(h.ptr, ctypes.byref(item), 1) == L.EINVAL
     item.sweep_chunks = 0                            # in range: the next check is the (missing) workspace
