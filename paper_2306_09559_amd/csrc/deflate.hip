@@ -129,6 +129,60 @@ __global__ void __launch_bounds__(kWaves * 64) k_coeff(CoeffArgs<T> a) {
     }
 }
 
+// One vector (the Gram-Schmidt steps of the set-up's Arnoldi runs): the same
+// partial sums as k_coeff, on the vector units.  The MFMA tiles would pad the
+// vector to 16 columns and do 16 times the products, which bounds that kernel
+// on the matrix cores (FP64 at 24^3x48, 128 basis vectors: ~1.7 ms of MFMA
+// per call against ~3 ms to read the basis); here every lane (eigenvector
+// row m, site kk of four) forms conj(v) b for its sites in FP64, and the
+// partials are summed over the sites of a wave and the waves in a fixed
+// order.  Only column 0 of the partial rows is written (ntr = 1).
+template <typename T>
+__global__ void __launch_bounds__(kWaves * 64) k_coeff_one(CoeffArgs<T> a) {
+    __shared__ double2 red[kWaves][2][64];
+    const int wave = (int)threadIdx.x / 64, l = (int)threadIdx.x % 64;
+    const int kk = l / 16, m = l % 16;
+    const int i = (int)blockIdx.x * 16 + m;
+    const int s_begin = (int)blockIdx.y * a.sites_per_split;
+    const int s_end = min(s_begin + a.sites_per_split, a.Vol);
+    const uint64_t S = a.b == nullptr ? sample_state(a.key, sample_base(a.first, a.off)) : 0ull;
+    double ur = 0.0, ui = 0.0, dr = 0.0, di = 0.0;
+    for (int s0 = s_begin + wave * 4; s0 < s_end; s0 += kWaves * 4) {
+        const int s = s0 + kk;
+        if (s >= s_end) continue;
+        const uint32_t codes = a.b == nullptr ? z4_site_codes(S, (unsigned)s) : 0u;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const cplx_t<T> v = a.V[((size_t)c * a.Vol + (size_t)s) * (size_t)a.kpad + (size_t)i];
+            const cplx_t<T> bb = a.b == nullptr ? z4_value<T>((codes >> (2 * c)) & 3u)
+                                                : a.b[((size_t)c * a.Vol + (size_t)s) * (size_t)a.rb];
+            const double vr = (double)v.x, vi = (double)v.y, br = (double)bb.x, bi = (double)bb.y;
+            // conj(v) b = (vr br + vi bi) + i (vr bi - vi br)
+            if (c < 6) {
+                ur += vr * br + vi * bi;
+                ui += vr * bi - vi * br;
+            } else {
+                dr += vr * br + vi * bi;
+                di += vr * bi - vi * br;
+            }
+        }
+    }
+    red[wave][0][l] = make_double2(ur, ui);
+    red[wave][1][l] = make_double2(dr, di);
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        const int h = (int)threadIdx.x / 16, mm = (int)threadIdx.x % 16;
+        double2 z = make_double2(0.0, 0.0);
+        for (int w = 0; w < kWaves; ++w)
+            for (int q = 0; q < 4; ++q) {
+                z.x += red[w][h][q * 16 + mm].x;
+                z.y += red[w][h][q * 16 + mm].y;
+            }
+        const int row = (int)blockIdx.x * 16 + mm;
+        a.part[(((size_t)blockIdx.y * 2 + h) * (size_t)a.kpad + (size_t)row) * 16] = z;
+    }
+}
+
 // zeta = up + dn, omega_i = conj(scale_i) (up - dn)[pair_i]; fixed split order
 // one 64-lane workgroup per (eigenvector, vector): the four split sums in a fixed order (sum_fixed)
 __global__ void __launch_bounds__(kSumLanes) k_coeff_finish(const double2 *part, int nsplit, int kpad, int ldr, int k,
@@ -284,7 +338,11 @@ int coeff_t(const mpmc_lattice &lat, const mpmc_defl &df, mpmc_shape sh, const v
     a.first = noise ? noise->first_sample : 0ull;
     a.off = noise ? noise->sample_offset : nullptr;
     a.part = (double2 *)ws;
-    hipLaunchKernelGGL(k_coeff<T>, dim3(p.nti_run * p.ntr, p.nsplit), dim3(kWaves * 64), 0, (hipStream_t)stream, a);
+    if (sh.nrhs == 1)
+        hipLaunchKernelGGL(k_coeff_one<T>, dim3(p.nti_run, p.nsplit), dim3(kWaves * 64), 0, (hipStream_t)stream, a);
+    else
+        hipLaunchKernelGGL(k_coeff<T>, dim3(p.nti_run * p.ntr, p.nsplit), dim3(kWaves * 64), 0, (hipStream_t)stream,
+                           a);
     if (hipGetLastError() != hipSuccess) return MPMC_EHIP;
     const int tot = df.k * sh.nrhs;
     hipLaunchKernelGGL(k_coeff_finish, dim3((unsigned)tot), dim3(kSumLanes), 0, (hipStream_t)stream,

@@ -238,7 +238,8 @@ def _device_defl(dims, Z, pair, U, H, prec=0, kpad=16):
     return device_defl(dims, Z, pair, U, H, prec, kpad)
 
 
-@pytest.mark.parametrize("nrhs,rb,z4", [(8, 4, True), (5, 1, False), (40, 8, True)])
+@pytest.mark.parametrize("nrhs,rb,z4", [(8, 4, True), (5, 1, False), (40, 8, True),
+                                        (1, 1, True), (1, 1, False)])     # one vector: the vector-unit kernel
 def test_deflate_coeff(small_defl, nrhs, rb, z4):
     L = lib()
     dims, dl, ol, lam, Z, pair, U, H = small_defl
@@ -262,8 +263,10 @@ def test_deflate_coeff(small_defl, nrhs, rb, z4):
     assert np.max(np.abs(omega.cpu().numpy() - ro) / (nb * np.linalg.norm(U, axis=1)[:, None])) < 1e-12
 
 
-def test_deflate_coeff_large_random():
-    """Tall-skinny V^H b over 4^4 x 12 rows with k = 20 padded to 32, ragged N."""
+@pytest.mark.parametrize("nrhs,rb", [(100, 4), (1, 1)])
+def test_deflate_coeff_large_random(nrhs, rb):
+    """Tall-skinny V^H b over 4^4 x 12 rows with k = 20 padded to 32, ragged N;
+    one vector (the Gram-Schmidt case) on the vector-unit kernel."""
     L = lib()
     dims = (4, 4, 4, 4)
     dl, ol = device_lattice(dims, 0.15, 0.5, 5, True)
@@ -273,7 +276,6 @@ def test_deflate_coeff_large_random():
     pair = np.arange(k)
     U = np.stack([ol.gamma5(Z[i]) for i in range(k)]) * 0.5
     D = _device_defl(dims, Z, pair, U, None, kpad=32)
-    nrhs, rb = 100, 4
     nz = L.Noise(8, 1, 2, 100)
     B = oracle.z4(8, 1, 2, 100, nrhs, dl.V)
     zeta = torch.empty((k, nrhs), dtype=torch.complex128, device="cuda")
