@@ -69,6 +69,32 @@ def test_graph_replays_match_eager(prec):
     assert gs.samples_drawn()[(0, 0)] == steps * ca.levels[0].samples
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_graph_replays_match_eager_on_the_8x4_workload(prec):
+    """The full 8^4 three-level workload (256 samples per level and step, the
+    two polynomial-difference levels deflated with 20 eigenvectors: the MFMA
+    GEMMs inside the recording) as one graph with a branch per level: every
+    replay gives
+    every level's samples of the eager step bit for bit, and the accumulators
+    match after two steps."""
+    from paper_2306_09559_amd import driver
+    from paper_2306_09559_amd.batch import GraphStep
+    from synth.configs import C2
+    run = driver.build(C2, prec=prec, rb=16)
+    assert any(lv.deflated for lv in C2.levels)
+    steps = 2
+    eager, accs = _eager_steps(run, steps)
+    gs = GraphStep([run], level_branches=True)
+    for k in range(steps):
+        gs.replay()
+        torch.cuda.synchronize()
+        for li, lv in enumerate(run.levels):
+            got = lv.samples[: C2.levels[li].samples].cpu().numpy()
+            assert np.array_equal(got, eager[k][li]), (li, k)
+    for li, lv in enumerate(run.levels):
+        assert np.array_equal(lv.acc.cpu().numpy(), accs[li]), li
+
+
 def test_graph_serial_equals_parallel():
     """One branch in order, one per lattice and one per level give the same
     accumulators bit for bit."""
