@@ -320,24 +320,26 @@ def pp_arnoldi_deflation(dl: L.DeviceLattice, pin: L.DevicePoly, start: np.ndarr
     one = (L.empty_field(V, 1, 1, F64), L.empty_field(V, 1, 1, F64))   # the single-candidate residuals
 
     def resid(coef: np.ndarray, src_perm: np.ndarray) -> np.ndarray:
-        """|| A z_p - coef_i z_p || for p = src_perm[i] (a batch of the
-        candidates' width, or single-vector fields for one candidate)."""
+        """|| A z_p - coef_i z_p || for p = src_perm[i]: for several
+        candidates in the batch's own column order (one coefficient per
+        column, no vector moved), for one candidate on single-vector fields."""
         if len(src_perm) == 1:
             P, R = one
+            L.field_copy_vector(dims, F64, Zb, int(src_perm[0]), P, 0)
+            L.field_copy_vector(dims, F64, AZ, int(src_perm[0]), R, 0)
+            cpad = np.array([-complex(coef[0])])
+            sel = np.array([0])
             w = 1
         else:
-            R = torch.empty_like(Zb)
-            P = torch.empty_like(Zb)
+            P, R = Zb, AZ.clone()
             w = kp
-        for i, p in enumerate(src_perm):
-            L.field_copy_vector(dims, F64, Zb, int(p), P, i)
-            L.field_copy_vector(dims, F64, AZ, int(p), R, i)
-        cpad = np.zeros(w, dtype=np.complex128)
-        cpad[: len(coef)] = -np.asarray(coef)
+            cpad = np.zeros(w, dtype=np.complex128)
+            cpad[np.asarray(src_perm)] = -np.asarray(coef)
+            sel = np.asarray(src_perm)
         L.field_axpby(dims, F64, _c(cpad), P, _c(np.ones(w)), R)
         out = torch.empty(w, dtype=torch.complex128, device="cuda")
         L.field_dot(dims, F64, R, R, out, wsd)
-        return np.sqrt(np.maximum(out.cpu().numpy().real[: len(coef)], 0.0))
+        return np.sqrt(np.maximum(out.cpu().numpy().real[sel], 0.0))
 
     lam_s = lam_all[order]
     rr_all = resid(lam_s, order)
