@@ -1,6 +1,8 @@
 // Newton step of a GMRES polynomial (Sec. 3.1) as a t-sweep: one workgroup
 // owns one vector and one whole xyz-plane of the lattice (one thread per
-// (x, y, z)), and marches through t = 0 .. Lt-1.
+// (x, y, z)), and marches through t = 0 .. Lt-1 (or, for larger planes, an
+// xyz-block of it with a halo; for small batches, one t-chunk of the planes,
+// started from the plane before it).
 //
 //   * The current plane is staged in LDS; the +-x, +-y, +-z neighbours are
 //     read from there (periodic wrap inside the plane).
