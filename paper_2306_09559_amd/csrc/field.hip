@@ -393,7 +393,9 @@ __global__ void __launch_bounds__(256) k_copy_bytes(const double2 *__restrict__ 
 int field_copy_bytes_impl(const void *src, void *dst, size_t bytes, void *stream) {
     const size_t n = bytes / 16;
     int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;                       // the grid size only: four workgroups per CU of an MI355X
     const size_t want = (n + 255) / 256, cap = (size_t)4 * (size_t)(cus > 0 ? cus : 256);
     const unsigned g = (unsigned)(want < cap ? want : cap);
     hipLaunchKernelGGL(k_copy_bytes, dim3(g), dim3(256), 0, (hipStream_t)stream, (const double2 *)src, (double2 *)dst,
