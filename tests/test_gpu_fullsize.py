@@ -378,6 +378,53 @@ def test_c4_planes_blocked_sweep_sampled_vs_oracle():
             assert err <= bound
 
 
+@pytest.mark.parametrize("i,plan_want", [(0, (False, 4)), (1, (True, 3)), (2, (True, 2)), (3, None)])
+def test_c5_lattices_sampled_vs_oracle(i, plan_want):
+    """The four independent lattices of the mixed batch at their sizes and
+    batch widths (8^4 x 64, 12^4 x 32, 16^4 x 16, 12^3x24 x 8 vectors, FP32,
+    block width 8) on the kernel the default plan picks: the whole-plane
+    t-sweep in 4 t-chunks, blocked sweeps in 3 and 2 t-chunks, and the
+    streaming kernel for the 12^3x24 batch.  A degree-12 GMRES polynomial of
+    each lattice's own operator; samples 0 and N-1 against the oracle."""
+    L = lib()
+    from synth.configs import C5
+    cfg = C5[i]
+    dims, V, N, rb, prec = cfg.dims, cfg.volume, cfg.levels[0].samples, 8, 1
+    U = synth.gauge_links(dims, cfg.eps, cfg.seed_links)
+    ol = oracle.Lattice(dims, cfg.kappa, U, cfg.antiperiodic_t)
+    d = 12
+    t = krylov.gmres_polys(ol.apply, synth.gaussian_start(ol.n, cfg.seed_start), [d]).inv_roots[d]
+    gauge = torch.empty(36 * V, dtype=L.complex_dtype(prec), device="cuda")
+    L.pack_gauge(dims, prec, torch.from_numpy(U).cuda(), gauge)
+    del U
+    dl = L.DeviceLattice(tuple(dims), cfg.kappa, cfg.antiperiodic_t, prec, gauge)
+    L.set_option(L.OPT_PLANE_SWEEP, 2)
+    L.set_option(L.OPT_SWEEP_CHUNKS, 0)
+    plan = L.sweep_plan(dl, N, rb)
+    print(dims, N, plan)
+    if plan_want is None:
+        assert not plan["ok"]
+    else:
+        assert plan["ok"] and (plan["halo"], plan["chunks"]) == plan_want, plan
+    poly = L.DevicePoly(dev_c128(t))
+    ws = L.workspace(L.poly_workspace_size(dl, poly, N, rb))
+    nz = L.Noise(cfg.seed_noise, cfg.lattice_id, 0, 0)
+    bhy = torch.empty(N, dtype=torch.complex128, device="cuda")
+    L.poly_apply(dl, poly, N, rb, None, nz, None, bhy, ws)
+    torch.cuda.synchronize()
+    got = bhy.cpu().numpy()
+    L.set_option(L.OPT_PLANE_SWEEP, 1)
+    del ws, gauge
+    for r in (0, N - 1):
+        b = oracle.z4(cfg.seed_noise, cfg.lattice_id, 0, r, 1, V)[0]
+        _, want = ol.poly_apply(t, b)
+        kN = _kappa_N(ol, t, b)
+        bound = 8 * d * kN * U32
+        err = abs(got[r] - want[0]) / abs(want[0])
+        print(f"r {r}: rel err {err:.2e}, kappa_N {kN:.3g}, bound {bound:.2e}")
+        assert err <= bound
+
+
 def test_c4_size_deflation_coefficients_exact():
     L = lib()
     dims = (24, 24, 24, 48)
