@@ -1,13 +1,16 @@
-"""Planted mistakes in the oracle (on the CPU, in a copy of its C source):
-each one must make a pin fail.  The pins are what the oracle is trusted on,
-so a plausible mistake anywhere in its arithmetic -- a dropped term, a wrong
-sign, index or constant -- has to be caught by one of them.
+"""Planted mistakes in the oracle (on the CPU, in a copy of it): each one
+must make a pin fail.  The pins are what the oracle is trusted on, so a
+plausible mistake anywhere in its arithmetic -- a dropped term, a wrong sign,
+index, conjugate or constant -- has to be caught by one of them.
 
-Each case copies oracle/ref.c, applies one textual change, compiles it the
-way oracle.build does, and runs the named pin file in a child process whose
-oracle module loads the mutated library.  An unchanged copy run the same way
-passes the same files (the control)."""
+A C case copies oracle/ref.c, applies one textual change, compiles it the way
+oracle.build does, and runs the named pin file in a child process whose oracle
+module loads the mutated library.  A Python case copies the oracle package,
+changes one of its modules and runs the pin file in a child process that
+imports the copy.  Unchanged copies run the same way pass the same files (the
+controls)."""
 import os
+import shutil
 import subprocess
 import sys
 
@@ -44,9 +47,49 @@ MUTATIONS = [
      "tests/test_oracle_operator.py"),
 ]
 
-# the child process: point the oracle at the given source and library, then run pytest
+# (label, module, original text, mutated text, pin file that must fail)
+PY_MUTATIONS = [
+    ("sample variance over n instead of n - 1", "estimator.py",
+     "np.sum(np.abs(s - mean) ** 2) / (n - 1)", "np.sum(np.abs(s - mean) ** 2) / n",
+     "tests/test_oracle_estimator.py"),
+    ("level 2 checked from 2 samples instead of 3", "estimator.py",
+     "return list(range(3, nmax + 1, 3))", "return list(range(2, nmax + 1, 3))",
+     "tests/test_oracle_estimator.py"),
+    ("first level's share of eps over sqrt(2) instead of sqrt(3)", "estimator.py",
+     "t1 = eps / np.sqrt(3.0)", "t1 = eps / np.sqrt(2.0)",
+     "tests/test_oracle_estimator.py"),
+    ("deflation term added to the sample", "estimator.py",
+     's = s - np.einsum("i,ir,ir->r", np.asarray(c), np.conj(zeta), omega)',
+     's = s + np.einsum("i,ir,ir->r", np.asarray(c), np.conj(zeta), omega)',
+     "tests/test_oracle_deflation.py"),
+    ("left vectors scaled by d instead of conj(d)", "deflation.py",
+     "return U / np.conj(d)[:, None]", "return U / d[:, None]",
+     "tests/test_oracle_deflation.py"),
+    ("zeta = V^T b instead of V^H b", "deflation.py",
+     "return Z.conj() @ B.T, U.conj() @ B.T", "return Z @ B.T, U.conj() @ B.T",
+     "tests/test_oracle_deflation.py"),
+    ("harmonic Ritz with H^-T e_m instead of H^-H e_m", "krylov.py",
+     "f = np.linalg.solve(Hm.conj().T, em)", "f = np.linalg.solve(Hm.T, em)",
+     "tests/test_oracle_poly.py"),
+    ("harmonic Ritz with |h| instead of |h|^2", "krylov.py",
+     "np.linalg.eigvals(Hm + (abs(h) ** 2) * np.outer(f, em))", "np.linalg.eigvals(Hm + abs(h) * np.outer(f, em))",
+     "tests/test_oracle_poly.py"),
+    ("Leja order by summed distances instead of their product", "krylov.py",
+     "score[i] += np.log(abs(th[i] - last))", "score[i] += abs(th[i] - last)",
+     "tests/test_oracle_poly.py"),
+    ("selection's left residual without g5", "krylov.py",
+     "        u = gamma5(Z[src])\n        u = u / np.linalg.norm(u)", "        u = Z[src]\n        u = u / np.linalg.norm(u)",
+     "tests/test_oracle_selection.py"),
+]
+
+# the child processes: point the oracle at the given source and library, or
+# import the oracle package from the given directory; then run pytest
 RUNNER = ("import sys, oracle; oracle._SRC, oracle._LIB = sys.argv[1], sys.argv[2]; "
           "import pytest; sys.exit(pytest.main(sys.argv[3:]))")
+PY_RUNNER = ("import sys; sys.path.insert(0, sys.argv[1]); import oracle; "
+             "assert oracle.__file__.startswith(sys.argv[1]), oracle.__file__; "
+             "import pytest; sys.exit(pytest.main(sys.argv[2:]))")
+PIN_ARGS = ["-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu"]
 
 
 def _build(tmp_path, text):
@@ -59,8 +102,20 @@ def _build(tmp_path, text):
 
 
 def _run_pins(src, lib, files):
-    r = subprocess.run([sys.executable, "-c", RUNNER, str(src), str(lib), "-x", "-q", "-p", "no:cacheprovider",
-                        "-m", "not gpu", *files], cwd=ROOT, capture_output=True, text=True, timeout=600)
+    r = subprocess.run([sys.executable, "-c", RUNNER, str(src), str(lib), *PIN_ARGS, *files], cwd=ROOT,
+                       capture_output=True, text=True, timeout=600)
+    return r.returncode, r.stdout[-3000:] + r.stderr[-2000:]
+
+
+def _copy_package(tmp_path):
+    shutil.copytree(os.path.join(ROOT, "oracle"), tmp_path / "oracle",
+                    ignore=shutil.ignore_patterns("__pycache__", "*.so", "*.tmp*"))
+    return tmp_path / "oracle"
+
+
+def _run_pins_on_copy(tmp_path, files):
+    r = subprocess.run([sys.executable, "-c", PY_RUNNER, str(tmp_path), *PIN_ARGS, *files], cwd=ROOT,
+                       capture_output=True, text=True, timeout=600)
     return r.returncode, r.stdout[-3000:] + r.stderr[-2000:]
 
 
@@ -78,4 +133,21 @@ def test_planted_mistake_fails_a_pin(tmp_path, label, old, new, pins):
     src, lib = _build(tmp_path, text.replace(old, new))
     rc, out = _run_pins(src, lib, [pins])
     # 1: the tests ran and at least one failed (anything else is a harness error)
+    assert rc == 1, out
+
+
+def test_unchanged_package_copy_passes_the_pins(tmp_path):
+    _copy_package(tmp_path)
+    rc, out = _run_pins_on_copy(tmp_path, sorted({m[4] for m in PY_MUTATIONS}))
+    assert rc == 0, out
+
+
+@pytest.mark.parametrize("label,module,old,new,pins", PY_MUTATIONS, ids=[m[0] for m in PY_MUTATIONS])
+def test_planted_mistake_in_a_module_fails_a_pin(tmp_path, label, module, old, new, pins):
+    pkg = _copy_package(tmp_path)
+    path = pkg / module
+    text = path.read_text()
+    assert text.count(old) == 1, label
+    path.write_text(text.replace(old, new))
+    rc, out = _run_pins_on_copy(tmp_path, [pins])
     assert rc == 1, out
