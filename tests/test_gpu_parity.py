@@ -755,6 +755,61 @@ def test_sweep_t_chunks(dims, prec, nrhs, rb, chunks):
         assert np.max(np.abs(Y - Y0)) <= (1e-13 if prec == 0 else tol) * np.max(np.abs(Y0)), k
 
 
+@pytest.mark.parametrize("chunks", [2, 4])
+def test_t_chunks_in_probing_composite_and_identity(chunks):
+    """The t-chunked sweep (FP64, 4^4, chunks of 2 and 1 planes) on its three
+    other paths: probe vectors generated inside the kernel (the exact trace of
+    a degree-3 polynomial against the oracle's brute-force colouring), the
+    double polynomial's inner chains (scalar mode against the oracle's
+    composite polynomial), and steps without hops (kappa = 0, A = I: every
+    sample equals 12 V p(1))."""
+    L = lib()
+    from oracle import probing as oprobe
+    from paper_2306_09559_amd import probing
+    dims = (4, 4, 4, 4)
+    L.set_option(L.OPT_PLANE_SWEEP, 1)
+    L.set_option(L.OPT_SWEEP_CHUNKS, chunks)
+    try:
+        # probe vectors drawn in the kernel
+        dl, ol = device_lattice(dims, 0.14, 0.5, 21, True)
+        assert L.sweep_plan(dl, 64, 1)["chunks"] == chunks
+        deg = 3
+        t = krylov.gmres_polys(ol.apply, synth.gaussian_start(ol.n, 2), [deg]).inv_roots[deg]
+        res = probing.probe_trace(dl, L.DevicePoly(dev_c128(t)), probing.colouring(dims, deg), nrhs=64, rb=1,
+                                  in_kernel=True)
+        want = oprobe.probe_trace(ol, t, oprobe.distance_colouring(dims, deg))
+        assert abs(res.trace - want) <= 1e-12 * abs(want), (res.trace, want)
+        # the double polynomial's inner chains
+        dl, ol = device_lattice(dims, 0.14, 0.4, 35, True)
+        r0 = synth.gaussian_start(ol.n, 6)
+        t_in = krylov.gmres_polys(ol.apply, r0, [3]).inv_roots[3]
+        opB = krylov.pp_operator(ol.apply, t_in, lambda tt, v: ol.poly_apply(tt, v)[0])
+        t_out, _ = krylov.pp_gmres_roots(opB, r0, n_out=3)
+        nrhs = 16
+        assert L.sweep_plan(dl, nrhs, 1)["chunks"] == chunks
+        poly = L.DevicePoly(dev_c128(t_in), dev_c128(t_out))
+        ws = L.workspace(L.poly_workspace_size(dl, poly, nrhs, 4))
+        bhy = torch.empty(nrhs, dtype=torch.complex128, device="cuda")
+        L.poly_apply(dl, poly, nrhs, 4, None, L.Noise(13, 4, 2, 5), None, bhy, ws)
+        torch.cuda.synchronize()
+        B = oracle.z4(13, 4, 2, 5, nrhs, dl.V)
+        ref_y, _ = ol.composite_apply(t_in, t_out, B)
+        ref = np.einsum("rn,rn->r", B.conj(), ref_y)
+        assert np.max(np.abs(bhy.cpu().numpy() - ref) / np.abs(ref)) < 1e-12
+        # steps without hops
+        dl, _ = device_lattice(dims, 0.0, 0.4, 43, True)
+        tz = np.array([0.6, 0.5 + 0.1j, 0.4, 0.3j, 0.2])
+        p1 = complex(deflation.poly_eval(tz, 1.0))
+        poly = L.DevicePoly(dev_c128(tz))
+        ws = L.workspace(L.poly_workspace_size(dl, poly, nrhs, 4))
+        bhy = torch.empty(nrhs, dtype=torch.complex128, device="cuda")
+        L.poly_apply(dl, poly, nrhs, 4, None, L.Noise(3, 1, 0, 0), None, bhy, ws)
+        torch.cuda.synchronize()
+        assert np.max(np.abs(bhy.cpu().numpy() - 12 * dl.V * p1)) <= 1e-13 * abs(12 * dl.V * p1)
+    finally:
+        L.set_option(L.OPT_SWEEP_CHUNKS, 0)
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_streaming_link_load_paths(prec):
     """The streaming kernel's two ways of reading the links (buffer loads
