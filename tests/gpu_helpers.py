@@ -105,3 +105,75 @@ def composite_amplification(apply, t_in, t_out, B) -> float:
             out = max(out, float(np.linalg.norm(w) / nb))
         out = max(out, newton_amplification(apply, t_in, y[None, :]) * float(np.linalg.norm(y) / nb))
     return out
+
+
+_SETUPS = {}
+
+
+def oracle_set_up(cfg, degrees, pin_degree=None, arnoldi_m=90, nev=40, imaglim=2e-4, evectol=1e-3):
+    """The oracle's own set-up of a workload (Sec. 5 setup step 2) from the
+    workload's seeded links and start vector: GMRES roots of the given degrees
+    and, with pin_degree, the PP(pin_degree + 1)-Arnoldi Ritz pairs nearest
+    the origin put through the selection of Sec. 4, of which the first
+    cfg.k_defl accepted are kept (a conjugate pair whole).  Cached for the
+    test process.  Returns a namespace (ol, start, ps, tri)."""
+    import types
+    from oracle import krylov as okr
+    key = (cfg.name, tuple(sorted(degrees)), pin_degree, arnoldi_m, nev, imaglim, evectol)
+    if key in _SETUPS:
+        return _SETUPS[key]
+    ol = oracle.Lattice(cfg.dims, cfg.kappa, synth.config_links(cfg), cfg.antiperiodic_t)
+    start = synth.gaussian_start(ol.n, cfg.seed_start)
+    ps = okr.gmres_polys(ol.apply, start, sorted(set(degrees) | ({pin_degree} - {None})))
+    tri = None
+    if pin_degree is not None:
+        opB = okr.pp_operator(ol.apply, ps.inv_roots[pin_degree], lambda t, v: ol.poly_apply(t, v)[0])
+        lam, Z, AZ, _ = okr.pp_arnoldi_ritz(opB, ol.apply, start, arnoldi_m, nev)
+        tri = okr.select_eigs(lam, Z, AZ, ol.gamma5, lambda v: ol.gamma5(ol.apply(ol.gamma5(v))), imaglim, evectol)
+        k = min(cfg.k_defl, len(tri.lam))
+        if k < len(tri.lam) and tri.pair[k - 1] == k:      # the last kept value's partner would be cut off
+            k -= 1
+        assert k > 0 and np.all(tri.pair[:k] < k)
+        tri = okr.Triplets(tri.lam[:k], tri.Z[:k], tri.pair[:k], tri.U[:k], tri.res_right[:k], tri.res_left[:k])
+    su = types.SimpleNamespace(ol=ol, start=start, ps=ps, tri=tri)
+    _SETUPS[key] = su
+    return su
+
+
+def build_from_oracle_set_up(cfg, su, path, prec=0, rb=16):
+    """The product's run of a workload whose set-up is the oracle's: the
+    roots and deflation triplets of `su` written in the product's checkpoint
+    format (fresh Monte Carlo state) and resumed with driver.build, so that
+    the GPU levels use no root or eigenvector the HIP path produced."""
+    import json
+    from paper_2306_09559_amd import driver
+    from oracle import krylov as okr
+    ps, tri, ol = su.ps, su.tri, su.ol
+    beta = ps.arn.beta
+    degs = sorted(ps.inv_roots)
+    d = {"meta": np.array(json.dumps({"version": driver.CHECKPOINT_VERSION, "config": driver._identity(cfg)})),
+         "root_degrees": np.array(degs, dtype=np.int64),
+         "root_residuals": np.array([okr.gmres_ls(ps.arn.Hbar, beta, min(k + 1, ps.arn.m))[1] / beta for k in degs]),
+         "composite_keys": np.zeros((0, 2), dtype=np.int64), "composite_residuals": np.zeros(0)}
+    for k in degs:
+        d[f"root_{k}"] = np.asarray(ps.inv_roots[k], dtype=np.complex128)
+    if tri is not None:
+        k = len(tri.lam)
+        kpad = 16
+        while kpad < k:
+            kpad *= 2
+        Zp = np.zeros((kpad, ol.n), dtype=np.complex128)
+        Zp[:k] = tri.Z
+        # u_i = scale_i g5 z_pair(i) with u_i^H z_i = 1
+        g5z = np.stack([ol.gamma5(z) for z in tri.Z])
+        scale = 1.0 / np.conj(np.einsum("ij,ij->i", g5z[tri.pair].conj(), tri.Z))
+        assert np.allclose(tri.U, scale[:, None] * g5z[tri.pair])
+        H = tri.U.conj() @ np.stack([ol.apply(z) for z in tri.Z]).T
+        d.update(defl_V=pack(cfg.dims, Zp, kpad, 0).cpu().numpy(), defl_pair=tri.pair.astype(np.int32),
+                 defl_scale=scale, defl_hinv=np.linalg.inv(H), defl_lam=np.asarray(tri.lam),
+                 defl_res=np.stack([tri.res_right, tri.res_left]),
+                 defl_counts=np.array([k, len(tri.lam), 0], dtype=np.int64), defl_arnoldi_residual=np.array(0.0))
+    d["acc"] = np.zeros((len(cfg.levels), 8))
+    d["drawn"] = np.zeros(len(cfg.levels), dtype=np.int64)
+    np.savez(path, **d)
+    return driver.build(cfg, prec=prec, rb=rb, resume=str(path))

@@ -9,7 +9,8 @@ oracle's stopping rule and estimator.
 * driver.run_to_tolerance on a three-level 4^4 workload, eagerly and with
   every batch a recorded step (mpmc_batch_build): both give the same stopping
   points and estimates bit for bit, and they are the oracle's -- its own
-  samples b^H p_hi(A) b - b^H p_lo(A) b of the same Z4 vectors and roots, its
+  samples b^H p_hi(A) b - b^H p_lo(A) b of the same Z4 vectors, with the
+  GMRES roots of its own set-up (resumed into the product's run), its
   level tolerances (eps/sqrt(3), sqrt(eps^2 - e^2)/sqrt(2), sqrt(eps^2 - e^2)),
   check points and level estimates.
 """
@@ -20,10 +21,9 @@ import pytest
 import torch
 
 import oracle
-import synth
 from oracle import estimator
 
-from gpu_helpers import lib
+from gpu_helpers import build_from_oracle_set_up, lib, oracle_set_up
 
 pytestmark = pytest.mark.gpu
 
@@ -76,14 +76,13 @@ def _three_levels():
     return dataclasses.replace(C1, name="C1a", levels=(Level(20, 10, 64), Level(10, 4, 64), Level(4, None, 64)))
 
 
-def test_adaptive_driver_matches_the_oracle():
+def test_adaptive_driver_matches_the_oracle(tmp_path):
     L = lib()
     from paper_2306_09559_amd import driver
     cfg = _three_levels()
-    run = driver.build(cfg, prec=L.F64, rb=16)
-    ol = oracle.Lattice(cfg.dims, cfg.kappa, synth.gauge_links(cfg.dims, cfg.eps, cfg.seed_links),
-                        cfg.antiperiodic_t)
-    roots = run.roots.inv_roots
+    su = oracle_set_up(cfg, [20, 10, 4])
+    run = build_from_oracle_set_up(cfg, su, tmp_path / "c1a_oracle_setup.npz", prec=L.F64, rb=16)
+    ol, roots = su.ol, su.ps.inv_roots
     nmax = 4096
 
     def ora_samples(li, n):

@@ -14,11 +14,13 @@
   oracle's arithmetic, so the samples must equal the oracle's bit for bit --
   an indexing, layout or spin-algebra mistake anywhere fails, whatever the
   rounding.
-* the same level deflated as the workload runs it (k = 20 eigenvectors from
-  the GPU set-up, FP64): the deflated samples b^H p150 b - b^H p30 b -
-  sum_i c_i conj(zeta_i) omega_i of three vectors, with zeta = V^H b, the left
-  vectors, their biorthonormal scaling and c_i = p150(lambda_i) - p30(lambda_i)
-  all recomputed by the oracle from the eigenvectors, eigenvalues and roots.
+* the same level deflated as the workload runs it (FP64), on the oracle's own
+  set-up: its GMRES roots and the first 20 eigen-triplets its PP(31)-Arnoldi
+  and selection accept, written as a checkpoint of the product's run and
+  resumed, so no root or eigenvector comes from the HIP path.  The deflated
+  samples b^H p150 b - b^H p30 b - sum_i c_i conj(zeta_i) omega_i of three
+  vectors, with zeta = V^H b, the left vectors, their biorthonormal scaling
+  and c_i = p150(lambda_i) - p30(lambda_i) formed by the oracle.
 * 24^3 x 48 workload (n = 7.96M, the largest): its lowest level's polynomial
   (degree 4, GMRES roots at full size) over 16 Z4 vectors in FP32 on the
   blocked t-sweep (24 x 4 x 4 blocks of the 24^3 plane with a one-site halo)
@@ -30,11 +32,11 @@
   make every product and partial sum exact in FP32, so sampled columns must
   equal the oracle's exactly, whatever the summation order.
 * 16^3 x 32 workload (n = 1.57M, 64 vectors): its double polynomial
-  p_1 = p_in(A) p_out(A p_in(A)) (PP(20) x 15, degree 299, roots from the GPU
-  set-up) in FP32 scalar mode, the inner chains on the blocked t-sweep and the
-  outer update on the streaming kernel; samples 0 and 63 recomputed by the
-  oracle at full size with the same roots, within 8 d kappa_N u32 with kappa_N
-  the measured growth of the double polynomial's intermediate vectors.
+  p_1 = p_in(A) p_out(A p_in(A)) (PP(20) x 15, degree 299, the oracle's own
+  GMRES and PP-GMRES roots) in FP32 scalar mode, the inner chains on the
+  blocked t-sweep and the outer update on the streaming kernel; samples 0 and
+  63 recomputed by the oracle at full size, within 8 d kappa_N u32 with
+  kappa_N the measured growth of the double polynomial's intermediate vectors.
 * 16^3 x 32 workload (n = 1.57M, 64 vectors): the top-level solutions of one
   batch satisfy ||b - A x|| <= 1e-6 ||b|| through the oracle operator, for
   sampled vectors (a property that holds at any size).
@@ -46,7 +48,7 @@ import torch
 import oracle
 import synth
 from oracle import krylov, solve as osolve
-from gpu_helpers import composite_amplification, dev_c128, lib, pack, unpack
+from gpu_helpers import build_from_oracle_set_up, composite_amplification, dev_c128, lib, oracle_set_up, pack, unpack
 
 pytestmark = pytest.mark.gpu
 
@@ -298,14 +300,15 @@ def test_c4_lattice_operator_bit_exact_with_monomial_links(prec):
         assert np.array_equal(got, want), (r, np.count_nonzero(got != want))
 
 
-def test_c2_deflated_level_sampled_vs_oracle(c2):
+def test_c2_deflated_level_sampled_vs_oracle(tmp_path):
     L = lib()
-    from paper_2306_09559_amd import driver
     from oracle import deflation
-    C2, U, ol, _ = c2
-    run = driver.build(C2, prec=L.F64, rb=16)
+    from synth.configs import C2
+    su = oracle_set_up(C2, [150, 30, 8], pin_degree=30)
+    ol, tri = su.ol, su.tri
+    run = build_from_oracle_set_up(C2, su, tmp_path / "c2_oracle_setup.npz", prec=L.F64, rb=16)
     lv = run.levels[0]
-    assert lv.c is not None and run.defl is not None
+    assert lv.c is not None and run.defl.device.k == len(tri.lam) == C2.k_defl
     N, rb, V = lv.batch, run.level_rb(0), C2.volume
     nz = L.Noise(C2.seed_noise, C2.lattice_id, lv.index, 0)
     samples = torch.empty((N, 6), dtype=torch.float64, device="cuda")
@@ -315,16 +318,9 @@ def test_c2_deflated_level_sampled_vs_oracle(c2):
     L.mlmc_level_estimate(run.dl, lv.device, N, rb, nz, samples, acc, ws)
     S = samples.cpu().numpy()
     got = S[:, 0] + 1j * S[:, 1]
-    # the eigenvectors as the device holds them, back in the canonical layout
-    D = run.defl.device
-    kpad = D.V.shape[-1]
-    canon = torch.empty((kpad, V, 4, 3), dtype=torch.complex128, device="cuda")
-    L.unpack_fields(C2.dims, L.F64, D.V, canon)
-    Z = canon.cpu().numpy().reshape(kpad, -1)[:D.k]
-    Uv = deflation.left_vectors(Z, np.asarray(run.defl.pair), ol.gamma5)
-    t150, t30 = run.roots.inv_roots[150], run.roots.inv_roots[30]
-    lam = np.asarray(run.defl.lam)
-    c = deflation.poly_eval(t150, lam) - deflation.poly_eval(t30, lam)
+    t150, t30 = su.ps.inv_roots[150], su.ps.inv_roots[30]
+    Z, Uv = tri.Z, tri.U
+    c = deflation.poly_eval(t150, tri.lam) - deflation.poly_eval(t30, tri.lam)
     for r in (0, 101, N - 1):
         b = oracle.z4(C2.seed_noise, C2.lattice_id, lv.index, r, 1, V)[0]
         _, hi = ol.poly_apply(t150, b)
@@ -503,24 +499,28 @@ def test_c4_size_reconstruction_and_projection_exact():
 
 def test_c3_double_polynomial_sampled_vs_oracle():
     L = lib()
-    from paper_2306_09559_amd import driver
     from synth.configs import C3
-    run = driver.build(C3, prec=L.F32, rb=16)
-    key = sorted(run.composites)[0]
-    comp = run.composites[key]
-    t_in, t_out = run.roots.inv_roots[key[0] - 1], comp.inv_roots
+    from gpu_helpers import device_lattice
+    n_in, n_out = C3.levels[0].lo
+    dl, ol = device_lattice(C3.dims, C3.kappa, C3.eps, C3.seed_links, C3.antiperiodic_t, L.F32, link_rows=2)
+    # the oracle's roots: GMRES p_in of degree n_in - 1, then PP-GMRES on A p_in(A) for p_out
+    start = synth.gaussian_start(ol.n, C3.seed_start)
+    t_in = krylov.gmres_polys(ol.apply, start, [n_in - 1]).inv_roots[n_in - 1]
+    opB = krylov.pp_operator(ol.apply, t_in, lambda t, v: ol.poly_apply(t, v)[0])
+    t_out, _ = krylov.pp_gmres_roots(opB, start, n_out=n_out)
+    comp = L.DevicePoly(dev_c128(t_in), dev_c128(t_out))
     N, rb, V = C3.levels[0].samples, 16, C3.volume
-    assert L.sweep_plan(run.dl, N, 1)["halo"]
+    assert L.sweep_plan(dl, N, 1)["halo"]
     nz = L.Noise(C3.seed_noise, C3.lattice_id, 5, 0)
-    ws = L.workspace(L.poly_workspace_size(run.dl, comp.device, N, rb))
+    ws = L.workspace(L.poly_workspace_size(dl, comp, N, rb))
     bhy = torch.empty(N, dtype=torch.complex128, device="cuda")
     L.set_option(L.OPT_PLANE_SWEEP, 1)
-    L.poly_apply(run.dl, comp.device, N, rb, None, nz, None, bhy, ws)
+    L.poly_apply(dl, comp, N, rb, None, nz, None, bhy, ws)
     torch.cuda.synchronize()
     got = bhy.cpu().numpy()
     del ws
     assert np.all(np.isfinite(got))
-    ol = oracle.Lattice(C3.dims, C3.kappa, synth.gauge_links(C3.dims, C3.eps, C3.seed_links), C3.antiperiodic_t)
+    key = (n_in, n_out)
     d = len(t_in) * len(t_out) - 1
     for r in (0, N - 1):
         b = oracle.z4(C3.seed_noise, C3.lattice_id, 5, r, 1, V)[0]

@@ -7,8 +7,9 @@ import pytest
 import torch
 
 import oracle
-import synth
-from oracle import estimator, krylov as okr
+from oracle import estimator
+
+from gpu_helpers import build_from_oracle_set_up, oracle_set_up
 
 pytestmark = pytest.mark.gpu
 
@@ -21,13 +22,15 @@ def _gpu():
         pytest.skip("no GPU")
 
 
-def test_mixed_levels_c1():
+def test_mixed_levels_c1(tmp_path):
     from paper_2306_09559_amd import _lib as L
     from paper_2306_09559_amd import driver
     from synth.configs import C1
-    run64 = driver.build(C1, prec=L.F64, rb=4)
+    # both runs on the oracle's own GMRES roots, resumed into the FP64 run and taken over by the FP32 one
+    su = oracle_set_up(C1, [lv.hi for lv in C1.levels])
+    run64 = build_from_oracle_set_up(C1, su, tmp_path / "c1_oracle_setup.npz", prec=L.F64, rb=4)
     run32 = driver.build(C1, prec=L.F32, rb=4, reuse=run64)
-    ol = oracle.Lattice(C1.dims, C1.kappa, synth.gauge_links(C1.dims, C1.eps, C1.seed_links), True)
+    ol = su.ol
     for run in (run64, run32):
         run.reset()
         run.step()
@@ -37,7 +40,7 @@ def test_mixed_levels_c1():
         S = run32.levels[lvl].samples.cpu().numpy()
         hi = S[:, 2] + 1j * S[:, 3]
         B = oracle.z4(C1.seed_noise, C1.lattice_id, lvl, 0, lv.samples, ol.V)
-        t = run64.roots.inv_roots[lv.hi]
+        t = su.ps.inv_roots[lv.hi]
         _, rh = ol.poly_apply(t, B)
         # amplification of rounding through the Newton recurrence
         kN = 1.0
