@@ -26,6 +26,10 @@
   blocked t-sweep (24 x 4 x 4 blocks of the 24^3 plane with a one-site halo)
   and on the streaming kernel; the first and last samples are recomputed by
   the oracle at full size, within 8 d kappa_N u32.
+* the 24^3 x 48 workload's second level, Tr(p60 - p15), as it is launched
+  (128 samples, block width 16, FP32 level kernel on the blocked t-sweep),
+  on roots the oracle computes on an 8^4 lattice of the same ensemble:
+  samples 0 and 127 of both polynomials within 8 d kappa_N u32.
 * the deflation coefficients V^H b and U^H b over the 24^3 x 48 lattice's
   n = 7.96M rows in FP32 on MFMA (k = 20 padded to 32, 128 Z4 vectors):
   eigenvector entries in {-1, 0, 1} + i{-1, 0, 1} and left vectors g5 z / 2
@@ -372,6 +376,55 @@ def test_c4_planes_blocked_sweep_sampled_vs_oracle():
             err = abs(out[opt][r] - want[0]) / abs(want[0])
             print(f"r {r} {'sweep' if opt else 'streaming'}: rel err {err:.2e}, kappa_N {kN:.3g}, bound {bound:.2e}")
             assert err <= bound
+
+
+def test_c4_level_at_its_degrees_sampled_vs_oracle():
+    """The 24^3 x 48 workload's second level, Tr(p60 - p15), as the workload
+    launches it: 128 samples, block width 16, FP32, two-row links, the level
+    kernel on the blocked t-sweep.  The roots are the oracle's GMRES roots of
+    degrees 60 and 15 on an 8^4 lattice with the same kappa, link ensemble and
+    seeds (the oracle's Arnoldi at n = 7.96M is too slow for a test; any roots
+    serve, the oracle applying the same ones).  Samples 0 and 127, both
+    polynomials, are recomputed by the oracle at full size within
+    8 d kappa_N u32."""
+    L = lib()
+    from synth.configs import C4
+    from gpu_helpers import device_lattice, newton_amplification
+    li = 1
+    hi, lo, N = C4.levels[li].hi, C4.levels[li].lo, C4.levels[li].samples
+    small = (8, 8, 8, 8)
+    ols = oracle.Lattice(small, C4.kappa, synth.gauge_links(small, C4.eps, C4.seed_links), C4.antiperiodic_t)
+    ps = krylov.gmres_polys(ols.apply, synth.gaussian_start(ols.n, C4.seed_start), [hi, lo])
+    del ols
+    dl, ol = device_lattice(C4.dims, C4.kappa, C4.eps, C4.seed_links, C4.antiperiodic_t, L.F32, link_rows=2)
+    rb, V = 16, C4.volume
+    plan = L.sweep_plan(dl, N, rb)
+    assert plan["ok"] and plan["halo"], plan
+    print("block", plan["block"], "chunks", plan["chunks"])
+    lev = L.DeviceLevel(L.OP_POLY, L.DevicePoly(dev_c128(ps.inv_roots[hi])), L.OP_POLY,
+                        L.DevicePoly(dev_c128(ps.inv_roots[lo])))
+    nz = L.Noise(C4.seed_noise, C4.lattice_id, li, 0)
+    samples = torch.empty((N, 6), dtype=torch.float64, device="cuda")
+    acc = torch.zeros(8, dtype=torch.float64, device="cuda")
+    ws = L.workspace(L.level_workspace_size(dl, lev, N, rb))
+    L.set_option(L.OPT_PLANE_SWEEP, L.SWEEP_AUTO)
+    L.mlmc_level_estimate(dl, lev, N, rb, nz, samples, acc, ws)
+    S = samples.cpu().numpy()
+    del ws
+    assert np.all(np.isfinite(S))
+    B = oracle.z4(C4.seed_noise, C4.lattice_id, li, 0, N, V)[[0, N - 1]]
+    for d, col in ((hi, 2), (lo, 4)):
+        t = ps.inv_roots[d]
+        _, want = ol.poly_apply(t, B)
+        kN = newton_amplification(ol.apply, t, B)
+        bound = 8 * d * kN * U32
+        for j, r in enumerate((0, N - 1)):
+            got = S[r, col] + 1j * S[r, col + 1]
+            err = abs(got - want[j]) / abs(want[j])
+            print(f"p{d} r {r}: rel err {err:.2e}, kappa_N {kN:.3g}, bound {bound:.2e}")
+            assert err <= bound
+        # the level's sample is the difference of the two constituents
+    assert np.array_equal(S[:, 0], S[:, 2] - S[:, 4]) and np.array_equal(S[:, 1], S[:, 3] - S[:, 5])
 
 
 @pytest.mark.parametrize("i,plan_want", [(0, (False, 4)), (1, (True, 3)), (2, (True, 2)), (3, None)])
