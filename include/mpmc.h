@@ -480,7 +480,9 @@ size_t mpmc_autotune_workspace_size(const mpmc_lattice *lat, const mpmc_level *l
  * cut into blocks, the three best-ranked blocks; for each sweep, the plan's
  * number of t-chunks and the divisors of Lt next to it.  `best` is in/out: on
  * entry the current shape, which is kept unless a candidate is faster by
- * more than keep_within (a fraction, e.g. 0.03); on exit the choice.  Each
+ * more than keep_within (a fraction, e.g. 0.03); a current shape with rb > 32
+ * (outside the workspace) is not timed, and the fastest candidate is taken;
+ * on exit the choice.  Each
  * candidate runs once untimed, then `reps` times between HIP events on
  * `stream`; the call synchronises with `stream` and returns after timing
  * (it is not capturable).  The noise's first_sample is used for every run;

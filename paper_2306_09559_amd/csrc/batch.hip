@@ -271,7 +271,8 @@ int mpmc_autotune(mpmc_handle h, const mpmc_lattice *lat, const mpmc_level *leve
     bool have_current = false;
     for (const auto &c : cand)
         if (same_choice(c, *best)) have_current = true;
-    if (!have_current && best->rb >= 1 && nrhs % best->rb == 0 && best->rb <= 256 && (best->rb & (best->rb - 1)) == 0)
+    // the current shape is timed too when the workspace covers it (rb <= 32, like the candidates)
+    if (!have_current && best->rb >= 1 && best->rb <= 32 && nrhs % best->rb == 0 && (best->rb & (best->rb - 1)) == 0)
         cand.push_back(*best);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MPMC_EHIP;

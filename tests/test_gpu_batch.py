@@ -169,6 +169,24 @@ def test_autotune_offers_the_blocked_sweep(tmp_path):
     assert np.max(np.abs(got - ref)) <= 1e-6 * np.max(np.abs(ref))
 
 
+def test_autotune_with_a_current_shape_wider_than_its_candidates():
+    """A level run at block width 64, wider than the tuner's candidates (its
+    workspace covers rb <= 32): mpmc_autotune times only the candidates,
+    returns the fastest of them and never the untimed current shape."""
+    from paper_2306_09559_amd import driver
+    from synth.configs import Level
+    L = lib()
+    cfg = dataclasses.replace(_small_cfgs()[0], name="C1w", levels=(Level(6, None, 64),), lattice_id=14)
+    run = driver.build(cfg, prec=L.F64, rb=16)
+    lv = run.levels[0]
+    nz = L.Noise(cfg.seed_noise, cfg.lattice_id, lv.index, 0)
+    best, secs, cached, table = L.autotune_level(L.Handle(), run.dl, lv.device, 64, nz, (64, 0, 0, 0), reps=1)
+    print(best, secs, table)
+    assert not cached and secs > 0 and table
+    assert all(c[0] <= 32 for c, _ in table)
+    assert best in [c for c, _ in table] and secs == min(t for _, t in table)
+
+
 def test_autotune_offers_t_chunks(tmp_path):
     """On 8^4 planes with 64 vectors the plan cuts the whole-plane t-sweep
     into 4 t-chunks (64 workgroups would leave three CUs in four idle);
