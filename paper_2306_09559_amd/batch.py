@@ -87,7 +87,7 @@ class GraphStep:
                 citems.append(L.BatchItem(run.dl, lv.device, it.nsamples, run.level_rb(it.level), cfg_noise,
                                           it.counter, it.repeats, lv.samples[: it.nsamples], lv.acc, lv.ws,
                                           branch=branch,
-                                          plane_sweep=L.SWEEP_AUTO if lv.sweep else L.SWEEP_OFF,
+                                          plane_sweep=int(lv.sweep),
                                           sweep_rank=int(lv.sweep_rank), sweep_chunks=int(lv.sweep_chunks)))
         L.batch_build(self.handle, citems)
         if keep_state:
@@ -146,23 +146,28 @@ def _key(run: LatticeRun, level: int) -> str:
 
 @dataclass
 class TuneResult:
-    # level -> (rb, sweep, block rank, t-chunks)
-    choice: Dict[int, Tuple[int, bool, int, int]] = field(default_factory=dict)
+    # level -> (rb, kernel family 0/1/2 as MPMC_OPT_PLANE_SWEEP, block rank, t-chunks)
+    choice: Dict[int, Tuple[int, int, int, int]] = field(default_factory=dict)
     timings: Dict[int, Dict[str, float]] = field(default_factory=dict)
     cached: Dict[int, bool] = field(default_factory=dict)
 
 
 def _label(choice) -> str:
     rb, sw, rank, chunks = choice
-    return f"rb{rb}" + (f"-sweep{'' if rank == 0 else rank}{'' if chunks == 0 else f'-t{chunks}'}" if sw else "")
+    if not sw:
+        return f"rb{rb}"
+    return f"rb{rb}-{'sweep' if sw == 1 else 'auto'}{'' if rank == 0 else rank}{'' if chunks == 0 else f'-t{chunks}'}"
 
 
 def autotune(run: LatticeRun, reps: int = 3, use_cache: bool = True, cache_path: Optional[str] = None,
              keep_within: float = 0.03, handle: Optional[L.Handle] = None) -> TuneResult:
-    """Pick (rb, sweep, block rank, t-chunks) per polynomial level of `run` with
-    mpmc_autotune; applies the choice to the run and resets its
-    accumulators.  The level's current shape is kept unless another is
-    faster by more than keep_within.  Choices persist in a JSON file."""
+    """Pick (rb, kernel family, block rank, t-chunks) per polynomial level of
+    `run` with mpmc_autotune; applies the choice to the run and resets its
+    accumulators.  The level's current shape (initially the plan's choice of
+    kernel, family 2) is timed as it runs and kept unless another is faster
+    by more than keep_within; a chosen candidate runs exactly as it was
+    timed (family 0 or 1, never re-decided by the plan).  Choices persist in
+    a JSON file."""
     path = cache_path or _CACHE
     cache = {}
     if use_cache and os.path.exists(path):
@@ -179,7 +184,7 @@ def autotune(run: LatticeRun, reps: int = 3, use_cache: bool = True, cache_path:
         key = _key(run, li)
         if use_cache and key in cache:
             c = cache[key]
-            rb, sw, rank, chunks = int(c["rb"]), bool(c["sweep"]), int(c.get("rank", 0)), int(c.get("chunks", 0))
+            rb, sw, rank, chunks = int(c["rb"]), int(c["sweep"]), int(c.get("rank", 0)), int(c.get("chunks", 0))
             run.set_level_shape(li, rb, sw, rank, chunks)
             res.choice[li] = (rb, sw, rank, chunks)
             res.cached[li] = True
@@ -190,11 +195,11 @@ def autotune(run: LatticeRun, reps: int = 3, use_cache: bool = True, cache_path:
         best, secs, _hit, table = L.autotune_level(h, run.dl, lv.device, N, nz, cur, reps=reps,
                                                    keep_within=keep_within)
         rb, sw, rank, chunks = best
-        run.set_level_shape(li, rb, bool(sw), rank, chunks)
-        res.choice[li] = (rb, bool(sw), rank, chunks)
+        run.set_level_shape(li, rb, sw, rank, chunks)
+        res.choice[li] = (rb, sw, rank, chunks)
         res.timings[li] = {_label(c): t for c, t in table}
         res.cached[li] = False
-        cache[key] = {"rb": rb, "sweep": bool(sw), "rank": rank, "chunks": chunks, "seconds": secs,
+        cache[key] = {"rb": rb, "sweep": sw, "rank": rank, "chunks": chunks, "seconds": secs,
                       "when": time.strftime("%Y-%m-%d")}
     run.reset()
     if use_cache:

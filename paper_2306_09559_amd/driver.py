@@ -64,7 +64,7 @@ class LevelState:
     solve_tol: float = 1e-6
     rb: int = 0                             # RHS block width of this level (0: the run's)
     batch: int = 0                          # vectors per batch (device buffers); samples per step / batch draws
-    sweep: bool = True                      # allow the t-sweep kernel for this level
+    sweep: int = L.SWEEP_AUTO               # kernel family (MPMC_OPT_PLANE_SWEEP: 0 streaming, 1 t-sweep, 2 plan's choice)
     sweep_rank: int = 0                     # block choice of a blocked t-sweep (MPMC_OPT_SWEEP_RANK)
     sweep_chunks: int = 0                   # t-chunks of the sweep (MPMC_OPT_SWEEP_CHUNKS; 0: the plan's)
 
@@ -99,7 +99,7 @@ class LatticeRun:
         lv = self.levels[level]
         # the level's kernel selection for this call only (the options are
         # process-wide; mpmc_batch_build scopes them per item the same way)
-        L.set_option(L.OPT_PLANE_SWEEP, L.SWEEP_AUTO if lv.sweep else L.SWEEP_OFF)
+        L.set_option(L.OPT_PLANE_SWEEP, int(lv.sweep))
         L.set_option(L.OPT_SWEEP_RANK, int(lv.sweep_rank))
         L.set_option(L.OPT_SWEEP_CHUNKS, int(lv.sweep_chunks))
         try:
@@ -146,17 +146,22 @@ class LatticeRun:
             lv.acc.zero_()
             lv.drawn = 0
 
-    def set_level_shape(self, level: int, rb: int, sweep: bool, rank: int = 0, chunks: int = 0):
+    def set_level_shape(self, level: int, rb: int, sweep, rank: int = 0, chunks: int = 0):
         """Choose the RHS block width, kernel family, blocked-sweep block rank
         and t-chunk count (0: the plan's) of one level (the autotuner's
-        knobs); resizes the level's workspace."""
+        knobs); resizes the level's workspace.  sweep is the kernel family as
+        MPMC_OPT_PLANE_SWEEP takes it (0 streaming, 1 the t-sweep wherever the
+        lattice admits one, 2 the plan's choice); True means 1, False 0."""
         lv = self.levels[level]
         if lv.solver is not None:
             raise ValueError("the block width of a solve level is fixed by its solver")
         N = lv.batch
         if N % rb:
             raise ValueError(f"rb={rb} does not divide {N}")
-        lv.rb, lv.sweep, lv.sweep_rank, lv.sweep_chunks = int(rb), bool(sweep), int(rank), int(chunks)
+        mode = int(sweep)
+        if mode not in (L.SWEEP_OFF, L.SWEEP_ALWAYS, L.SWEEP_AUTO):
+            raise ValueError(f"kernel family {sweep!r} is not 0, 1 or 2")
+        lv.rb, lv.sweep, lv.sweep_rank, lv.sweep_chunks = int(rb), mode, int(rank), int(chunks)
         lv.ws = L.workspace(L.level_workspace_size(self.dl, lv.device, N, rb))
 
     def estimates(self):
@@ -658,7 +663,7 @@ def _stop_step(run: LatticeRun, level: int, batch: int, state: torch.Tensor, fir
     h = L.Handle()
     item = L.BatchItem(run.dl, lv.device, batch, run.level_rb(level),
                        L.Noise(run.cfg.seed_noise, run.cfg.lattice_id, lv.index, 0), ctr, 1, lv.samples[:batch],
-                       lv.acc, lv.ws, 0, L.SWEEP_AUTO if lv.sweep else L.SWEEP_OFF, int(lv.sweep_rank),
+                       lv.acc, lv.ws, 0, int(lv.sweep), int(lv.sweep_rank),
                        int(lv.sweep_chunks),
                        state, first, every)
     L.batch_build(h, [item])

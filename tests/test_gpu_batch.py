@@ -187,6 +187,43 @@ def test_autotune_with_a_current_shape_wider_than_its_candidates():
     assert best in [c for c, _ in table] and secs == min(t for _, t in table)
 
 
+def test_a_level_runs_the_kernel_family_it_was_tuned_with(tmp_path, monkeypatch):
+    """The tuner times forced kernel families (0 streaming, 1 t-sweep) next to
+    the level's current shape as it runs (family 2: the plan decides); the
+    level then runs with exactly the chosen family.  A t-sweep in 2 t-chunks
+    on 8^4 x 64 vectors (128 workgroups for 256 CUs, where the plan's own
+    test would fall back to streaming) still runs as a t-sweep."""
+    from paper_2306_09559_amd import driver
+    from paper_2306_09559_amd.batch import autotune
+    from synth.configs import Level
+    L = lib()
+    cfg = dataclasses.replace(_small_cfgs()[0], name="C1f", dims=(8, 8, 8, 8), kappa=0.14,
+                              levels=(Level(6, None, 64),), seed_links=141, lattice_id=15)
+    run = driver.build(cfg, prec=L.F64, rb=16)
+    calls = []
+    set_option = L.set_option
+
+    def record(opt, value):
+        calls.append((opt, value))
+        return set_option(opt, value)
+    monkeypatch.setattr(L, "set_option", record)
+    run.draw(0, 64)
+    assert calls[:3] == [(L.OPT_PLANE_SWEEP, L.SWEEP_AUTO), (L.OPT_SWEEP_RANK, 0), (L.OPT_SWEEP_CHUNKS, 0)]
+    calls.clear()
+    run.set_level_shape(0, 16, True, 0, 2)
+    run.draw(0, 64)
+    assert calls[:3] == [(L.OPT_PLANE_SWEEP, L.SWEEP_ALWAYS), (L.OPT_SWEEP_RANK, 0), (L.OPT_SWEEP_CHUNKS, 2)]
+    run.set_level_shape(0, 16, L.SWEEP_AUTO)
+    res = autotune(run, reps=1, use_cache=False, cache_path=str(tmp_path / "t.json"))
+    print(res.timings[0], res.choice[0])
+    assert "rb16-auto" in res.timings[0]              # the current shape, timed as it runs
+    rb, family, rank, chunks = res.choice[0]
+    calls.clear()
+    run.draw(0, 64)
+    assert calls[:3] == [(L.OPT_PLANE_SWEEP, family), (L.OPT_SWEEP_RANK, rank), (L.OPT_SWEEP_CHUNKS, chunks)]
+    torch.cuda.synchronize()
+
+
 def test_autotune_offers_t_chunks(tmp_path):
     """On 8^4 planes with 64 vectors the plan cuts the whole-plane t-sweep
     into 4 t-chunks (64 workgroups would leave three CUs in four idle);
