@@ -528,7 +528,10 @@ def batch_build(h: Handle, items: Sequence[BatchItem]):
     for i, it in enumerate(items):
         L = it.lat.c()
         lv, dref = it.level.cstruct()
-        keep += [L, lv, dref]
+        # the C descriptors and every device buffer the recorded graph uses stay
+        # alive with the handle (a level reshaped later gets a new workspace;
+        # the graph keeps writing its own)
+        keep += [L, lv, dref, it.lat, it.level, it.counter, it.samples, it.acc, it.ws, it.stop_state]
         assert it.counter.dtype == torch.int64 and it.counter.is_cuda
         arr[i] = mpmc_batch_item(ctypes.pointer(L), ctypes.pointer(lv), mpmc_shape(it.nrhs, it.rb), it.noise.c(),
                                  it.counter.data_ptr(), int(it.batches), it.samples.data_ptr(), it.acc.data_ptr(),

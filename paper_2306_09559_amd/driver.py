@@ -163,6 +163,9 @@ class LatticeRun:
             raise ValueError(f"kernel family {sweep!r} is not 0, 1 or 2")
         lv.rb, lv.sweep, lv.sweep_rank, lv.sweep_chunks = int(rb), mode, int(rank), int(chunks)
         lv.ws = L.workspace(L.level_workspace_size(self.dl, lv.device, N, rb))
+        # the adaptive loop's recorded one-batch steps of this level have the old shape
+        for key in [k for k in self.adaptive if k[0] == "step" and k[1] == level]:
+            del self.adaptive[key]
 
     def estimates(self):
         """Per-level (estimate, stderr, variance, n) on the host."""

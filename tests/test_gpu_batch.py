@@ -224,6 +224,37 @@ def test_a_level_runs_the_kernel_family_it_was_tuned_with(tmp_path, monkeypatch)
     torch.cuda.synchronize()
 
 
+def test_a_recorded_step_outlives_a_reshaped_level():
+    """A recorded step keeps the buffers it was recorded with: after the
+    level is reshaped (a new workspace; the old one would go back to torch's
+    allocator), a tensor of the old workspace's size filled with a constant
+    stays untouched by replays, and the replays still give the recorded
+    shape's samples bit for bit.  The adaptive loop's recorded steps of a
+    reshaped level are dropped, to be recorded again with its new shape."""
+    from paper_2306_09559_amd import driver
+    from paper_2306_09559_amd.batch import GraphStep
+    L = lib()
+    cfg = _small_cfgs()[1]
+    run = driver.build(cfg, prec=L.F64, rb=4)
+    lv = run.levels[0]
+    run.reset()
+    run.step()
+    torch.cuda.synchronize()
+    ref = lv.samples.cpu().numpy().copy()
+    gs = GraphStep([run])
+    driver.prepare_adaptive(run)
+    assert any(k[0] == "step" and k[1] == 0 for k in run.adaptive)
+    old_bytes = lv.ws.numel()
+    run.set_level_shape(0, 8, L.SWEEP_OFF)
+    assert not any(k[0] == "step" and k[1] == 0 for k in run.adaptive)
+    filler = torch.full((old_bytes,), 7, dtype=torch.uint8, device="cuda")
+    gs.reset()
+    gs.replay()
+    torch.cuda.synchronize()
+    assert bool((filler == 7).all())
+    assert np.array_equal(lv.samples.cpu().numpy(), ref)
+
+
 def test_autotune_offers_t_chunks(tmp_path):
     """On 8^4 planes with 64 vectors the plan cuts the whole-plane t-sweep
     into 4 t-chunks (64 workgroups would leave three CUs in four idle);
