@@ -149,8 +149,19 @@ def build_info() -> str:
     return _lib.mpmc_build_info().decode()
 
 
+# the library's process-wide options as last set through this binding (their
+# defaults in the library until then)
+_OPTIONS = {OPT_PLANE_SWEEP: SWEEP_AUTO, OPT_SWEEP_RANK: 0, OPT_HOP_SLAB: 1, OPT_LINK_BUF: 1, OPT_SWEEP_CHUNKS: 0}
+
+
 def set_option(option: int, value: int):
     _check("mpmc_set_option", _lib.mpmc_set_option(int(option), int(value)))
+    _OPTIONS[int(option)] = int(value)
+
+
+def get_option(option: int) -> int:
+    """The value of a process-wide option as last set through set_option."""
+    return _OPTIONS[int(option)]
 
 
 def _check(fn: str, st: int):

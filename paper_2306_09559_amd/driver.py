@@ -98,17 +98,18 @@ class LatticeRun:
         device counter)."""
         lv = self.levels[level]
         # the level's kernel selection for this call only (the options are
-        # process-wide; mpmc_batch_build scopes them per item the same way)
-        L.set_option(L.OPT_PLANE_SWEEP, int(lv.sweep))
-        L.set_option(L.OPT_SWEEP_RANK, int(lv.sweep_rank))
-        L.set_option(L.OPT_SWEEP_CHUNKS, int(lv.sweep_chunks))
+        # process-wide; mpmc_batch_build scopes them per item the same way):
+        # the caller's values are restored afterwards
+        opts = (L.OPT_PLANE_SWEEP, L.OPT_SWEEP_RANK, L.OPT_SWEEP_CHUNKS)
+        prev = [L.get_option(o) for o in opts]
+        for o, v in zip(opts, (lv.sweep, lv.sweep_rank, lv.sweep_chunks)):
+            L.set_option(o, int(v))
         try:
             L.mlmc_level_estimate(self.dl, lv.device, nsamples, self.level_rb(level), nz, lv.samples[:nsamples],
                                   lv.acc, lv.ws)
         finally:
-            L.set_option(L.OPT_PLANE_SWEEP, L.SWEEP_AUTO)
-            L.set_option(L.OPT_SWEEP_RANK, 0)
-            L.set_option(L.OPT_SWEEP_CHUNKS, 0)
+            for o, v in zip(opts, prev):
+                L.set_option(o, v)
 
     def draw(self, level: int, nsamples: int):
         """Enqueue nsamples more samples of one level (one batch)."""

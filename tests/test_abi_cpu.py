@@ -225,3 +225,18 @@ def test_set_option_checks_its_arguments(L):
         assert lib.mpmc_set_option(opt, default) == L.OK
     assert lib.mpmc_set_option(0, 1) == L.EUNSUPPORTED
     assert lib.mpmc_set_option(max(ranges) + 1, 1) == L.EUNSUPPORTED
+
+
+def test_binding_tracks_the_options_it_sets(L):
+    """set_option records what the library accepted, so that a call that
+    scopes an option (a level's kernel selection) can restore the caller's
+    value; a rejected value leaves the record alone."""
+    assert L.get_option(L.OPT_PLANE_SWEEP) == L.SWEEP_AUTO and L.get_option(L.OPT_SWEEP_CHUNKS) == 0
+    try:
+        L.set_option(L.OPT_SWEEP_CHUNKS, 4)
+        assert L.get_option(L.OPT_SWEEP_CHUNKS) == 4
+        with pytest.raises(L.MpmcError):
+            L.set_option(L.OPT_SWEEP_CHUNKS, 2000)
+        assert L.get_option(L.OPT_SWEEP_CHUNKS) == 4
+    finally:
+        L.set_option(L.OPT_SWEEP_CHUNKS, 0)
