@@ -225,6 +225,7 @@ def probe_hop(reps: int, orders=(0, 1)):
     from paper_2306_09559_amd import _lib as L
     cases = [((16, 16, 16, 16), L.F32, 16, 16), ((12, 12, 12, 24), L.F32, 8, 8), ((24, 24, 24, 48), L.F64, 1, 1),
              ((24, 24, 24, 48), L.F32, 128, 16), ((8, 8, 8, 8), L.F32, 256, 16)]
+    prev = L.get_option(L.OPT_PLANE_SWEEP)
     L.set_option(L.OPT_PLANE_SWEEP, 0)
     out = []
     for dims, prec, N, rb in cases:
@@ -258,7 +259,7 @@ def probe_hop(reps: int, orders=(0, 1)):
         del ws, g
         torch.cuda.empty_cache()
     L.set_option(L.OPT_HOP_SLAB, 1)
-    L.set_option(L.OPT_PLANE_SWEEP, 1)
+    L.set_option(L.OPT_PLANE_SWEEP, prev)
     return out
 
 
@@ -272,6 +273,8 @@ def probe_sweep(reps: int):
     import synth
     from paper_2306_09559_amd import _lib as L
     cases = [((24, 24, 24, 48), 256, 16), ((24, 24, 24, 48), 32, 16), ((16, 16, 16, 16), 16, 16)]
+    prev = L.get_option(L.OPT_PLANE_SWEEP)
+    L.set_option(L.OPT_PLANE_SWEEP, 1)
     out = []
     for dims, N, rb in cases:
         V = int(np.prod(dims))
@@ -304,6 +307,7 @@ def probe_sweep(reps: int):
         del ws, g
         torch.cuda.empty_cache()
     L.set_option(L.OPT_SWEEP_RANK, 0)
+    L.set_option(L.OPT_PLANE_SWEEP, prev)
     return out
 
 
@@ -351,6 +355,7 @@ def kernel_launch_seconds(run, steps: int, stream) -> float:
     from paper_2306_09559_amd import _lib as L
     lv = run.levels[0]
     poly = lv.device.poly_hi
+    prev = L.get_option(L.OPT_PLANE_SWEEP)
     L.set_option(L.OPT_PLANE_SWEEP, 1)
     N = run.cfg.levels[0].samples
     ws = L.workspace(L.poly_workspace_size(run.dl, poly, N, run.rb))
@@ -363,6 +368,7 @@ def kernel_launch_seconds(run, steps: int, stream) -> float:
         L.poly_apply(run.dl, poly, N, run.rb, None, nz, None, bhy, ws)
     e1.record(stream)
     torch.cuda.synchronize()
+    L.set_option(L.OPT_PLANE_SWEEP, prev)
     launches = steps * (int(poly.inv_in.numel()) - 1)
     return e0.elapsed_time(e1) * 1e-3 / launches
 
