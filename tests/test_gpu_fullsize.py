@@ -17,10 +17,12 @@
 * the same level deflated as the workload runs it (FP64), on the oracle's own
   set-up: its GMRES roots and the first 20 eigen-triplets its PP(31)-Arnoldi
   and selection accept, written as a checkpoint of the product's run and
-  resumed, so no root or eigenvector comes from the HIP path.  The deflated
-  samples b^H p150 b - b^H p30 b - sum_i c_i conj(zeta_i) omega_i of three
-  vectors, with zeta = V^H b, the left vectors, their biorthonormal scaling
-  and c_i = p150(lambda_i) - p30(lambda_i) formed by the oracle.
+  resumed, so no root or eigenvector comes from the HIP path.  All 256
+  deflated samples b^H p150 b - b^H p30 b - sum_i c_i conj(zeta_i) omega_i,
+  with zeta = V^H b, the left vectors, their biorthonormal scaling and
+  c_i = p150(lambda_i) - p30(lambda_i) formed by the oracle, within 1e-12 of
+  each sample's scale, and the level's FP64 accumulator (n, mean, M2) against
+  the oracle's estimate of the same samples.
 * 24^3 x 48 workload (n = 7.96M, the largest): its lowest level's polynomial
   (degree 4, GMRES roots at full size) over 16 Z4 vectors in FP32 on the
   blocked t-sweep (24 x 4 x 4 blocks of the 24^3 plane with a one-site halo)
@@ -304,9 +306,9 @@ def test_c4_lattice_operator_bit_exact_with_monomial_links(prec):
         assert np.array_equal(got, want), (r, np.count_nonzero(got != want))
 
 
-def test_c2_deflated_level_sampled_vs_oracle(tmp_path):
+def test_c2_deflated_level_every_sample_vs_oracle(tmp_path):
     L = lib()
-    from oracle import deflation
+    from oracle import deflation, estimator
     from synth.configs import C2
     su = oracle_set_up(C2, [150, 30, 8], pin_degree=30)
     ol, tri = su.ol, su.tri
@@ -323,21 +325,29 @@ def test_c2_deflated_level_sampled_vs_oracle(tmp_path):
     S = samples.cpu().numpy()
     got = S[:, 0] + 1j * S[:, 1]
     t150, t30 = su.ps.inv_roots[150], su.ps.inv_roots[30]
-    Z, Uv = tri.Z, tri.U
     c = deflation.poly_eval(t150, tri.lam) - deflation.poly_eval(t30, tri.lam)
-    for r in (0, 101, N - 1):
-        b = oracle.z4(C2.seed_noise, C2.lattice_id, lv.index, r, 1, V)[0]
-        _, hi = ol.poly_apply(t150, b)
-        _, lo = ol.poly_apply(t30, b)
-        zeta, omega = Z.conj() @ b, Uv.conj() @ b
-        terms = c * np.conj(zeta) * omega
-        want = hi[0] - lo[0] - np.sum(terms)
-        scale = abs(hi[0]) + abs(lo[0]) + np.sum(np.abs(terms))
-        kN = max(_kappa_N(ol, t150, b), _kappa_N(ol, t30, b))
-        bound = 1e-12
-        err = abs(got[r] - want) / scale
-        print(f"r {r}: deflated sample {want:.6g}, error / scale {err:.2e}, kappa_N {kN:.3g}, bound {bound:.2e}")
-        assert err <= bound
+    # every sample of the batch, by the oracle (a batch of N Newton applications per polynomial)
+    B = oracle.z4(C2.seed_noise, C2.lattice_id, lv.index, 0, N, V)
+    _, hi = ol.poly_apply(t150, B)
+    _, lo = ol.poly_apply(t30, B)
+    zeta, omega = tri.Z.conj() @ B.T, tri.U.conj() @ B.T
+    terms = c[:, None] * np.conj(zeta) * omega
+    want = estimator.level_samples(hi, lo, zeta, omega, c)
+    scale = np.abs(hi) + np.abs(lo) + np.sum(np.abs(terms), axis=0)
+    err = np.abs(got - want) / scale
+    kN = max(_kappa_N(ol, t150, B[0]), _kappa_N(ol, t30, B[0]))
+    r = int(np.argmax(err))
+    print(f"{N} deflated samples: max error / scale {err[r]:.2e} (sample {r}), kappa_N of sample 0 {kN:.3g}")
+    assert np.all(err <= 1e-12)
+    # the level's FP64 accumulator: n, mean and M2 of exactly these samples
+    est = estimator.level_estimate(want)
+    A = acc.cpu().numpy()
+    assert A[0] == N and A[4] == 0
+    # with every sample within delta = 1e-12 of its scale, the mean moves by at most
+    # that and the variance by 4 delta (sqrt(var) + delta) N / (N - 1); plus FP64 summation order
+    delta = 1e-12 * float(np.max(scale))
+    assert abs(complex(A[1], A[2]) - est.mean) <= delta
+    assert abs(A[3] / (N - 1) - est.var) <= 4 * delta * (np.sqrt(est.var) + delta) * N / (N - 1) + 1e-13 * est.var
 
 
 def test_c4_planes_blocked_sweep_sampled_vs_oracle():
