@@ -956,8 +956,10 @@ SweepPlan sweep_plan(const mpmc_lattice &lat, mpmc_shape sh) {
     // 128-byte lines only when bx spans the x extent or a multiple of a line.
     // The plan minimises the input bytes per block site over the compulsory
     // ones, (1 + halo / block sites) / line efficiency, then takes the larger
-    // block (measured: 4x8x16 -> 16x4x8 blocks of 16^3 planes 1.2 -> 2.8 TB/s,
-    // 8x8x8 -> 24x4x4 of 24^3 planes 1.8 -> 2.2 TB/s).  The candidates are
+    // block, then the one longer in y (measured: 4x8x16 -> 16x4x8 blocks of
+    // 16^3 planes 1.2 -> 2.8 TB/s, 8x8x8 -> 24x4x4 of 24^3 planes 1.8 -> 2.2
+    // TB/s; of the equal-cost 16x4x8 and 16x8x4, the latter is 5% faster on
+    // 16^4 x 16 vectors and 0-1% on 16^3x32).  The candidates are
     // ranked by that cost; the kernel-selection option MPMC_OPT_SWEEP_RANK
     // picks a lower-ranked block (the autotuner times a few).
     auto cost = [&](int bx, int Pb, int Hb) {
@@ -986,10 +988,11 @@ SweepPlan sweep_plan(const mpmc_lattice &lat, mpmc_shape sh) {
                 if (lds > kLds) continue;
                 if ((size_t)sh.nrhs * (size_t)(P / Pb) > avail) continue;
                 const Cand c{cost(bx, Pb, Hb), bx, by, bz, Pb, Hb, lds};
-                // keep the 64 best by (cost, larger block first), insertion-sorted
+                // keep the 64 best by (cost, larger block, longer y extent first), insertion-sorted
                 int at = nc < 64 ? nc : 64;
                 while (at > 0 && (c.cost < cands[at - 1].cost - 1e-9 ||
-                                  (c.cost < cands[at - 1].cost + 1e-9 && c.Pb > cands[at - 1].Pb)))
+                                  (c.cost < cands[at - 1].cost + 1e-9 &&
+                                   (c.Pb > cands[at - 1].Pb || (c.Pb == cands[at - 1].Pb && c.by > cands[at - 1].by)))))
                     --at;
                 if (at >= 64) continue;
                 for (int m = (nc < 64 ? nc : 63); m > at; --m) cands[m] = cands[m - 1];

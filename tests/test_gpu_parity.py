@@ -474,10 +474,10 @@ def test_level_accumulates_batches_and_is_deterministic():
     # planes larger than one workgroup: xyz-blocks with a halo (FP32), with
     # enough vectors for a workgroup's worth of threads per CU (256 CUs)
     ((8, 8, 16, 4), True, 1, 128, 4, True),    # 8 x 8 x 8 blocks, cut in z
-    ((16, 8, 8, 3), True, 1, 128, 2, False),   # 16 x 4 x 8 blocks, field input, odd Lt
+    ((16, 8, 8, 3), True, 1, 128, 2, False),   # 16-wide 512-site blocks, field input, odd Lt
     ((12, 12, 12, 2), True, 1, 80, 8, True),   # 12 x 4 x 4 blocks, cut in y and z
-    ((16, 16, 16, 2), False, 1, 32, 4, True),  # eight 16 x 4 x 8 blocks of a 16^3 plane
-    ((32, 8, 8, 2), True, 1, 64, 16, True),    # 16 x 4 x 8 blocks, cut in x and y
+    ((16, 16, 16, 2), False, 1, 32, 4, True),  # eight 16 x 8 x 4 blocks of a 16^3 plane
+    ((32, 8, 8, 2), True, 1, 64, 16, True),    # 16-wide 512-site blocks, cut in x
 ])
 def test_sweep_matches_oracle_and_streaming(dims, ap, prec, nrhs, rb, z4):
     L = lib()
@@ -700,7 +700,7 @@ def test_vector_mode_sweep(dims, prec, nrhs, field_in, dot):
     ((8, 8, 8, 8), 1, 64, 16, (2, 4)),          # FP32 whole plane (own backward-hop products)
     # blocked planes are offered only when the unchunked launch already
     # covers the CUs: 32 x 8 workgroups of 512 sites, 64 x 9 of 192 (two per CU)
-    ((16, 16, 16, 8), 1, 32, 8, (2, 4, 8)),     # FP32 16 x 4 x 8 blocks with a halo
+    ((16, 16, 16, 8), 1, 32, 8, (2, 4, 8)),     # FP32 16 x 8 x 4 blocks with a halo
     ((12, 12, 12, 4), 1, 64, 8, (2, 4)),        # FP32 12 x 4 x 4 blocks, cut in y and z
 ])
 def test_sweep_t_chunks(dims, prec, nrhs, rb, chunks):
