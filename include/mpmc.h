@@ -478,12 +478,13 @@ size_t mpmc_autotune_workspace_size(const mpmc_lattice *lat, const mpmc_level *l
  * pick the fastest: block widths rb = 1, 2, 4, .. 32 dividing nrhs on the
  * streaming kernel; rb >= 8 on the t-sweep where it applies; on FP32 planes
  * cut into blocks, the three best-ranked blocks; for each sweep, the plan's
- * number of t-chunks and the divisors of Lt next to it.  `best` is in/out: on
- * entry the current shape, which is kept unless a candidate is faster by
- * more than keep_within (a fraction, e.g. 0.03); a current shape with rb > 32
- * (outside the workspace) is not timed, and the fastest candidate is taken;
- * on exit the choice.  Each
- * candidate runs once untimed, then `reps` times between HIP events on
+ * number of t-chunks and the divisors of Lt next to it.  `best` is in/out:
+ * on entry the current shape, timed with its own plane_sweep (2 leaves the
+ * choice to the plan, as a call under the default options would) and kept
+ * unless a candidate is faster by more than keep_within (a fraction, e.g.
+ * 0.03); a current shape with rb > 32 (outside the workspace) is not timed,
+ * and the fastest candidate is taken; on exit the choice.  Each candidate
+ * runs once untimed, then `reps` times between HIP events on
  * `stream`; the call synchronises with `stream` and returns after timing
  * (it is not capturable).  The noise's first_sample is used for every run;
  * the level's samples and accumulator are not touched (scratch in ws).
